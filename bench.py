@@ -1,0 +1,219 @@
+"""Benchmark of the Rosko hot path on one MI355X.
+
+Workload: a pruned CNN layer as a GEMM -- weights A = 256 x 2304 (256
+channels x 3x3 x 256), N(0,1) draws magnitude-pruned to 70/80/90/95/99/99.8%
+sparsity, times the im2col activations B = 2304 x 3136 of a ReLU'd N(0,1)
+256 x 56 x 56 input (about half zeros, kept dense), FP32.
+
+One step packs each of the six weight matrices (count, scan, write) and
+multiplies it with B (C = A B), i.e. one pass of the forward hot path over
+the whole sparsity sweep.  value = sum over the sweep of 2*nnz*N divided by
+the step time (effective GFLOP/s, FLOPs counted on stored nonzeros only).
+
+Also reported: per-sparsity SpMM kernel time and its fraction of the HBM
+roofline (algorithmic bytes / time / 8 TB/s), the dense FP32 GEMM time
+(torch.matmul) for the speedup, cold-cache kernel times (a 512 MB buffer is
+written between trials so the 256 MB Infinity Cache holds nothing of the
+inputs), and the CPU oracle on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MR = 32
+
+
+def alg_bytes(nnz, ncols, P, k_touched, N, M, s_val=4, s_b=4, s_c=4, beta=0):
+    """Compulsory bytes of one SpMM: packed values + row bytes, column index
+    and count per kept column, panel pointers, the touched rows of B, and C
+    written (read too when beta = 1)."""
+    return (nnz * (s_val + 1) + ncols * 8 + (P + 1) * 12 + k_touched * N * s_b
+            + M * N * s_c * (1 + beta))
+
+
+def cpu_baseline(As, B, budget_s: float = 20.0):
+    """Time the CPU oracle (FP64 CSR loop, row-parallel) on a bounded sample
+    of the same workload; returns the baseline record."""
+    import numpy as np
+    import oracle as O
+    O.build(force=False)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    N = B.shape[1]
+    flops = 0.0
+    t_total = 0.0
+    reps = 0
+    t_start = time.perf_counter()
+    while time.perf_counter() - t_start < budget_s / 2 or reps == 0:
+        for A in As:
+            nnz = int(np.count_nonzero(A.view(np.uint32) & np.uint32(0x7FFFFFFF)))
+            t0 = time.perf_counter()
+            O.spmm(A, B, threads=threads)
+            t_total += time.perf_counter() - t0
+            flops += 2.0 * nnz * N
+        reps += 1
+        if reps >= 3:
+            break
+    return {"value": round(flops / t_total / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{reps} pass(es) over all six sparsities of the 256x2304x3136 layer, "
+                      f"FP64 CSR loop, {threads} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--reps", type=int, default=50, help="kernel launches per timing")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip cold/dense timings")
+    ap.add_argument("--cols-per-lane", type=int, default=None)
+    ap.add_argument("--waves", type=int, default=None)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2307_03930_amd import ops, synth
+
+    torch.backends.cuda.matmul.allow_tf32 = False
+    dev = torch.device("cuda:0")
+    sparsities = list(synth.CNN_SPARSITIES)
+    B_np = synth.cnn_activations()
+    As_np = [synth.cnn_weights(s) for s in sparsities]
+    M, K = As_np[0].shape
+    N = B_np.shape[1]
+    B = torch.from_numpy(B_np).to(dev)
+    As = [torch.from_numpy(a).to(dev) for a in As_np]
+    plan = ops.make_plan(args.cols_per_lane, args.waves)
+
+    # buffers sized once (the sizing query synchronises; the step does not)
+    packs, wss, Cs = [], [], []
+    for A in As:
+        P = ops.pack(A, MR, "f32")
+        packs.append(P)
+        wss.append(torch.empty(max(ops.workspace_size(M, K, MR), 1), dtype=torch.uint8,
+                               device=dev))
+        Cs.append(torch.empty((M, N), dtype=torch.float32, device=dev))
+    nnzs = [P.nnz for P in packs]
+    ncolss = [P.ncols for P in packs]
+    k_touched = [int((a != 0).any(axis=0).sum()) for a in As_np]
+
+    def step():
+        for A, P, ws, C in zip(As, packs, wss, Cs):
+            ops.pack_into(A, P, ws)
+            ops.spmm(P, B, C, plan=plan)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    flops_step = sum(2.0 * z * N for z in nnzs)
+    value = flops_step / (ms_step * 1e-3) / 1e9
+
+    # ---- per-sparsity SpMM kernel time (back-to-back launches, warm)
+    P_panels = (M + MR - 1) // MR
+    per = []
+    tot_bytes, tot_ms = 0.0, 0.0
+    for s, P, C, nnz, nc, kt in zip(sparsities, packs, Cs, nnzs, ncolss, k_touched):
+        for _ in range(3):
+            ops.spmm(P, B, C, plan=plan)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.reps):
+            ops.spmm(P, B, C, plan=plan)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.reps
+        by = alg_bytes(nnz, nc, P_panels, kt, N, M)
+        tot_bytes += by
+        tot_ms += ms
+        per.append({"sparsity": s, "nnz": nnz, "spmm_us": round(ms * 1e3, 2),
+                    "gflops": round(2.0 * nnz * N / (ms * 1e-3) / 1e9, 1),
+                    "alg_MB": round(by / 1e6, 2),
+                    "hbm_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)})
+
+    extras = {}
+    if not args.no_extras:
+        # dense FP32 GEMM at the same shape (hipBLASLt through torch), warm
+        Ad = As[2]
+        for _ in range(3):
+            torch.matmul(Ad, B)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(20):
+            torch.matmul(Ad, B)
+        b.record()
+        torch.cuda.synchronize()
+        dense_us = a.elapsed_time(b) / 20 * 1e3
+        extras["dense_fp32_gemm_us"] = round(dense_us, 2)
+        for rec in per:
+            rec["speedup_vs_dense"] = round(dense_us / rec["spmm_us"], 2)
+        # cold-cache SpMM: overwrite 512 MB between trials
+        flush = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+        for rec, P, C in zip(per, packs, Cs):
+            ts = []
+            for _ in range(10):
+                flush.fill_(1.0)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                ops.spmm(P, B, C, plan=plan)
+                b.record()
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b) * 1e3)
+            rec["spmm_cold_us_median"] = round(float(np.median(ts)), 2)
+        del flush
+
+    achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
+    out = {
+        "metric": "SpMM effective GFLOP/s (2*nnz*N/t)",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "pruned-CNN conv-as-GEMM FP32: A 256x2304 magnitude-pruned at "
+                               "70/80/90/95/99/99.8%, B 2304x3136 im2col(ReLU(N(0,1))); "
+                               "step = pack + SpMM for all six",
+                   "M": M, "K": K, "N": N, "mr": MR, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "k_spmm_sparse",
+                     "launches": len(per)},
+        "per_sparsity": per,
+    }
+    out.update(extras)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(As_np, B_np)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

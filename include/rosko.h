@@ -1,0 +1,195 @@
+/*
+ * rosko.h -- C ABI of the MI355X (gfx950) Rosko library, librosko.so.
+ *
+ * Rosko computes C = A*B where A is an unstructured-sparse M x K matrix (a
+ * pruned weight) and B a dense K x N matrix, as a sum of outer products in
+ * which the result row of each zero entry of an A column is skipped (Sec. 3,
+ * Fig. 4).  A is first packed into mr-row panels; in every panel each column
+ * keeps only its nonzero values, their row indices inside the panel and a
+ * per-column count, and empty columns are dropped (Alg. 1, Sec. 4.1, Fig. 5).
+ * The product then streams, for each kept column, the B row it selects and
+ * multiply-accumulates it into the panel's C rows named by the row indices
+ * (Alg. 2).
+ *
+ * Conventions for every call:
+ *   - Matrices are row-major with an explicit leading dimension (elements).
+ *   - Pointers named as "device" must point to GPU memory of the current HIP
+ *     device; "host" pointers to ordinary process memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     GPU work is enqueued on it and the call returns without waiting, unless
+ *     the call's comment says it synchronises.
+ *   - The library never allocates device memory.  Scratch space is passed in
+ *     as a device workspace `ws` of at least the size the matching
+ *     *_workspace_size call reports.  The caller owns every buffer.
+ *   - Every call returns a status code and never aborts.  On failure,
+ *     rosko_last_error() (per host thread) describes the reason.  Argument
+ *     checks happen on the host before any GPU work is enqueued; a failed
+ *     check enqueues nothing.  Faults of enqueued kernels surface at the
+ *     caller's next synchronisation of the stream.
+ *   - Sizes M, K, N equal to 0 are valid and do no work, except that
+ *     rosko_spmm with beta = 0 still zero-fills an M x N output when K = 0.
+ */
+#ifndef ROSKO_H
+#define ROSKO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------- */
+#define ROSKO_OK 0
+#define ROSKO_EINVAL (-1)        /* invalid argument (null pointer, bad size) */
+#define ROSKO_EUNSUPPORTED (-2)  /* valid but not implemented (dtype, mr, plan) */
+#define ROSKO_ESMALLBUF (-3)     /* a caller buffer or workspace is too small */
+#define ROSKO_EHIP (-4)          /* a HIP runtime call failed */
+#define ROSKO_EINTERNAL (-5)     /* internal inconsistency */
+
+/* ---- value encodings of the packed values --------------------------- */
+#define ROSKO_F32 0       /* IEEE binary32, the source bits unchanged */
+#define ROSKO_BF16 1      /* bfloat16, round to nearest even; NaN -> 0x7FC0 */
+#define ROSKO_FP8_E4M3 2  /* OCP E4M3FN of x / s_m, nearest-even, saturating
+                             to +-448, NaN -> 0x7F; s_m = max_k |A[m][k]| / 448
+                             in FP32 (1.0 for an all-zero row) */
+
+/* ---- packed sparse matrix (Alg. 1 applied to every mr-row panel) ----
+ *
+ * Panel p holds rows [p*mr, min(M, (p+1)*mr)).  Inside a panel, kept columns
+ * are in ascending k and the values of a column in ascending row; panels are
+ * concatenated in ascending p.  An entry is kept when its FP32 bits other
+ * than the sign are not all zero (so -0.0 is dropped; NaN, Inf and
+ * subnormals are kept).  The kept structure never depends on val_dtype.
+ *
+ * All arrays are device memory owned by the caller:
+ *   panel_nz_ptr [n_panels+1] int64  first value slot of each panel; [n_panels] = nnz
+ *   panel_col_ptr[n_panels+1] int64  first column slot of each panel; [n_panels] = ncols
+ *   col_ind  [ncols]   int32   k of each kept column (the paper's col_ind)
+ *   col_nnz  [ncols]   int32   values in the column (the paper's nnz array)
+ *   col_ptr  [ncols+1] int64   first value slot of each column; [ncols] = nnz
+ *                              (a prefix sum of col_nnz, kept so a kernel can
+ *                              start inside a panel without rescanning it)
+ *   loc      [nnz]     uint8   row of the value inside its panel (loc_m)
+ *   val      [nnz]     4, 2 or 1 bytes per value by val_dtype (A_p)
+ *   row_scale[M]       float   s_m for ROSKO_FP8_E4M3, otherwise unused (may be NULL)
+ * nnz_cap and ncols_cap are the capacities of the caller's buffers
+ * (col_ptr must hold ncols_cap+1 entries).  rosko_spmm reads values in
+ * batches of 8 and row bytes by aligned dwords, so val and loc must stay
+ * readable for ROSKO_READ_SLACK entries past nnz (allocate nnz_cap +
+ * ROSKO_READ_SLACK entries); the extra entries are never used.  nnz and ncols are written by
+ * rosko_pack_query / rosko_pack_result on the host side only. */
+#define ROSKO_READ_SLACK 64
+typedef struct rosko_packed {
+  int64_t M, K;
+  int32_t mr;          /* panel height, 1..256 */
+  int32_t n_panels;    /* ceil(M / mr) */
+  int32_t val_dtype;   /* ROSKO_F32 / ROSKO_BF16 / ROSKO_FP8_E4M3 */
+  int32_t reserved;
+  int64_t nnz_cap, ncols_cap;
+  int64_t nnz, ncols;  /* host copies when known, else -1 */
+  int64_t *panel_nz_ptr;
+  int64_t *panel_col_ptr;
+  int32_t *col_ind;
+  int32_t *col_nnz;
+  int64_t *col_ptr;
+  uint8_t *loc;
+  void *val;
+  float *row_scale;
+} rosko_packed;
+
+/* ---- execution plan for rosko_spmm ----------------------------------
+ * path:  ROSKO_PATH_SPARSE  row-skipping vector kernel
+ *        ROSKO_PATH_AUTO    let the library choose
+ * cols_per_lane: B/C columns each of the 64 lanes of a wavefront covers;
+ *        a wavefront covers 64*cols_per_lane columns.  The register tile
+ *        (panel height rounded up to 8/16/32/64/128, times cols_per_lane)
+ *        must be one of 8x4, 16x4, 32x4, 32x2, 64x2, 128x1; other pairs
+ *        return ROSKO_EUNSUPPORTED.  Panel heights above 128 are packed but
+ *        not multiplied by this path.
+ * waves: wavefronts per workgroup splitting one panel's kept columns (1, 2
+ *        or 4); their partial tiles are summed on chip in a fixed order, so
+ *        results do not depend on timing.  */
+#define ROSKO_PATH_AUTO (-1)
+#define ROSKO_PATH_SPARSE 0
+typedef struct rosko_plan {
+  int32_t path;
+  int32_t cols_per_lane;
+  int32_t waves;
+  int32_t reserved;
+} rosko_plan;
+
+/* ---- packing (Alg. 1, Sec. 4.1) --------------------------------------- */
+
+/* Device workspace bytes needed by rosko_pack_query / rosko_pack /
+ * rosko_pack_result for an M x K matrix with panel height mr.  transpose != 0
+ * sizes it for rosko_pack_transpose instead.  EINVAL for negative sizes or mr
+ * outside 1..256. */
+int32_t rosko_pack_workspace_size(int64_t M, int64_t K, int32_t mr, int32_t transpose,
+                                  size_t *bytes);
+
+/* Counts the kept values and kept columns that packing A (device, M x K,
+ * row-major, lda >= K) with panel height mr produces.  SYNCHRONISES `stream`
+ * to return the two totals in *nnz and *ncols (host).  ws: device workspace. */
+int32_t rosko_pack_query(const float *A, int64_t M, int64_t K, int64_t lda, int32_t mr,
+                         void *ws, size_t ws_bytes, void *stream, int64_t *nnz, int64_t *ncols);
+
+/* Packs A (device, M x K, lda >= K) into `out`.  The caller sets out->M, K,
+ * mr, val_dtype, the capacities and the buffer pointers; the call sets
+ * out->n_panels.  The packed arrays are bit-identical to those Alg. 1
+ * produces with the panel order above.  Writes never exceed the capacities;
+ * if the matrix needs more, the excess is dropped and rosko_pack_result
+ * reports ROSKO_ESMALLBUF.  Asynchronous. */
+int32_t rosko_pack(const float *A, int64_t M, int64_t K, int64_t lda, int32_t mr,
+                   int32_t val_dtype, void *ws, size_t ws_bytes, rosko_packed *out,
+                   void *stream);
+
+/* Packs the transpose: the K x M matrix A^T, given A (device, M x K, lda).
+ * out->M must be K and out->K must be M.  Used for dB = A^T dC.  Asynchronous. */
+int32_t rosko_pack_transpose(const float *A, int64_t M, int64_t K, int64_t lda, int32_t mr,
+                             int32_t val_dtype, void *ws, size_t ws_bytes, rosko_packed *out,
+                             void *stream);
+
+/* As rosko_pack_query, for packing A^T (K x M) from A (M x K, lda); ws sized
+ * with transpose != 0.  SYNCHRONISES `stream`. */
+int32_t rosko_pack_transpose_query(const float *A, int64_t M, int64_t K, int64_t lda,
+                                   int32_t mr, void *ws, size_t ws_bytes, void *stream,
+                                   int64_t *nnz, int64_t *ncols);
+
+/* After rosko_pack / rosko_pack_transpose with the same ws: SYNCHRONISES the
+ * stream, stores the totals in packed->nnz / ncols, and returns
+ * ROSKO_ESMALLBUF if they exceeded the capacities. */
+int32_t rosko_pack_result(const void *ws, size_t ws_bytes, rosko_packed *packed, void *stream);
+
+/* ---- SpMM (Alg. 2) ------------------------------------------------------ */
+
+/* C = A*B (beta = 0) or C += A*B (beta = 1), with A packed, B (device,
+ * A->K x N, row-major, ldb >= N) in FP32 (b_dtype ROSKO_F32) or BF16
+ * (ROSKO_BF16, raw 16-bit patterns), C (device, A->M x N FP32, ldc >= N).
+ * Accumulation is FP32; FP8 values are multiplied by s_m once per output.
+ * plan may be NULL (automatic).  Asynchronous. */
+int32_t rosko_spmm(const rosko_packed *A, const void *B, int32_t b_dtype, int64_t N,
+                   int64_t ldb, float *C, int64_t ldc, int32_t beta, const rosko_plan *plan,
+                   void *stream);
+
+/* ---- backward of C = A*B (training decomposition, Sec. 5.4) ------------
+ * dB = A^T dC, computed as a Rosko SpMM over At, the packed transpose of A
+ * (from rosko_pack_transpose; FP32 values).  dA = (dC B^T) restricted to the
+ * kept entries of A, written as one FP32 value per kept entry in A's packed
+ * order (an SDDMM; pruned entries get no gradient).  dC (device, A->M x N,
+ * lddc), B (device FP32, A->K x N, ldb).  dB (device, A->K x N, lddb) or
+ * dA_val (device, A's nnz floats) may be NULL to skip that gradient; At may
+ * be NULL when dB is.  Asynchronous. */
+int32_t rosko_spmm_backward(const rosko_packed *A, const rosko_packed *At, const float *B,
+                            int64_t ldb, const float *dC, int64_t lddc, int64_t N, float *dB,
+                            int64_t lddb, float *dA_val, void *stream);
+
+/* ---- errors ----------------------------------------------------------- */
+const char *rosko_status_str(int32_t status);
+const char *rosko_last_error(void);   /* per host thread; "" if none */
+int32_t rosko_abi_version(void);      /* 1 */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ROSKO_H */

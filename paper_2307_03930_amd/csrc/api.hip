@@ -1,0 +1,311 @@
+// C-ABI entry points of librosko.so: argument checks on the host, then
+// kernel launches on the caller's stream.  See include/rosko.h.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "internal.h"
+
+namespace rosko {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+void clear_error() { g_err[0] = '\0'; }
+
+}  // namespace rosko
+
+using namespace rosko;
+
+#define RK_REQUIRE(cond, code, ...) \
+  do {                              \
+    if (!(cond)) {                  \
+      set_error(__VA_ARGS__);       \
+      return (code);                \
+    }                               \
+  } while (0)
+
+static int32_t check_dense(const void* A, int64_t M, int64_t K, int64_t lda, const char* name) {
+  RK_REQUIRE(M >= 0 && K >= 0, ROSKO_EINVAL, "%s: negative size (%lld x %lld)", name,
+             (long long)M, (long long)K);
+  RK_REQUIRE(lda >= K && lda >= 1, ROSKO_EINVAL, "%s: leading dimension %lld < %lld", name,
+             (long long)lda, (long long)K);
+  RK_REQUIRE(A != nullptr || M == 0 || K == 0, ROSKO_EINVAL, "%s: null pointer", name);
+  return ROSKO_OK;
+}
+
+static int32_t check_mr(int32_t mr) {
+  RK_REQUIRE(mr >= 1 && mr <= 256, ROSKO_EINVAL, "mr %d outside 1..256", mr);
+  return ROSKO_OK;
+}
+
+static int32_t check_packed_for_write(const rosko_packed* out, int64_t R, int64_t S, int32_t mr,
+                                      int32_t dt) {
+  RK_REQUIRE(out != nullptr, ROSKO_EINVAL, "packed output is null");
+  RK_REQUIRE(out->M == R && out->K == S && out->mr == mr, ROSKO_EINVAL,
+             "packed output shape (%lld x %lld, mr %d) does not match (%lld x %lld, mr %d)",
+             (long long)out->M, (long long)out->K, out->mr, (long long)R, (long long)S, mr);
+  RK_REQUIRE(dt == ROSKO_F32 || dt == ROSKO_BF16 || dt == ROSKO_FP8_E4M3, ROSKO_EUNSUPPORTED,
+             "value dtype %d not supported", dt);
+  RK_REQUIRE(out->nnz_cap >= 0 && out->ncols_cap >= 0, ROSKO_EINVAL, "negative capacity");
+  RK_REQUIRE(out->panel_nz_ptr && out->panel_col_ptr && out->col_ptr, ROSKO_EINVAL,
+             "packed pointer arrays are null");
+  RK_REQUIRE(out->ncols_cap == 0 || (out->col_ind && out->col_nnz), ROSKO_EINVAL,
+             "packed column arrays are null");
+  RK_REQUIRE(out->nnz_cap == 0 || (out->loc && out->val), ROSKO_EINVAL,
+             "packed value arrays are null");
+  RK_REQUIRE(dt != ROSKO_FP8_E4M3 || R == 0 || out->row_scale, ROSKO_EINVAL,
+             "FP8 packing needs row_scale");
+  return ROSKO_OK;
+}
+
+static int32_t check_packed_for_read(const rosko_packed* A) {
+  RK_REQUIRE(A != nullptr, ROSKO_EINVAL, "packed matrix is null");
+  RK_REQUIRE(A->M >= 0 && A->K >= 0, ROSKO_EINVAL, "packed matrix has a negative size");
+  int32_t st = check_mr(A->mr);
+  if (st) return st;
+  RK_REQUIRE(A->n_panels == ceil_div(A->M, A->mr), ROSKO_EINVAL,
+             "n_panels %d != ceil(M / mr) = %lld", A->n_panels,
+             (long long)ceil_div(A->M, A->mr));
+  RK_REQUIRE(A->val_dtype == ROSKO_F32 || A->val_dtype == ROSKO_BF16 ||
+                 A->val_dtype == ROSKO_FP8_E4M3,
+             ROSKO_EUNSUPPORTED, "value dtype %d not supported", A->val_dtype);
+  RK_REQUIRE(A->M == 0 || (A->panel_nz_ptr && A->panel_col_ptr && A->col_ptr), ROSKO_EINVAL,
+             "packed pointer arrays are null");
+  RK_REQUIRE(A->ncols_cap == 0 || (A->col_ind && A->col_nnz), ROSKO_EINVAL,
+             "packed column arrays are null");
+  RK_REQUIRE(A->nnz_cap == 0 || (A->loc && A->val), ROSKO_EINVAL,
+             "packed value arrays are null");
+  RK_REQUIRE(A->val_dtype != ROSKO_FP8_E4M3 || A->M == 0 || A->row_scale, ROSKO_EINVAL,
+             "FP8 values need row_scale");
+  return ROSKO_OK;
+}
+
+extern "C" {
+
+int32_t rosko_abi_version(void) { return 1; }
+
+const char* rosko_last_error(void) { return g_err; }
+
+const char* rosko_status_str(int32_t s) {
+  switch (s) {
+    case ROSKO_OK: return "ROSKO_OK";
+    case ROSKO_EINVAL: return "ROSKO_EINVAL";
+    case ROSKO_EUNSUPPORTED: return "ROSKO_EUNSUPPORTED";
+    case ROSKO_ESMALLBUF: return "ROSKO_ESMALLBUF";
+    case ROSKO_EHIP: return "ROSKO_EHIP";
+    case ROSKO_EINTERNAL: return "ROSKO_EINTERNAL";
+    default: return "ROSKO_UNKNOWN";
+  }
+}
+
+int32_t rosko_pack_workspace_size(int64_t M, int64_t K, int32_t mr, int32_t transpose,
+                                  size_t* bytes) {
+  clear_error();
+  RK_REQUIRE(bytes != nullptr, ROSKO_EINVAL, "bytes is null");
+  RK_REQUIRE(M >= 0 && K >= 0, ROSKO_EINVAL, "negative size");
+  int32_t st = check_mr(mr);
+  if (st) return st;
+  // transpose packing packs the K x M matrix A^T
+  const PackWs L = transpose ? pack_ws_layout(K, M, mr, true) : pack_ws_layout(M, K, mr, false);
+  *bytes = L.bytes;
+  return ROSKO_OK;
+}
+
+int32_t rosko_pack_query(const float* A, int64_t M, int64_t K, int64_t lda, int32_t mr,
+                         void* ws, size_t ws_bytes, void* stream, int64_t* nnz,
+                         int64_t* ncols) {
+  clear_error();
+  int32_t st = check_dense(A, M, K, lda, "A");
+  if (st) return st;
+  if ((st = check_mr(mr))) return st;
+  RK_REQUIRE(nnz && ncols, ROSKO_EINVAL, "nnz / ncols outputs are null");
+  const PackWs L = pack_ws_layout(M, K, mr, false);
+  RK_REQUIRE(ws != nullptr && ws_bytes >= L.bytes, ROSKO_ESMALLBUF,
+             "workspace %zu bytes < %zu", ws_bytes, L.bytes);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  if ((st = launch_pack_count_scan(A, M, K, lda, mr, ws, L, nullptr, s))) return st;
+  int64_t tot[4];
+  ROSKO_HIP_CHECK(hipMemcpyAsync(tot, static_cast<char*>(ws) + L.totals, sizeof(tot),
+                                 hipMemcpyDeviceToHost, s));
+  ROSKO_HIP_CHECK(hipStreamSynchronize(s));
+  *nnz = tot[0];
+  *ncols = tot[1];
+  return ROSKO_OK;
+}
+
+int32_t rosko_pack_transpose_query(const float* A, int64_t M, int64_t K, int64_t lda,
+                                   int32_t mr, void* ws, size_t ws_bytes, void* stream,
+                                   int64_t* nnz, int64_t* ncols) {
+  clear_error();
+  int32_t st = check_dense(A, M, K, lda, "A");
+  if (st) return st;
+  if ((st = check_mr(mr))) return st;
+  RK_REQUIRE(nnz && ncols, ROSKO_EINVAL, "nnz / ncols outputs are null");
+  const PackWs L = pack_ws_layout(K, M, mr, true);
+  RK_REQUIRE(ws != nullptr && ws_bytes >= L.bytes, ROSKO_ESMALLBUF,
+             "workspace %zu bytes < %zu", ws_bytes, L.bytes);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float* At = reinterpret_cast<float*>(static_cast<char*>(ws) + L.transposed);
+  (void)hipGetLastError();
+  if ((st = launch_transpose(A, M, K, lda, At, s))) return st;
+  if ((st = launch_pack_count_scan(At, K, M, M > 0 ? M : 1, mr, ws, L, nullptr, s))) return st;
+  int64_t tot[4];
+  ROSKO_HIP_CHECK(hipMemcpyAsync(tot, static_cast<char*>(ws) + L.totals, sizeof(tot),
+                                 hipMemcpyDeviceToHost, s));
+  ROSKO_HIP_CHECK(hipStreamSynchronize(s));
+  *nnz = tot[0];
+  *ncols = tot[1];
+  return ROSKO_OK;
+}
+
+static int32_t pack_common(const float* A, int64_t R, int64_t S, int64_t lda, int32_t mr,
+                           int32_t val_dtype, void* ws, const PackWs& L, rosko_packed* out,
+                           hipStream_t s) {
+  int32_t st;
+  out->n_panels = (int32_t)L.P;
+  out->val_dtype = val_dtype;
+  out->nnz = -1;
+  out->ncols = -1;
+  (void)hipGetLastError();
+  if (val_dtype == ROSKO_FP8_E4M3) {
+    if ((st = launch_row_scale(A, R, S, lda, out->row_scale, s))) return st;
+  }
+  if ((st = launch_pack_count_scan(A, R, S, lda, mr, ws, L, out, s))) return st;
+  return launch_pack_write(A, R, S, lda, mr, val_dtype, ws, L, out, s);
+}
+
+int32_t rosko_pack(const float* A, int64_t M, int64_t K, int64_t lda, int32_t mr,
+                   int32_t val_dtype, void* ws, size_t ws_bytes, rosko_packed* out,
+                   void* stream) {
+  clear_error();
+  int32_t st = check_dense(A, M, K, lda, "A");
+  if (st) return st;
+  if ((st = check_mr(mr))) return st;
+  if ((st = check_packed_for_write(out, M, K, mr, val_dtype))) return st;
+  const PackWs L = pack_ws_layout(M, K, mr, false);
+  RK_REQUIRE(L.P <= INT32_MAX, ROSKO_EUNSUPPORTED, "too many panels");
+  RK_REQUIRE(ws != nullptr && ws_bytes >= L.bytes, ROSKO_ESMALLBUF,
+             "workspace %zu bytes < %zu", ws_bytes, L.bytes);
+  return pack_common(A, M, K, lda, mr, val_dtype, ws, L, out, static_cast<hipStream_t>(stream));
+}
+
+int32_t rosko_pack_transpose(const float* A, int64_t M, int64_t K, int64_t lda, int32_t mr,
+                             int32_t val_dtype, void* ws, size_t ws_bytes, rosko_packed* out,
+                             void* stream) {
+  clear_error();
+  int32_t st = check_dense(A, M, K, lda, "A");
+  if (st) return st;
+  if ((st = check_mr(mr))) return st;
+  if ((st = check_packed_for_write(out, K, M, mr, val_dtype))) return st;
+  const PackWs L = pack_ws_layout(K, M, mr, true);
+  RK_REQUIRE(L.P <= INT32_MAX, ROSKO_EUNSUPPORTED, "too many panels");
+  RK_REQUIRE(ws != nullptr && ws_bytes >= L.bytes, ROSKO_ESMALLBUF,
+             "workspace %zu bytes < %zu", ws_bytes, L.bytes);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float* At = reinterpret_cast<float*>(static_cast<char*>(ws) + L.transposed);
+  (void)hipGetLastError();
+  if ((st = launch_transpose(A, M, K, lda, At, s))) return st;
+  return pack_common(At, K, M, M > 0 ? M : 1, mr, val_dtype, ws, L, out, s);
+}
+
+int32_t rosko_pack_result(const void* ws, size_t ws_bytes, rosko_packed* packed, void* stream) {
+  clear_error();
+  RK_REQUIRE(packed != nullptr, ROSKO_EINVAL, "packed is null");
+  int32_t st = check_mr(packed->mr);
+  if (st) return st;
+  const PackWs L = pack_ws_layout(packed->M, packed->K, packed->mr, false);
+  RK_REQUIRE(ws != nullptr && ws_bytes >= L.totals + 4 * sizeof(int64_t), ROSKO_ESMALLBUF,
+             "workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int64_t tot[4];
+  ROSKO_HIP_CHECK(hipMemcpyAsync(tot, static_cast<const char*>(ws) + L.totals, sizeof(tot),
+                                 hipMemcpyDeviceToHost, s));
+  ROSKO_HIP_CHECK(hipStreamSynchronize(s));
+  packed->nnz = tot[0];
+  packed->ncols = tot[1];
+  RK_REQUIRE(tot[2] == 0, ROSKO_ESMALLBUF,
+             "packing needs %lld values / %lld columns, capacities are %lld / %lld",
+             (long long)tot[0], (long long)tot[1], (long long)packed->nnz_cap,
+             (long long)packed->ncols_cap);
+  return ROSKO_OK;
+}
+
+// Default plan (the analytic fallback): the widest register tile the panel
+// height allows -- 128 accumulators per lane -- and two wavefronts
+// splitting each panel's kept columns.
+static rosko_plan default_plan(const rosko_packed* A, int64_t N) {
+  rosko_plan p{};
+  p.path = ROSKO_PATH_SPARSE;
+  if (A->mr <= 32) p.cols_per_lane = 4;
+  else if (A->mr <= 64) p.cols_per_lane = 2;
+  else p.cols_per_lane = 1;
+  if (A->mr > 16 && A->mr <= 32 && N <= 128) p.cols_per_lane = 2;
+  p.waves = 2;
+  return p;
+}
+
+int32_t rosko_spmm(const rosko_packed* A, const void* B, int32_t b_dtype, int64_t N,
+                   int64_t ldb, float* C, int64_t ldc, int32_t beta, const rosko_plan* plan,
+                   void* stream) {
+  clear_error();
+  int32_t st = check_packed_for_read(A);
+  if (st) return st;
+  RK_REQUIRE(b_dtype == ROSKO_F32 || b_dtype == ROSKO_BF16, ROSKO_EUNSUPPORTED,
+             "B dtype %d not supported", b_dtype);
+  RK_REQUIRE(N >= 0, ROSKO_EINVAL, "negative N");
+  RK_REQUIRE(ldb >= N && ldb >= 1, ROSKO_EINVAL, "ldb %lld < N %lld", (long long)ldb,
+             (long long)N);
+  RK_REQUIRE(ldc >= N && ldc >= 1, ROSKO_EINVAL, "ldc %lld < N %lld", (long long)ldc,
+             (long long)N);
+  RK_REQUIRE(beta == 0 || beta == 1, ROSKO_EINVAL, "beta must be 0 or 1");
+  RK_REQUIRE(B != nullptr || A->K == 0 || N == 0, ROSKO_EINVAL, "B is null");
+  RK_REQUIRE(C != nullptr || A->M == 0 || N == 0, ROSKO_EINVAL, "C is null");
+  if (A->M == 0 || N == 0) return ROSKO_OK;
+  rosko_plan p = (plan && plan->path != ROSKO_PATH_AUTO) ? *plan : default_plan(A, N);
+  RK_REQUIRE(p.path == ROSKO_PATH_SPARSE, ROSKO_EUNSUPPORTED, "plan path %d not supported",
+             p.path);
+  (void)hipGetLastError();
+  return launch_spmm_sparse(A, B, b_dtype, N, ldb, C, ldc, beta, p,
+                            static_cast<hipStream_t>(stream));
+}
+
+int32_t rosko_spmm_backward(const rosko_packed* A, const rosko_packed* At, const float* B,
+                            int64_t ldb, const float* dC, int64_t lddc, int64_t N, float* dB,
+                            int64_t lddb, float* dA_val, void* stream) {
+  clear_error();
+  int32_t st = check_packed_for_read(A);
+  if (st) return st;
+  RK_REQUIRE(N >= 0, ROSKO_EINVAL, "negative N");
+  RK_REQUIRE(lddc >= N && lddc >= 1, ROSKO_EINVAL, "lddc < N");
+  RK_REQUIRE(dC != nullptr || A->M == 0 || N == 0, ROSKO_EINVAL, "dC is null");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dB) {
+    if ((st = check_packed_for_read(At))) return st;
+    RK_REQUIRE(At->M == A->K && At->K == A->M, ROSKO_EINVAL,
+               "At is %lld x %lld, expected %lld x %lld", (long long)At->M, (long long)At->K,
+               (long long)A->K, (long long)A->M);
+    RK_REQUIRE(At->val_dtype == ROSKO_F32, ROSKO_EUNSUPPORTED, "At must hold FP32 values");
+    RK_REQUIRE(lddb >= N && lddb >= 1, ROSKO_EINVAL, "lddb < N");
+    if (At->M > 0 && N > 0) {
+      rosko_plan p = default_plan(At, N);
+      (void)hipGetLastError();
+      if ((st = launch_spmm_sparse(At, dC, ROSKO_F32, N, lddc, dB, lddb, 0, p, s))) return st;
+    }
+  }
+  if (dA_val) {
+    RK_REQUIRE(ldb >= N && ldb >= 1, ROSKO_EINVAL, "ldb < N");
+    RK_REQUIRE(B != nullptr || A->K == 0 || N == 0, ROSKO_EINVAL, "B is null");
+    (void)hipGetLastError();
+    if ((st = launch_sddmm(A, dC, lddc, B, ldb, N, dA_val, s))) return st;
+  }
+  return ROSKO_OK;
+}
+
+}  // extern "C"

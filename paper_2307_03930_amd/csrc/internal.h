@@ -1,0 +1,105 @@
+// Internal declarations shared by the library's HIP translation units.
+// Nothing here is part of the public ABI (include/rosko.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/rosko.h"
+
+namespace rosko {
+
+// Error state (per host thread) and helpers.
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define ROSKO_HIP_CHECK(call)                                                          \
+  do {                                                                                 \
+    hipError_t e__ = (call);                                                           \
+    if (e__ != hipSuccess) {                                                           \
+      ::rosko::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e__),       \
+                         __FILE__, __LINE__);                                          \
+      return ROSKO_EHIP;                                                               \
+    }                                                                                  \
+  } while (0)
+
+// Launch check right after a kernel launch.
+#define ROSKO_LAUNCH_CHECK(name)                                                       \
+  do {                                                                                 \
+    hipError_t e__ = hipGetLastError();                                                \
+    if (e__ != hipSuccess) {                                                           \
+      ::rosko::set_error("launch of %s failed: %s", name, hipGetErrorString(e__));     \
+      return ROSKO_EHIP;                                                               \
+    }                                                                                  \
+  } while (0)
+
+// ---------------------------------------------------------------- packing
+// Workspace layout (byte offsets, 256-byte aligned) for packing an
+// R x S matrix (R rows split into panels of mr) given as rows x cols.
+struct PackWs {
+  size_t counts;       // int32 [P*S]        values per (panel, column)
+  size_t tile_sums;    // int64 [2*NT]       (values, kept columns) per tile
+  size_t tile_offs;    // int64 [2*NT]       exclusive prefix of tile_sums
+  size_t totals;       // int64 [4]          nnz, ncols, overflow flag, spare
+  size_t transposed;   // float [R*S]        dense transpose (transpose packing only)
+  size_t bytes;        // total
+  int64_t P, NT;
+};
+constexpr int kPackTile = 1024;      // (panel, column) pairs per scan tile
+constexpr int kPackThreads = 256;
+PackWs pack_ws_layout(int64_t R, int64_t S, int32_t mr, bool transpose);
+
+// Enqueue count + tile scan (everything rosko_pack_query needs).
+int32_t launch_pack_count_scan(const float* A, int64_t R, int64_t S, int64_t lda, int32_t mr,
+                               void* ws, const PackWs& L, const rosko_packed* out,
+                               hipStream_t s);
+// Enqueue the write pass (values, loc, col arrays, panel pointers).
+int32_t launch_pack_write(const float* A, int64_t R, int64_t S, int64_t lda, int32_t mr,
+                          int32_t val_dtype, void* ws, const PackWs& L, const rosko_packed* out,
+                          hipStream_t s);
+int32_t launch_row_scale(const float* A, int64_t R, int64_t S, int64_t lda, float* scale,
+                         hipStream_t s);
+int32_t launch_transpose(const float* A, int64_t M, int64_t K, int64_t lda, float* At,
+                         hipStream_t s);
+
+// ------------------------------------------------------------------- SpMM
+// Kernel arguments of the row-skipping SpMM (device pointers of the packed
+// matrix, B and C).
+struct SpmmArgs {
+  const int64_t* panel_col_ptr;
+  const int32_t* col_ind;
+  const int32_t* col_nnz;
+  const int64_t* col_ptr;
+  const uint8_t* loc;
+  const void* val;
+  const float* row_scale;
+  const void* B;
+  float* C;
+  int64_t M, N, ldb, ldc;
+  int32_t mr, n_panels;
+  int32_t beta;
+  int32_t vec;   // B/C rows allow V-wide vector access (alignment, N % V)
+};
+// One dispatcher per (value dtype, B dtype); H = register-tile height,
+// V = columns per lane, W = waves per workgroup.
+int32_t spmm_dispatch_f32_f32(const SpmmArgs& g, int H, int V, int W, hipStream_t s);
+int32_t spmm_dispatch_f32_bf16(const SpmmArgs& g, int H, int V, int W, hipStream_t s);
+int32_t spmm_dispatch_bf16_f32(const SpmmArgs& g, int H, int V, int W, hipStream_t s);
+int32_t spmm_dispatch_bf16_bf16(const SpmmArgs& g, int H, int V, int W, hipStream_t s);
+int32_t spmm_dispatch_fp8_f32(const SpmmArgs& g, int H, int V, int W, hipStream_t s);
+int32_t spmm_dispatch_fp8_bf16(const SpmmArgs& g, int H, int V, int W, hipStream_t s);
+
+int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype, int64_t N,
+                           int64_t ldb, float* C, int64_t ldc, int32_t beta,
+                           const rosko_plan& plan, hipStream_t s);
+int32_t launch_fill_zero(float* C, int64_t M, int64_t N, int64_t ldc, hipStream_t s);
+
+// ---------------------------------------------------------------- SDDMM
+int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const float* B,
+                     int64_t ldb, int64_t N, float* dA_val, hipStream_t s);
+
+// Round x up to a multiple of a (a > 0).
+inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+inline int64_t ceil_div(int64_t x, int64_t a) { return (x + a - 1) / a; }
+
+}  // namespace rosko

@@ -1,0 +1,8 @@
+// Row-skipping SpMM instances: f32 packed values, f32 B.
+#include "spmm_kernel.h"
+
+namespace rosko {
+int32_t spmm_dispatch_f32_f32(const SpmmArgs& g, int H, int V, int W, hipStream_t s) {
+  return dispatch_tile<ROSKO_F32, ROSKO_F32>(g, H, V, W, s);
+}
+}  // namespace rosko

@@ -1,0 +1,230 @@
+"""Torch-facing wrappers of the C ABI: device memory and streams come from
+torch, every step of the computation runs in librosko.so.
+
+  pack(A, mr, dtype)            Alg. 1 on the GPU -> PackedMatrix
+  pack_transpose(A, mr)         packs A^T (for dB = A^T dC)
+  spmm(P, B, C=None, beta=0)    Alg. 2 on the GPU: C = A B (or C += A B)
+  spmm_backward(P, Pt, B, dC)   dB = A^T dC and dA (packed order)
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+DTYPES = {"f32": L.ROSKO_F32, "bf16": L.ROSKO_BF16, "fp8": L.ROSKO_FP8_E4M3}
+_VAL_TORCH = {L.ROSKO_F32: torch.float32, L.ROSKO_BF16: torch.int16,
+              L.ROSKO_FP8_E4M3: torch.uint8}
+# reads of a column batch may run up to 8 values / 12 bytes past a column's
+# end, so value and row arrays carry this many spare entries
+SLACK = 64
+
+
+def _stream_ptr(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> C.c_void_p:
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dtype_code(dtype) -> int:
+    if isinstance(dtype, str):
+        return DTYPES[dtype]
+    return int(dtype)
+
+
+@dataclass
+class PackedMatrix:
+    """A packed M x K matrix: the device arrays of include/rosko.h's
+    rosko_packed, owned here as torch tensors."""
+    M: int
+    K: int
+    mr: int
+    val_dtype: int
+    nnz: int
+    ncols: int
+    panel_nz_ptr: torch.Tensor
+    panel_col_ptr: torch.Tensor
+    col_ind: torch.Tensor
+    col_nnz: torch.Tensor
+    col_ptr: torch.Tensor
+    loc: torch.Tensor
+    val: torch.Tensor
+    row_scale: torch.Tensor | None
+
+    @property
+    def n_panels(self) -> int:
+        return (self.M + self.mr - 1) // self.mr
+
+    def struct(self) -> L.RoskoPacked:
+        s = L.RoskoPacked()
+        s.M, s.K, s.mr, s.n_panels = self.M, self.K, self.mr, self.n_panels
+        s.val_dtype = self.val_dtype
+        s.nnz_cap, s.ncols_cap = self.nnz, self.ncols
+        s.nnz, s.ncols = self.nnz, self.ncols
+        s.panel_nz_ptr = self.panel_nz_ptr.data_ptr()
+        s.panel_col_ptr = self.panel_col_ptr.data_ptr()
+        s.col_ind = self.col_ind.data_ptr()
+        s.col_nnz = self.col_nnz.data_ptr()
+        s.col_ptr = self.col_ptr.data_ptr()
+        s.loc = self.loc.data_ptr()
+        s.val = self.val.data_ptr()
+        s.row_scale = 0 if self.row_scale is None else self.row_scale.data_ptr()
+        return s
+
+    def values(self) -> torch.Tensor:
+        """The nnz stored values (raw encoding)."""
+        return self.val[: self.nnz]
+
+
+def workspace_size(M: int, K: int, mr: int, transpose: bool = False) -> int:
+    n = C.c_size_t(0)
+    L.check(L.lib().rosko_pack_workspace_size(M, K, mr, 1 if transpose else 0, C.byref(n)))
+    return int(n.value)
+
+
+def _check_dense(A: torch.Tensor, name: str):
+    if not (A.is_cuda and A.dtype == torch.float32 and A.dim() == 2):
+        raise ValueError(f"{name} must be a 2-D float32 CUDA tensor")
+    if A.stride(1) != 1:
+        raise ValueError(f"{name} must be row-major with unit column stride")
+
+
+def _alloc(M, K, mr, dtype, nnz, ncols, device):
+    P = (M + mr - 1) // mr
+    i64, i32 = torch.int64, torch.int32
+    return PackedMatrix(
+        M=M, K=K, mr=mr, val_dtype=dtype, nnz=nnz, ncols=ncols,
+        panel_nz_ptr=torch.empty(P + 1, dtype=i64, device=device),
+        panel_col_ptr=torch.empty(P + 1, dtype=i64, device=device),
+        col_ind=torch.empty(max(ncols, 1), dtype=i32, device=device),
+        col_nnz=torch.empty(max(ncols, 1), dtype=i32, device=device),
+        col_ptr=torch.empty(ncols + 1, dtype=i64, device=device),
+        loc=torch.zeros(nnz + SLACK, dtype=torch.uint8, device=device),
+        val=torch.zeros(nnz + SLACK, dtype=_VAL_TORCH[dtype], device=device),
+        row_scale=(torch.empty(max(M, 1), dtype=torch.float32, device=device)
+                   if dtype == L.ROSKO_FP8_E4M3 else None),
+    )
+
+
+def pack_query(A: torch.Tensor, mr: int, ws: torch.Tensor | None = None):
+    """(nnz, ncols) of packing A with panel height mr.  Synchronises."""
+    _check_dense(A, "A")
+    M, K = A.shape
+    if ws is None:
+        ws = torch.empty(max(workspace_size(M, K, mr), 1), dtype=torch.uint8, device=A.device)
+    nnz, ncols = C.c_int64(0), C.c_int64(0)
+    L.check(L.lib().rosko_pack_query(_ptr(A), M, K, max(A.stride(0), 1), mr, _ptr(ws), ws.numel(),
+                                     _stream_ptr(), C.byref(nnz), C.byref(ncols)))
+    return int(nnz.value), int(ncols.value)
+
+
+def pack(A: torch.Tensor, mr: int = 32, dtype="f32") -> PackedMatrix:
+    """Alg. 1 on every mr-row panel of A (2-D float32 CUDA tensor)."""
+    _check_dense(A, "A")
+    dt = _dtype_code(dtype)
+    M, K = A.shape
+    ws = torch.empty(max(workspace_size(M, K, mr), 1), dtype=torch.uint8, device=A.device)
+    nnz, ncols = pack_query(A, mr, ws)
+    P = _alloc(M, K, mr, dt, nnz, ncols, A.device)
+    st = P.struct()
+    L.check(L.lib().rosko_pack(_ptr(A), M, K, max(A.stride(0), 1), mr, dt, _ptr(ws), ws.numel(),
+                               C.byref(st), _stream_ptr()))
+    P._ws = ws  # keep the workspace alive until the enqueued work is done
+    return P
+
+
+def pack_transpose(A: torch.Tensor, mr: int = 32) -> PackedMatrix:
+    """Packs A^T (K x M, FP32 values) directly from A."""
+    _check_dense(A, "A")
+    M, K = A.shape
+    ws = torch.empty(max(workspace_size(M, K, mr, transpose=True), 1), dtype=torch.uint8,
+                     device=A.device)
+    nnz, ncols = C.c_int64(0), C.c_int64(0)
+    L.check(L.lib().rosko_pack_transpose_query(_ptr(A), M, K, max(A.stride(0), 1), mr,
+                                               _ptr(ws), ws.numel(), _stream_ptr(),
+                                               C.byref(nnz), C.byref(ncols)))
+    nnz, ncols = int(nnz.value), int(ncols.value)
+    P = _alloc(K, M, mr, L.ROSKO_F32, nnz, ncols, A.device)
+    st = P.struct()
+    L.check(L.lib().rosko_pack_transpose(_ptr(A), M, K, max(A.stride(0), 1), mr, L.ROSKO_F32, _ptr(ws),
+                                         ws.numel(), C.byref(st), _stream_ptr()))
+    P._ws = ws
+    return P
+
+
+def make_plan(cols_per_lane: int | None = None, waves: int | None = None,
+              path: int = L.ROSKO_PATH_SPARSE) -> L.RoskoPlan | None:
+    if cols_per_lane is None and waves is None:
+        return None
+    p = L.RoskoPlan()
+    p.path = path
+    p.cols_per_lane = cols_per_lane or 4
+    p.waves = waves or 2
+    return p
+
+
+def spmm(P: PackedMatrix, B: torch.Tensor, C_out: torch.Tensor | None = None, beta: int = 0,
+         plan: L.RoskoPlan | None = None) -> torch.Tensor:
+    """C = A B (beta 0) or C += A B (beta 1).  B: K x N float32 or bfloat16."""
+    if not (B.is_cuda and B.dim() == 2 and B.stride(1) == 1):
+        raise ValueError("B must be a 2-D row-major CUDA tensor")
+    if B.dtype == torch.float32:
+        bdt = L.ROSKO_F32
+    elif B.dtype == torch.bfloat16:
+        bdt = L.ROSKO_BF16
+    else:
+        raise ValueError("B must be float32 or bfloat16")
+    if B.shape[0] != P.K:
+        raise ValueError(f"B has {B.shape[0]} rows, A has {P.K} columns")
+    N = B.shape[1]
+    if C_out is None:
+        if beta:
+            raise ValueError("beta = 1 needs C_out")
+        C_out = torch.empty((P.M, N), dtype=torch.float32, device=B.device)
+    st = P.struct()
+    pl = C.byref(plan) if plan is not None else None
+    L.check(L.lib().rosko_spmm(C.byref(st), _ptr(B), bdt, N, max(B.stride(0), 1), _ptr(C_out),
+                               max(C_out.stride(0), 1), beta, pl, _stream_ptr()))
+    return C_out
+
+
+def spmm_backward(P: PackedMatrix, Pt: PackedMatrix | None, B: torch.Tensor, dC: torch.Tensor,
+                  need_dB: bool = True, need_dA: bool = True):
+    """(dA in packed order, dB) for C = A B."""
+    N = dC.shape[1]
+    dB = torch.empty((P.K, N), dtype=torch.float32, device=dC.device) if need_dB else None
+    dA = torch.empty(max(P.nnz, 1), dtype=torch.float32, device=dC.device) if need_dA else None
+    st = P.struct()
+    stt = Pt.struct() if Pt is not None else None
+    L.check(L.lib().rosko_spmm_backward(
+        C.byref(st), C.byref(stt) if stt is not None else None, _ptr(B),
+        max(B.stride(0), 1), _ptr(dC), max(dC.stride(0), 1), N, _ptr(dB),
+        max(dB.stride(0), 1) if dB is not None else 1, _ptr(dA), _stream_ptr()))
+    return (dA[: P.nnz] if dA is not None else None), dB
+
+
+def pack_into(A: torch.Tensor, P: PackedMatrix, ws: torch.Tensor) -> PackedMatrix:
+    """Re-packs A into P's existing buffers (same shape, mr and dtype; the
+    capacities must hold A's structure).  Asynchronous: no host sync."""
+    _check_dense(A, "A")
+    M, K = A.shape
+    if (M, K) != (P.M, P.K):
+        raise ValueError("shape differs from the packed buffers")
+    st = P.struct()
+    L.check(L.lib().rosko_pack(_ptr(A), M, K, max(A.stride(0), 1), P.mr, P.val_dtype, _ptr(ws),
+                               ws.numel(), C.byref(st), _stream_ptr()))
+    return P
+
+
+def pack_result(P: PackedMatrix, ws: torch.Tensor) -> tuple[int, int]:
+    """Synchronises; (nnz, ncols) of the last pack_into with this workspace.
+    Raises if they exceeded P's capacities."""
+    st = P.struct()
+    L.check(L.lib().rosko_pack_result(_ptr(ws), ws.numel(), C.byref(st), _stream_ptr()))
+    return int(st.nnz), int(st.ncols)

@@ -1,0 +1,54 @@
+"""Shared helpers of the GPU parity tests (HIP path through the C ABI versus
+the CPU oracle)."""
+import sys
+
+import numpy as np
+import torch
+
+import oracle as O
+from paper_2307_03930_amd import ops
+
+DT = {"f32": O.F32, "bf16": O.BF16, "fp8": O.FP8}
+
+
+def say(msg: str) -> None:
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def packed_to_np(P: ops.PackedMatrix) -> dict:
+    torch.cuda.synchronize()
+    out = {
+        "panel_nz_ptr": P.panel_nz_ptr.cpu().numpy(),
+        "panel_col_ptr": P.panel_col_ptr.cpu().numpy(),
+        "col_ind": P.col_ind[: P.ncols].cpu().numpy(),
+        "col_nnz": P.col_nnz[: P.ncols].cpu().numpy(),
+        "col_ptr": P.col_ptr[: P.ncols + 1].cpu().numpy(),
+        "loc": P.loc[: P.nnz].cpu().numpy(),
+        "val": P.val[: P.nnz].cpu().numpy(),
+    }
+    if P.row_scale is not None:
+        out["row_scale"] = P.row_scale[: P.M].cpu().numpy()
+    return out
+
+
+def assert_pack_equal(P: ops.PackedMatrix, ref: O.Packed) -> None:
+    g = packed_to_np(P)
+    assert P.nnz == ref.nnz and P.ncols == ref.ncols
+    assert np.array_equal(g["panel_nz_ptr"], ref.panel_nz_ptr)
+    assert np.array_equal(g["panel_col_ptr"], ref.panel_col_ptr)
+    assert np.array_equal(g["col_ind"], ref.col_ind)
+    assert np.array_equal(g["col_nnz"], ref.col_nnz)
+    assert np.array_equal(g["col_ptr"], ref.col_ptr)
+    assert np.array_equal(g["loc"], ref.loc)
+    assert g["val"].tobytes() == ref.val.tobytes()
+    if ref.row_scale is not None:
+        assert g["row_scale"].tobytes() == ref.row_scale.tobytes()
+
+
+def err(C_hat, C_ref, scale) -> float:
+    return O.err_metric(np.asarray(C_hat, np.float64), C_ref, scale)

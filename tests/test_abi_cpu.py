@@ -1,0 +1,164 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+that include/rosko.h declares, and rejects bad arguments on the host with the
+documented status codes before any GPU work is enqueued."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2307_03930_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rosko.h")
+
+
+def setup_module(_m):
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2307_03930_amd import build
+        build.build()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rosko_\w+)\s*\(", text)))
+
+
+def test_header_declares_expected_calls():
+    names = declared_functions()
+    for n in ("rosko_pack", "rosko_pack_query", "rosko_pack_transpose", "rosko_spmm",
+              "rosko_spmm_backward", "rosko_pack_workspace_size", "rosko_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(L.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(declared_functions()) == set(L.SIGNATURES), "binding signatures out of date"
+
+
+def test_abi_version_and_status_strings():
+    lib = L.lib()
+    assert lib.rosko_abi_version() == 1
+    assert lib.rosko_status_str(L.ROSKO_EINVAL) == b"ROSKO_EINVAL"
+    assert lib.rosko_status_str(123) == b"ROSKO_UNKNOWN"
+
+
+def test_workspace_size_closed_form():
+    lib = L.lib()
+    n = C.c_size_t(0)
+    assert lib.rosko_pack_workspace_size(256, 2304, 32, 0, C.byref(n)) == 0
+    P, K = 8, 2304
+    NT = (P * K + 1023) // 1024
+    r = lambda x: (x + 255) // 256 * 256
+    assert n.value == r(4 * P * K) + 2 * r(16 * NT) + r(32)
+    assert lib.rosko_pack_workspace_size(256, 2304, 32, 1, C.byref(n)) == 0
+    P2 = (2304 + 31) // 32
+    NT2 = (P2 * 256 + 1023) // 1024
+    assert n.value == r(4 * P2 * 256) + 2 * r(16 * NT2) + r(32) + r(4 * 256 * 2304)
+
+
+@pytest.mark.parametrize("mr", [0, -1, 257])
+def test_bad_mr_rejected(mr):
+    n = C.c_size_t(0)
+    assert L.lib().rosko_pack_workspace_size(10, 10, mr, 0, C.byref(n)) == L.ROSKO_EINVAL
+    assert b"mr" in L.lib().rosko_last_error()
+
+
+def test_query_argument_checks():
+    lib = L.lib()
+    nnz, nc = C.c_int64(0), C.c_int64(0)
+    fake = C.c_void_p(0x1000)   # never dereferenced: every call below fails its checks first
+    # negative size
+    assert lib.rosko_pack_query(fake, -1, 4, 4, 8, fake, 1 << 20, None, C.byref(nnz),
+                                C.byref(nc)) == L.ROSKO_EINVAL
+    # lda < K
+    assert lib.rosko_pack_query(fake, 4, 8, 4, 8, fake, 1 << 20, None, C.byref(nnz),
+                                C.byref(nc)) == L.ROSKO_EINVAL
+    # null matrix with nonzero size
+    assert lib.rosko_pack_query(None, 4, 4, 4, 8, fake, 1 << 20, None, C.byref(nnz),
+                                C.byref(nc)) == L.ROSKO_EINVAL
+    # workspace too small
+    assert lib.rosko_pack_query(fake, 4, 4, 4, 8, fake, 1, None, C.byref(nnz),
+                                C.byref(nc)) == L.ROSKO_ESMALLBUF
+    # null outputs
+    assert lib.rosko_pack_query(fake, 4, 4, 4, 8, fake, 1 << 20, None, None,
+                                None) == L.ROSKO_EINVAL
+
+
+def _packed(M, K, mr, dtype=L.ROSKO_F32, fill=True):
+    s = L.RoskoPacked()
+    s.M, s.K, s.mr, s.n_panels, s.val_dtype = M, K, mr, (M + mr - 1) // mr, dtype
+    s.nnz_cap, s.ncols_cap = 10, 10
+    if fill:
+        for f in ("panel_nz_ptr", "panel_col_ptr", "col_ind", "col_nnz", "col_ptr", "loc",
+                  "val", "row_scale"):
+            setattr(s, f, 0x1000)
+    return s
+
+
+def test_pack_argument_checks():
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)
+    s = _packed(8, 8, 4)
+    # shape mismatch between arguments and output struct
+    assert lib.rosko_pack(fake, 8, 9, 9, 4, L.ROSKO_F32, fake, 1 << 20, C.byref(s),
+                          None) == L.ROSKO_EINVAL
+    # unsupported value dtype
+    assert lib.rosko_pack(fake, 8, 8, 8, 4, 7, fake, 1 << 20, C.byref(s),
+                          None) == L.ROSKO_EUNSUPPORTED
+    # FP8 without row_scale
+    s2 = _packed(8, 8, 4)
+    s2.row_scale = None
+    assert lib.rosko_pack(fake, 8, 8, 8, 4, L.ROSKO_FP8_E4M3, fake, 1 << 20, C.byref(s2),
+                          None) == L.ROSKO_EINVAL
+    # null value arrays with nonzero capacity
+    s3 = _packed(8, 8, 4)
+    s3.val = None
+    assert lib.rosko_pack(fake, 8, 8, 8, 4, L.ROSKO_F32, fake, 1 << 20, C.byref(s3),
+                          None) == L.ROSKO_EINVAL
+    # transpose packing wants the K x M shape
+    s4 = _packed(8, 6, 4)
+    assert lib.rosko_pack_transpose(fake, 8, 6, 6, 4, L.ROSKO_F32, fake, 1 << 20, C.byref(s4),
+                                    None) == L.ROSKO_EINVAL
+
+
+def test_spmm_argument_checks():
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)
+    s = _packed(8, 8, 4)
+    # bad beta, bad ldb/ldc, bad B dtype, wrong n_panels, bad plan tile
+    assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 16, fake, 16, 2, None,
+                          None) == L.ROSKO_EINVAL
+    assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 8, fake, 16, 0, None,
+                          None) == L.ROSKO_EINVAL
+    assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 16, fake, 15, 0, None,
+                          None) == L.ROSKO_EINVAL
+    assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_FP8_E4M3, 16, 16, fake, 16, 0, None,
+                          None) == L.ROSKO_EUNSUPPORTED
+    s.n_panels = 5
+    assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 16, fake, 16, 0, None,
+                          None) == L.ROSKO_EINVAL
+    s = _packed(8, 8, 4)
+    plan = L.RoskoPlan()
+    plan.path, plan.cols_per_lane, plan.waves = 5, 4, 2
+    assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 16, fake, 16, 0, C.byref(plan),
+                          None) == L.ROSKO_EUNSUPPORTED
+    # empty problems are valid no-ops and touch no memory
+    s0 = _packed(0, 8, 4)
+    assert lib.rosko_spmm(C.byref(s0), fake, L.ROSKO_F32, 16, 16, fake, 16, 0, None,
+                          None) == L.ROSKO_OK
+
+
+def test_backward_argument_checks():
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)
+    s = _packed(8, 6, 4)
+    st = _packed(8, 6, 4)   # wrong: must be 6 x 8
+    assert lib.rosko_spmm_backward(C.byref(s), C.byref(st), fake, 16, fake, 16, 16, fake, 16,
+                                   None, None) == L.ROSKO_EINVAL
+    st = _packed(6, 8, 4, dtype=L.ROSKO_BF16)
+    assert lib.rosko_spmm_backward(C.byref(s), C.byref(st), fake, 16, fake, 16, 16, fake, 16,
+                                   None, None) == L.ROSKO_EUNSUPPORTED

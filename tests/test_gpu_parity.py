@@ -1,0 +1,280 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Packing is compared bit for bit; FP32 SpMM within max |dC| / (|A||B|) <= 1e-5
+of the FP64 oracle; BF16-value results within 1e-2 of the oracle on the FP32
+source values (and within FP32 accumulation error of the oracle on the
+decoded values); FP8 results within the E4M3 bound 2^-4."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2307_03930_amd import ops, synth
+from tests.gpu_helpers import DT, assert_pack_equal, dev, err, packed_to_np, say
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+TOL_BF16 = 1e-2
+TOL_FP8 = 2.0 ** -4
+
+
+def setup_module(_m):
+    assert torch.cuda.is_available(), "GPU tests need the MI355X"
+    O.build(force=False)
+
+
+# --------------------------------------------------------------------------
+# packing: bit-exact against Alg. 1 in the oracle
+# --------------------------------------------------------------------------
+PACK_CASES = [
+    (77, 131, 0.1, "iid"), (512, 512, 0.1, "iid"), (300, 1000, 0.02, "row_clustered"),
+    (64, 2304, 0.3, "column_banded"), (1, 1, 1.0, "iid"), (1000, 3, 0.5, "iid"),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("mr", [1, 8, 13, 32, 64, 200])
+@pytest.mark.parametrize("case", PACK_CASES)
+def test_pack_bit_exact(case, mr, dtype):
+    M, K, d, kind = case
+    say(f"pack {M}x{K} d={d} {kind} mr={mr} {dtype}")
+    A = synth.sparse_matrix(M, K, d, 500 + M + K, kind)
+    P = ops.pack(dev(A), mr, dtype)
+    assert_pack_equal(P, O.pack(A, mr, DT[dtype]))
+
+
+def test_pack_special_values():
+    say("pack special values")
+    g = synth.rng(501)
+    A = synth.sparse_matrix(40, 70, 0.3, 502)
+    flat = A.reshape(-1)
+    idx = g.choice(flat.size, 40, replace=False)
+    specials = np.array([-0.0, np.nan, np.inf, -np.inf, 1e-45, -1e-45, 1e-39, 3.4e38,
+                         -3.4e38, 0.0], np.float32)
+    flat[idx] = np.resize(specials, 40)
+    for dtype in ("f32", "bf16"):
+        P = ops.pack(dev(A), 16, dtype)
+        assert_pack_equal(P, O.pack(A, 16, DT[dtype]))
+    # FP8 needs finite rows for a finite scale; check the specials that keep
+    # the scale finite (tiny values, signed zeros) bit for bit
+    A8 = synth.sparse_matrix(40, 70, 0.3, 503)
+    A8.reshape(-1)[idx] = np.resize(np.array([-0.0, 1e-45, -1e-45, 1e-39, -1e-30, 0.0],
+                                             np.float32), 40)
+    P = ops.pack(dev(A8), 16, "fp8")
+    assert_pack_equal(P, O.pack(A8, 16, O.FP8))
+
+
+@pytest.mark.parametrize("shape", [(0, 10), (10, 0), (0, 0), (33, 17)])
+def test_pack_empty(shape):
+    say(f"pack empty {shape}")
+    A = np.zeros(shape, np.float32)
+    P = ops.pack(dev(A) if A.size else torch.zeros(shape, dtype=torch.float32, device="cuda"),
+                 8)
+    ref = O.pack(A, 8)
+    assert P.nnz == 0 and P.ncols == 0
+    assert np.array_equal(packed_to_np(P)["panel_nz_ptr"], ref.panel_nz_ptr)
+
+
+@pytest.mark.parametrize("mr", [8, 32, 64])
+def test_pack_transpose_bit_exact(mr):
+    say(f"pack transpose mr={mr}")
+    A = synth.sparse_matrix(150, 333, 0.07, 504)
+    Pt = ops.pack_transpose(dev(A), mr)
+    assert_pack_equal(Pt, O.pack(np.ascontiguousarray(A.T), mr))
+
+
+def test_pack_deterministic():
+    say("pack determinism")
+    A = synth.sparse_matrix(700, 900, 0.05, 505)
+    a = packed_to_np(ops.pack(dev(A), 32, "bf16"))
+    b = packed_to_np(ops.pack(dev(A), 32, "bf16"))
+    for k in a:
+        assert a[k].tobytes() == b[k].tobytes()
+
+
+def test_pack_capacity_overflow_reported():
+    """Too-small buffers: the write pass drops the excess (never writes past
+    the capacities) and rosko_pack_result reports ROSKO_ESMALLBUF."""
+    import ctypes as C
+    from paper_2307_03930_amd import _lib as L
+    say("pack capacity overflow")
+    A = synth.sparse_matrix(64, 256, 0.2, 506)
+    Ad = dev(A)
+    nnz, ncols = ops.pack_query(Ad, 16)
+    P = ops._alloc(64, 256, 16, L.ROSKO_F32, nnz // 2, ncols // 2, Ad.device)
+    # sentinels just past the capacities (the arrays carry spare entries)
+    P.val[nnz // 2:] = 7.0
+    P.loc[nnz // 2:] = 7
+    ws = torch.empty(ops.workspace_size(64, 256, 16), dtype=torch.uint8, device="cuda")
+    st = P.struct()
+    L.check(L.lib().rosko_pack(C.c_void_p(Ad.data_ptr()), 64, 256, 256, 16, L.ROSKO_F32,
+                               C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(st),
+                               ops._stream_ptr()))
+    rc = L.lib().rosko_pack_result(C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(st),
+                                   ops._stream_ptr())
+    assert rc == L.ROSKO_ESMALLBUF
+    assert st.nnz == nnz and st.ncols == ncols
+    assert bool((P.val[nnz // 2:] == 7.0).all()) and bool((P.loc[nnz // 2:] == 7).all())
+    # the kept prefix is still the oracle's
+    ref = O.pack(A, 16)
+    got = P.val[: nnz // 2].cpu().numpy()
+    assert got.tobytes() == ref.val[: nnz // 2].tobytes()
+
+
+# --------------------------------------------------------------------------
+# SpMM, FP32
+# --------------------------------------------------------------------------
+PLANS = [(4, 1), (4, 2), (4, 4), (2, 1), (2, 2)]
+
+
+@pytest.mark.parametrize("plan", PLANS)
+def test_spmm_plain_512(plan):
+    """512 x 512 at 90% sparsity times 512 x 512 (the plain FP32 case)."""
+    V, W = plan
+    say(f"spmm plain-512 plan V={V} W={W}")
+    pr = synth.plain_512()
+    ref = O.spmm(pr.A, pr.B)
+    scale = O.abs_product(pr.A, pr.B)
+    P = ops.pack(dev(pr.A), 32, "f32")
+    C = ops.spmm(P, dev(pr.B), plan=ops.make_plan(V, W)).cpu().numpy()
+    e = err(C, ref, scale)
+    say(f"  err {e:.3e}")
+    assert e <= TOL_F32
+
+
+@pytest.mark.parametrize("mr,V", [(8, 4), (13, 4), (16, 4), (32, 4), (32, 2), (50, 2),
+                                  (64, 2), (100, 1), (128, 1)])
+@pytest.mark.parametrize("N", [1, 63, 190, 256, 700])
+def test_spmm_shapes_ragged(mr, V, N):
+    M, K = 77 + mr, 131
+    say(f"spmm ragged M={M} K={K} N={N} mr={mr} V={V}")
+    A = synth.sparse_matrix(M, K, 0.15, 600 + mr, "row_clustered")
+    B = synth.dense_normal(K, N, 601 + N)
+    ref = O.spmm(A, B)
+    scale = O.abs_product(A, B)
+    P = ops.pack(dev(A), mr, "f32")
+    for W in (1, 2, 4):
+        C = ops.spmm(P, dev(B), plan=ops.make_plan(V, W)).cpu().numpy()
+        assert err(C, ref, scale) <= TOL_F32, (W,)
+
+
+def test_spmm_beta_one_and_strides():
+    say("spmm beta=1 with padded leading dimensions")
+    A = synth.sparse_matrix(96, 200, 0.1, 602)
+    B = synth.dense_normal(200, 130, 603)
+    C0 = synth.dense_normal(96, 130, 604)
+    Bpad = np.zeros((200, 136), np.float32)
+    Bpad[:, :130] = B
+    Cpad = np.zeros((96, 140), np.float32)
+    Cpad[:, :130] = C0
+    P = ops.pack(dev(A), 32)
+    Bd = dev(Bpad)[:, :130]
+    Cd = dev(Cpad)
+    ops.spmm(P, Bd, Cd[:, :130], beta=1)
+    got = Cd.cpu().numpy()
+    ref = O.spmm(A, B) + C0.astype(np.float64)
+    scale = O.abs_product(A, B) + np.abs(C0)
+    assert err(got[:, :130], ref, scale) <= TOL_F32
+    assert not got[:, 130:].any()   # padding untouched
+
+
+def test_spmm_identity_exact_and_zero():
+    say("spmm identity / zero / K=0")
+    B = synth.dense_normal(64, 100, 605)
+    I = np.eye(64, dtype=np.float32)
+    C = ops.spmm(ops.pack(dev(I), 32), dev(B)).cpu().numpy()
+    assert np.array_equal(C, B)
+    Z = np.zeros((40, 64), np.float32)
+    C = ops.spmm(ops.pack(dev(Z), 16), dev(B)).cpu().numpy()
+    assert not C.any()
+    A0 = torch.zeros((40, 0), dtype=torch.float32, device="cuda")
+    P0 = ops.pack(A0, 16)
+    B0 = torch.zeros((0, 50), dtype=torch.float32, device="cuda")
+    C = ops.spmm(P0, B0).cpu().numpy()
+    assert C.shape == (40, 50) and not C.any()
+
+
+def test_spmm_zero_sparsity_matches_dense():
+    say("spmm 0% sparsity vs dense")
+    A = synth.dense_normal(128, 300, 606)
+    B = synth.dense_normal(300, 256, 607)
+    ref = O.dense_mm(A, B)
+    scale = O.abs_product(A, B)
+    C = ops.spmm(ops.pack(dev(A), 32), dev(B)).cpu().numpy()
+    assert err(C, ref, scale) <= TOL_F32
+
+
+def test_spmm_deterministic():
+    say("spmm determinism")
+    A = synth.sparse_matrix(256, 2304, 0.1, 608)
+    B = synth.dense_normal(2304, 512, 609)
+    P = ops.pack(dev(A), 32)
+    Bd = dev(B)
+    for W in (1, 2, 4):
+        c1 = ops.spmm(P, Bd, plan=ops.make_plan(4, W)).cpu().numpy()
+        c2 = ops.spmm(P, Bd, plan=ops.make_plan(4, W)).cpu().numpy()
+        assert c1.tobytes() == c2.tobytes()
+
+
+@pytest.mark.parametrize("s", synth.CNN_SPARSITIES)
+def test_spmm_cnn_layer_sampled(s):
+    """256 x 2304 magnitude-pruned weights times the 2304 x 3136 im2col
+    activations, full size on the GPU; 24 sampled rows of C checked."""
+    say(f"spmm cnn layer s={s}")
+    pr = synth.cnn_layer(s)
+    rows = np.sort(synth.rng(610).choice(256, 24, replace=False))
+    ref = O.spmm(pr.A[rows], pr.B)
+    scale = O.abs_product(pr.A[rows], pr.B)
+    P = ops.pack(dev(pr.A), 32)
+    Bd = dev(pr.B)
+    for V, W in ((4, 1), (4, 2), (2, 2)):
+        C = ops.spmm(P, Bd, plan=ops.make_plan(V, W))
+        e = err(C.cpu().numpy()[rows], ref, scale)
+        say(f"  V={V} W={W} err {e:.3e}")
+        assert e <= TOL_F32
+
+
+# --------------------------------------------------------------------------
+# precision forms
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+@pytest.mark.parametrize("b_bf16", [False, True])
+def test_spmm_quantised_values(dtype, b_bf16):
+    say(f"spmm values={dtype} B bf16={b_bf16}")
+    A = synth.sparse_matrix(200, 500, 0.1, 611)
+    B = synth.dense_normal(500, 384, 612)
+    if b_bf16:
+        B = synth.bf16_representable(B)
+    opk = O.pack(A, 32, DT[dtype])
+    c_deq = O.spmm_packed(opk, B)
+    scale_deq = np.abs(O.unpack(opk)) @ np.abs(B).astype(np.float64)
+    c_src = O.spmm(A, B)
+    scale = O.abs_product(A, B)
+    P = ops.pack(dev(A), 32, dtype)
+    Bd = dev(B).to(torch.bfloat16) if b_bf16 else dev(B)
+    C = ops.spmm(P, Bd).cpu().numpy()
+    e_deq, e_src = err(C, c_deq, scale_deq), err(C, c_src, scale)
+    say(f"  err vs decoded {e_deq:.3e}, vs FP32 source {e_src:.3e}")
+    assert e_deq <= TOL_F32
+    assert e_src <= (TOL_BF16 if dtype == "bf16" else TOL_FP8)
+
+
+@pytest.mark.parametrize("s", [0.90, 0.98])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_spmm_precision_form_sampled(s, dtype):
+    """4096 x 4096 at 90/98% times 4096 x 2048 BF16 activations, full size on
+    the GPU; 16 sampled rows checked against the oracle."""
+    say(f"spmm precision form s={s} values={dtype}")
+    pr = synth.precision_problem(s)
+    rows = np.sort(synth.rng(613).choice(4096, 16, replace=False))
+    Arows = pr.A[rows]
+    c_src = O.spmm(Arows, pr.B)
+    scale = O.abs_product(Arows, pr.B)
+    P = ops.pack(dev(pr.A), 32, dtype)
+    Bd = dev(pr.B).to(torch.bfloat16) if dtype != "f32" else dev(pr.B)
+    C = ops.spmm(P, Bd).cpu().numpy()[rows]
+    e = err(C, c_src, scale)
+    say(f"  err vs FP32 source {e:.3e}")
+    tol = {"f32": TOL_F32, "bf16": TOL_BF16, "fp8": TOL_FP8}[dtype]
+    assert e <= tol
