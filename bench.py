@@ -77,7 +77,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip cold/dense timings")
     ap.add_argument("--cols-per-lane", type=int, default=None)
-    ap.add_argument("--waves", type=int, default=None)
+    ap.add_argument("--panels-per-wg", type=int, default=None)
+    ap.add_argument("--k-split", type=int, default=None)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -98,24 +99,26 @@ def main():
     N = B_np.shape[1]
     B = torch.from_numpy(B_np).to(dev)
     As = [torch.from_numpy(a).to(dev) for a in As_np]
-    plan = ops.make_plan(args.cols_per_lane, args.waves)
+    plan = ops.make_plan(args.cols_per_lane, args.panels_per_wg, args.k_split)
 
     # buffers sized once (the sizing query synchronises; the step does not)
-    packs, wss, Cs = [], [], []
+    packs, wss, Cs, sws = [], [], [], []
     for A in As:
         P = ops.pack(A, MR, "f32")
         packs.append(P)
         wss.append(torch.empty(max(ops.workspace_size(M, K, MR), 1), dtype=torch.uint8,
                                device=dev))
         Cs.append(torch.empty((M, N), dtype=torch.float32, device=dev))
+        sws.append(torch.empty(max(ops.spmm_workspace_size(P, N, plan), 1), dtype=torch.uint8,
+                               device=dev))
     nnzs = [P.nnz for P in packs]
     ncolss = [P.ncols for P in packs]
     k_touched = [int((a != 0).any(axis=0).sum()) for a in As_np]
 
     def step():
-        for A, P, ws, C in zip(As, packs, wss, Cs):
+        for A, P, ws, C, sw in zip(As, packs, wss, Cs, sws):
             ops.pack_into(A, P, ws)
-            ops.spmm(P, B, C, plan=plan)
+            ops.spmm(P, B, C, plan=plan, ws=sw)
 
     for _ in range(args.warmup):
         step()
@@ -134,14 +137,14 @@ def main():
     P_panels = (M + MR - 1) // MR
     per = []
     tot_bytes, tot_ms = 0.0, 0.0
-    for s, P, C, nnz, nc, kt in zip(sparsities, packs, Cs, nnzs, ncolss, k_touched):
+    for s, P, C, sw, nnz, nc, kt in zip(sparsities, packs, Cs, sws, nnzs, ncolss, k_touched):
         for _ in range(3):
-            ops.spmm(P, B, C, plan=plan)
+            ops.spmm(P, B, C, plan=plan, ws=sw)
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         for _ in range(args.reps):
-            ops.spmm(P, B, C, plan=plan)
+            ops.spmm(P, B, C, plan=plan, ws=sw)
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / args.reps
@@ -172,13 +175,13 @@ def main():
             rec["speedup_vs_dense"] = round(dense_us / rec["spmm_us"], 2)
         # cold-cache SpMM: overwrite 512 MB between trials
         flush = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
-        for rec, P, C in zip(per, packs, Cs):
+        for rec, P, C, sw in zip(per, packs, Cs, sws):
             ts = []
             for _ in range(10):
                 flush.fill_(1.0)
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record()
-                ops.spmm(P, B, C, plan=plan)
+                ops.spmm(P, B, C, plan=plan, ws=sw)
                 b.record()
                 torch.cuda.synchronize()
                 ts.append(a.elapsed_time(b) * 1e3)

@@ -73,6 +73,11 @@ extern "C" {
  *   loc      [nnz]     uint8   row of the value inside its panel (loc_m)
  *   val      [nnz]     4, 2 or 1 bytes per value by val_dtype (A_p)
  *   row_scale[M]       float   s_m for ROSKO_FP8_E4M3, otherwise unused (may be NULL)
+ *   kblk_ptr [n_panels * ceil(K / ROSKO_KSTEP)] int64
+ *                              slot of the first kept column of panel p with
+ *                              k >= j * ROSKO_KSTEP (the panel's end slot if
+ *                              none), at [p * ceil(K / ROSKO_KSTEP) + j]; lets
+ *                              a workgroup start a K range inside a panel
  * nnz_cap and ncols_cap are the capacities of the caller's buffers
  * (col_ptr must hold ncols_cap+1 entries).  rosko_spmm reads values in
  * batches of 8 and row bytes by aligned dwords, so val and loc must stay
@@ -80,6 +85,7 @@ extern "C" {
  * ROSKO_READ_SLACK entries); the extra entries are never used.  nnz and ncols are written by
  * rosko_pack_query / rosko_pack_result on the host side only. */
 #define ROSKO_READ_SLACK 64
+#define ROSKO_KSTEP 128
 typedef struct rosko_packed {
   int64_t M, K;
   int32_t mr;          /* panel height, 1..256 */
@@ -96,27 +102,33 @@ typedef struct rosko_packed {
   uint8_t *loc;
   void *val;
   float *row_scale;
+  int64_t *kblk_ptr;
 } rosko_packed;
 
 /* ---- execution plan for rosko_spmm ----------------------------------
- * path:  ROSKO_PATH_SPARSE  row-skipping vector kernel
- *        ROSKO_PATH_AUTO    let the library choose
- * cols_per_lane: B/C columns each of the 64 lanes of a wavefront covers;
- *        a wavefront covers 64*cols_per_lane columns.  The register tile
- *        (panel height rounded up to 8/16/32/64/128, times cols_per_lane)
- *        must be one of 8x4, 16x4, 32x4, 32x2, 64x2, 128x1; other pairs
- *        return ROSKO_EUNSUPPORTED.  Panel heights above 128 are packed but
- *        not multiplied by this path.
- * waves: wavefronts per workgroup splitting one panel's kept columns (1, 2
- *        or 4); their partial tiles are summed on chip in a fixed order, so
- *        results do not depend on timing.  */
+ * A workgroup holds `panels_per_wg` panels (one wavefront each, with its C
+ * tile in VGPRs) and one chunk of 64*cols_per_lane columns; it stages the B
+ * rows of its K range through LDS in blocks shared by its panels.  K is cut
+ * into `k_split` ranges (on ROSKO_KSTEP boundaries) handled by different
+ * workgroups; with k_split > 1 their partial tiles go to the workspace and a
+ * second kernel adds them in a fixed order (so results do not depend on
+ * timing) and applies the FP8 row scale and beta.
+ * path:          ROSKO_PATH_SPARSE (row-skipping vector kernel), or
+ *                ROSKO_PATH_AUTO to let the library choose everything.
+ * cols_per_lane: 1, 2 or 4.  The register tile (panel height rounded up to
+ *                8/16/32/64/128, times cols_per_lane) must be one of 8x4,
+ *                16x4, 32x4, 32x2, 64x2, 128x1; other pairs return
+ *                ROSKO_EUNSUPPORTED.  Panel heights above 128 are packed but
+ *                not multiplied by this path.
+ * panels_per_wg: 1, 2, 4 or 8.
+ * k_split:       1 .. ceil(K / ROSKO_KSTEP) (larger values are clamped).  */
 #define ROSKO_PATH_AUTO (-1)
 #define ROSKO_PATH_SPARSE 0
 typedef struct rosko_plan {
   int32_t path;
   int32_t cols_per_lane;
-  int32_t waves;
-  int32_t reserved;
+  int32_t panels_per_wg;
+  int32_t k_split;
 } rosko_plan;
 
 /* ---- packing (Alg. 1, Sec. 4.1) --------------------------------------- */
@@ -163,14 +175,22 @@ int32_t rosko_pack_result(const void *ws, size_t ws_bytes, rosko_packed *packed,
 
 /* ---- SpMM (Alg. 2) ------------------------------------------------------ */
 
+/* Device workspace bytes rosko_spmm needs for A (only its shape and mr are
+ * read), N columns and `plan` (NULL = the automatic plan): 4*k_split*M*N
+ * when k_split > 1, else 0. */
+int32_t rosko_spmm_workspace_size(const rosko_packed *A, int64_t N, const rosko_plan *plan,
+                                  size_t *bytes);
+
 /* C = A*B (beta = 0) or C += A*B (beta = 1), with A packed, B (device,
  * A->K x N, row-major, ldb >= N) in FP32 (b_dtype ROSKO_F32) or BF16
  * (ROSKO_BF16, raw 16-bit patterns), C (device, A->M x N FP32, ldc >= N).
  * Accumulation is FP32; FP8 values are multiplied by s_m once per output.
- * plan may be NULL (automatic).  Asynchronous. */
+ * plan may be NULL (automatic).  ws (device) must hold the bytes
+ * rosko_spmm_workspace_size reports for the same plan (may be NULL when that
+ * is 0).  Asynchronous. */
 int32_t rosko_spmm(const rosko_packed *A, const void *B, int32_t b_dtype, int64_t N,
                    int64_t ldb, float *C, int64_t ldc, int32_t beta, const rosko_plan *plan,
-                   void *stream);
+                   void *ws, size_t ws_bytes, void *stream);
 
 /* ---- backward of C = A*B (training decomposition, Sec. 5.4) ------------
  * dB = A^T dC, computed as a Rosko SpMM over At, the packed transpose of A
@@ -179,10 +199,13 @@ int32_t rosko_spmm(const rosko_packed *A, const void *B, int32_t b_dtype, int64_
  * order (an SDDMM; pruned entries get no gradient).  dC (device, A->M x N,
  * lddc), B (device FP32, A->K x N, ldb).  dB (device, A->K x N, lddb) or
  * dA_val (device, A's nnz floats) may be NULL to skip that gradient; At may
- * be NULL when dB is.  Asynchronous. */
+ * be NULL when dB is.  ws: device workspace of the size
+ * rosko_spmm_backward_workspace_size reports.  Asynchronous. */
+int32_t rosko_spmm_backward_workspace_size(const rosko_packed *At, int64_t N, size_t *bytes);
 int32_t rosko_spmm_backward(const rosko_packed *A, const rosko_packed *At, const float *B,
                             int64_t ldb, const float *dC, int64_t lddc, int64_t N, float *dB,
-                            int64_t lddb, float *dA_val, void *stream);
+                            int64_t lddb, float *dA_val, void *ws, size_t ws_bytes,
+                            void *stream);
 
 /* ---- errors ----------------------------------------------------------- */
 const char *rosko_status_str(int32_t status);

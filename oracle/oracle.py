@@ -65,6 +65,7 @@ def lib():
         L.ro_grad_dA_packed.argtypes = [i64, i32, p, p, p, p, p, p, i64, p, i64, i64, p]
         L.ro_grad_dA_packed.restype = None
         L.ro_max_threads.argtypes = []; L.ro_max_threads.restype = i32
+        L.ro_kblk_ptr.argtypes = [i64, i64, i32, i32, p, p, p]; L.ro_kblk_ptr.restype = None
         _lib = L
     return _lib
 
@@ -157,6 +158,17 @@ def pack(A: np.ndarray, mr: int, dtype: int = F32) -> Packed:
                   _ptr(cp), _ptr(loc), _ptr(val), _ptr(rs))
     return Packed(M, K, mr, dtype, pnz, pcol, ci[:ncols], cn[:ncols], cp, loc[:nnz], val[:nnz],
                   None if rs is None else rs[:M])
+
+
+KSTEP = 128   # K-block width of the derived kblk_ptr index
+
+
+def kblk_ptr(pk: Packed, kstep: int = KSTEP) -> np.ndarray:
+    nkb = (pk.K + kstep - 1) // kstep
+    out = np.zeros(max(pk.n_panels * nkb, 1), np.int64)
+    lib().ro_kblk_ptr(pk.M, pk.K, pk.mr, kstep, _ptr(pk.panel_col_ptr), _ptr(pk.col_ind),
+                      _ptr(out))
+    return out[:pk.n_panels * nkb]
 
 
 def unpack(pk: Packed) -> np.ndarray:

@@ -199,6 +199,23 @@ void ro_pack(const float *A, int64_t M, int64_t K, int64_t lda, int32_t mr, int3
   col_ptr[i2] = i1;
 }
 
+/* Derived column index per K block of KSTEP columns: kblk_ptr[p*nkb + j]
+ * is the slot of the first kept column of panel p with k >= j*KSTEP (the
+ * panel's end slot if there is none), for j < nkb = ceil(K / KSTEP).  A
+ * plain scan of the panel's column list. */
+void ro_kblk_ptr(int64_t M, int64_t K, int32_t mr, int32_t kstep,
+                 const int64_t *panel_col_ptr, const int32_t *col_ind, int64_t *kblk_ptr) {
+  int64_t P = (M + mr - 1) / mr;
+  int64_t nkb = (K + kstep - 1) / kstep;
+  for (int64_t p = 0; p < P; ++p) {
+    for (int64_t j = 0; j < nkb; ++j) {
+      int64_t c = panel_col_ptr[p];
+      while (c < panel_col_ptr[p + 1] && col_ind[c] < j * kstep) ++c;
+      kblk_ptr[p * nkb + j] = c;
+    }
+  }
+}
+
 /* Decoded value of packed entry z as a double. */
 static double packed_value(int32_t dtype, const void *val, const float *row_scale,
                            int64_t row, int64_t z) {

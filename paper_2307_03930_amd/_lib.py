@@ -24,6 +24,8 @@ ROSKO_FP8_E4M3 = 2
 
 ROSKO_PATH_AUTO = -1
 ROSKO_PATH_SPARSE = 0
+ROSKO_KSTEP = 128
+ROSKO_READ_SLACK = 64
 
 
 class RoskoPacked(C.Structure):
@@ -36,12 +38,13 @@ class RoskoPacked(C.Structure):
         ("panel_nz_ptr", C.c_void_p), ("panel_col_ptr", C.c_void_p),
         ("col_ind", C.c_void_p), ("col_nnz", C.c_void_p), ("col_ptr", C.c_void_p),
         ("loc", C.c_void_p), ("val", C.c_void_p), ("row_scale", C.c_void_p),
+        ("kblk_ptr", C.c_void_p),
     ]
 
 
 class RoskoPlan(C.Structure):
     _fields_ = [("path", C.c_int32), ("cols_per_lane", C.c_int32),
-                ("waves", C.c_int32), ("reserved", C.c_int32)]
+                ("panels_per_wg", C.c_int32), ("k_split", C.c_int32)]
 
 
 class RoskoError(RuntimeError):
@@ -72,10 +75,14 @@ SIGNATURES = {
     "rosko_pack_transpose": (_I32, [_P, _I64, _I64, _I64, _I32, _I32, _P, _SZ,
                                     C.POINTER(RoskoPacked), _P]),
     "rosko_pack_result": (_I32, [_P, _SZ, C.POINTER(RoskoPacked), _P]),
+    "rosko_spmm_workspace_size": (_I32, [C.POINTER(RoskoPacked), _I64, C.POINTER(RoskoPlan),
+                                         C.POINTER(_SZ)]),
     "rosko_spmm": (_I32, [C.POINTER(RoskoPacked), _P, _I32, _I64, _I64, _P, _I64, _I32,
-                          C.POINTER(RoskoPlan), _P]),
+                          C.POINTER(RoskoPlan), _P, _SZ, _P]),
+    "rosko_spmm_backward_workspace_size": (_I32, [C.POINTER(RoskoPacked), _I64,
+                                                  C.POINTER(_SZ)]),
     "rosko_spmm_backward": (_I32, [C.POINTER(RoskoPacked), C.POINTER(RoskoPacked), _P, _I64,
-                                   _P, _I64, _I64, _P, _I64, _P, _P]),
+                                   _P, _I64, _I64, _P, _I64, _P, _P, _SZ, _P]),
     "rosko_status_str": (C.c_char_p, [_I32]),
     "rosko_last_error": (C.c_char_p, []),
     "rosko_abi_version": (_I32, []),

@@ -61,6 +61,7 @@ static int32_t check_packed_for_write(const rosko_packed* out, int64_t R, int64_
              "packed value arrays are null");
   RK_REQUIRE(dt != ROSKO_FP8_E4M3 || R == 0 || out->row_scale, ROSKO_EINVAL,
              "FP8 packing needs row_scale");
+  RK_REQUIRE(R == 0 || S == 0 || out->kblk_ptr, ROSKO_EINVAL, "kblk_ptr is null");
   return ROSKO_OK;
 }
 
@@ -83,6 +84,7 @@ static int32_t check_packed_for_read(const rosko_packed* A) {
              "packed value arrays are null");
   RK_REQUIRE(A->val_dtype != ROSKO_FP8_E4M3 || A->M == 0 || A->row_scale, ROSKO_EINVAL,
              "FP8 values need row_scale");
+  RK_REQUIRE(A->M == 0 || A->K == 0 || A->kblk_ptr, ROSKO_EINVAL, "kblk_ptr is null");
   return ROSKO_OK;
 }
 
@@ -237,23 +239,22 @@ int32_t rosko_pack_result(const void* ws, size_t ws_bytes, rosko_packed* packed,
   return ROSKO_OK;
 }
 
-// Default plan (the analytic fallback): the widest register tile the panel
-// height allows -- 128 accumulators per lane -- and two wavefronts
-// splitting each panel's kept columns.
-static rosko_plan default_plan(const rosko_packed* A, int64_t N) {
-  rosko_plan p{};
-  p.path = ROSKO_PATH_SPARSE;
-  if (A->mr <= 32) p.cols_per_lane = 4;
-  else if (A->mr <= 64) p.cols_per_lane = 2;
-  else p.cols_per_lane = 1;
-  if (A->mr > 16 && A->mr <= 32 && N <= 128) p.cols_per_lane = 2;
-  p.waves = 2;
-  return p;
+int32_t rosko_spmm_workspace_size(const rosko_packed* A, int64_t N, const rosko_plan* plan,
+                                  size_t* bytes) {
+  clear_error();
+  RK_REQUIRE(A != nullptr && bytes != nullptr, ROSKO_EINVAL, "null argument");
+  RK_REQUIRE(A->M >= 0 && A->K >= 0 && N >= 0, ROSKO_EINVAL, "negative size");
+  int32_t st = check_mr(A->mr);
+  if (st) return st;
+  rosko_plan p = plan ? *plan : auto_plan(A, N);
+  if ((st = normalize_plan(A, N, &p))) return st;
+  *bytes = spmm_ws_bytes(A, N, p);
+  return ROSKO_OK;
 }
 
 int32_t rosko_spmm(const rosko_packed* A, const void* B, int32_t b_dtype, int64_t N,
                    int64_t ldb, float* C, int64_t ldc, int32_t beta, const rosko_plan* plan,
-                   void* stream) {
+                   void* ws, size_t ws_bytes, void* stream) {
   clear_error();
   int32_t st = check_packed_for_read(A);
   if (st) return st;
@@ -267,18 +268,31 @@ int32_t rosko_spmm(const rosko_packed* A, const void* B, int32_t b_dtype, int64_
   RK_REQUIRE(beta == 0 || beta == 1, ROSKO_EINVAL, "beta must be 0 or 1");
   RK_REQUIRE(B != nullptr || A->K == 0 || N == 0, ROSKO_EINVAL, "B is null");
   RK_REQUIRE(C != nullptr || A->M == 0 || N == 0, ROSKO_EINVAL, "C is null");
+  rosko_plan p = plan ? *plan : auto_plan(A, N);
+  if ((st = normalize_plan(A, N, &p))) return st;
   if (A->M == 0 || N == 0) return ROSKO_OK;
-  rosko_plan p = (plan && plan->path != ROSKO_PATH_AUTO) ? *plan : default_plan(A, N);
-  RK_REQUIRE(p.path == ROSKO_PATH_SPARSE, ROSKO_EUNSUPPORTED, "plan path %d not supported",
-             p.path);
   (void)hipGetLastError();
-  return launch_spmm_sparse(A, B, b_dtype, N, ldb, C, ldc, beta, p,
-                            static_cast<hipStream_t>(stream));
+  return launch_spmm_sparse(A, B, b_dtype, N, ldb, C, ldc, beta, p, static_cast<float*>(ws),
+                            ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int32_t rosko_spmm_backward_workspace_size(const rosko_packed* At, int64_t N, size_t* bytes) {
+  clear_error();
+  RK_REQUIRE(bytes != nullptr, ROSKO_EINVAL, "bytes is null");
+  *bytes = 0;
+  if (At == nullptr) return ROSKO_OK;
+  RK_REQUIRE(At->M >= 0 && At->K >= 0 && N >= 0, ROSKO_EINVAL, "negative size");
+  int32_t st = check_mr(At->mr);
+  if (st) return st;
+  rosko_plan p = auto_plan(At, N);
+  *bytes = spmm_ws_bytes(At, N, p);
+  return ROSKO_OK;
 }
 
 int32_t rosko_spmm_backward(const rosko_packed* A, const rosko_packed* At, const float* B,
                             int64_t ldb, const float* dC, int64_t lddc, int64_t N, float* dB,
-                            int64_t lddb, float* dA_val, void* stream) {
+                            int64_t lddb, float* dA_val, void* ws, size_t ws_bytes,
+                            void* stream) {
   clear_error();
   int32_t st = check_packed_for_read(A);
   if (st) return st;
@@ -294,9 +308,11 @@ int32_t rosko_spmm_backward(const rosko_packed* A, const rosko_packed* At, const
     RK_REQUIRE(At->val_dtype == ROSKO_F32, ROSKO_EUNSUPPORTED, "At must hold FP32 values");
     RK_REQUIRE(lddb >= N && lddb >= 1, ROSKO_EINVAL, "lddb < N");
     if (At->M > 0 && N > 0) {
-      rosko_plan p = default_plan(At, N);
+      rosko_plan p = auto_plan(At, N);
       (void)hipGetLastError();
-      if ((st = launch_spmm_sparse(At, dC, ROSKO_F32, N, lddc, dB, lddb, 0, p, s))) return st;
+      if ((st = launch_spmm_sparse(At, dC, ROSKO_F32, N, lddc, dB, lddb, 0, p,
+                                   static_cast<float*>(ws), ws_bytes, s)))
+        return st;
     }
   }
   if (dA_val) {

@@ -73,25 +73,36 @@ struct SpmmArgs {
   const uint8_t* loc;
   const void* val;
   const float* row_scale;
+  const int64_t* kblk_ptr;
   const void* B;
   float* C;
-  int64_t M, N, ldb, ldc;
+  float* ws;           // k_split x M x N partial tiles (k_split > 1)
+  int64_t M, K, N, ldb, ldc;
+  int64_t n_chunks;    // ceil(N / (64 * cols_per_lane))
   int32_t mr, n_panels;
   int32_t beta;
-  int32_t vec;   // B/C rows allow V-wide vector access (alignment, N % V)
+  int32_t k_split;
+  int32_t vec;         // B/C rows allow V-wide vector access (alignment, N % V)
+  int32_t ws_vec;      // workspace rows allow V-wide vector access
 };
 // One dispatcher per (value dtype, B dtype); H = register-tile height,
-// V = columns per lane, W = waves per workgroup.
-int32_t spmm_dispatch_f32_f32(const SpmmArgs& g, int H, int V, int W, hipStream_t s);
-int32_t spmm_dispatch_f32_bf16(const SpmmArgs& g, int H, int V, int W, hipStream_t s);
-int32_t spmm_dispatch_bf16_f32(const SpmmArgs& g, int H, int V, int W, hipStream_t s);
-int32_t spmm_dispatch_bf16_bf16(const SpmmArgs& g, int H, int V, int W, hipStream_t s);
-int32_t spmm_dispatch_fp8_f32(const SpmmArgs& g, int H, int V, int W, hipStream_t s);
-int32_t spmm_dispatch_fp8_bf16(const SpmmArgs& g, int H, int V, int W, hipStream_t s);
+// V = columns per lane, G = panels (wavefronts) per workgroup.
+int32_t spmm_dispatch_f32_f32(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
+int32_t spmm_dispatch_f32_bf16(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
+int32_t spmm_dispatch_bf16_f32(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
+int32_t spmm_dispatch_bf16_bf16(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
+int32_t spmm_dispatch_fp8_f32(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
+int32_t spmm_dispatch_fp8_bf16(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
+
+// Plan helpers (spmm.hip): the automatic plan, validation/normalisation of a
+// caller's plan, and the workspace a plan needs.
+rosko_plan auto_plan(const rosko_packed* A, int64_t N);
+int32_t normalize_plan(const rosko_packed* A, int64_t N, rosko_plan* p);
+size_t spmm_ws_bytes(const rosko_packed* A, int64_t N, const rosko_plan& p);
 
 int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype, int64_t N,
                            int64_t ldb, float* C, int64_t ldc, int32_t beta,
-                           const rosko_plan& plan, hipStream_t s);
+                           const rosko_plan& plan, float* ws, size_t ws_bytes, hipStream_t s);
 int32_t launch_fill_zero(float* C, int64_t M, int64_t N, int64_t ldc, hipStream_t s);
 
 // ---------------------------------------------------------------- SDDMM

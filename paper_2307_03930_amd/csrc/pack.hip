@@ -173,8 +173,9 @@ k_pack_write(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
              int64_t* __restrict__ panel_col_ptr, int32_t* __restrict__ col_ind,
              int32_t* __restrict__ col_nnz, int64_t* __restrict__ col_ptr,
              uint8_t* __restrict__ loc, void* __restrict__ val,
-             const float* __restrict__ row_scale) {
+             const float* __restrict__ row_scale, int64_t* __restrict__ kblk_ptr) {
   const int64_t total = P * S;
+  const int64_t nkb = (S + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
   const int64_t f0 = (int64_t)blockIdx.x * kPackTile;
   Pair carry{tile_offs[2 * blockIdx.x], tile_offs[2 * blockIdx.x + 1]};
   // The tile is visited as four rows of 256 flattened indices; within a row
@@ -196,6 +197,9 @@ k_pack_write(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
       panel_nz_ptr[p] = nz_off;
       panel_col_ptr[p] = col_slot;
     }
+    // the exclusive column prefix at a block start is the first kept column
+    // of the panel with k >= that start (or the panel's end)
+    if (k % ROSKO_KSTEP == 0) kblk_ptr[p * nkb + k / ROSKO_KSTEP] = col_slot;
     if (c == 0) continue;
     if (col_slot < ncols_cap) {
       col_ind[col_slot] = (int32_t)k;
@@ -321,7 +325,7 @@ int32_t launch_pack_write(const float* A, int64_t R, int64_t S, int64_t lda, int
   hipLaunchKernelGGL(k_pack_write<DT>, dim3((unsigned)L.NT), dim3(kPackThreads), 0, s, A, R, \
                      S, lda, mr, L.P, counts, toff, out->nnz_cap, out->ncols_cap,            \
                      out->panel_nz_ptr, out->panel_col_ptr, out->col_ind, out->col_nnz,      \
-                     out->col_ptr, out->loc, out->val, out->row_scale)
+                     out->col_ptr, out->loc, out->val, out->row_scale, out->kblk_ptr)
   if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_F32);
   else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_BF16);
   else ROSKO_WRITE(ROSKO_FP8_E4M3);

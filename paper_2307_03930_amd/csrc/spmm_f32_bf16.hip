@@ -2,7 +2,7 @@
 #include "spmm_kernel.h"
 
 namespace rosko {
-int32_t spmm_dispatch_f32_bf16(const SpmmArgs& g, int H, int V, int W, hipStream_t s) {
-  return dispatch_tile<ROSKO_F32, ROSKO_BF16>(g, H, V, W, s);
+int32_t spmm_dispatch_f32_bf16(const SpmmArgs& g, int H, int V, int G, hipStream_t s) {
+  return dispatch_tile<ROSKO_F32, ROSKO_BF16>(g, H, V, G, s);
 }
 }  // namespace rosko

@@ -20,7 +20,7 @@ _VAL_TORCH = {L.ROSKO_F32: torch.float32, L.ROSKO_BF16: torch.int16,
               L.ROSKO_FP8_E4M3: torch.uint8}
 # reads of a column batch may run up to 8 values / 12 bytes past a column's
 # end, so value and row arrays carry this many spare entries
-SLACK = 64
+SLACK = L.ROSKO_READ_SLACK
 
 
 def _stream_ptr(stream=None) -> C.c_void_p:
@@ -56,6 +56,7 @@ class PackedMatrix:
     loc: torch.Tensor
     val: torch.Tensor
     row_scale: torch.Tensor | None
+    kblk_ptr: torch.Tensor
 
     @property
     def n_panels(self) -> int:
@@ -75,6 +76,7 @@ class PackedMatrix:
         s.loc = self.loc.data_ptr()
         s.val = self.val.data_ptr()
         s.row_scale = 0 if self.row_scale is None else self.row_scale.data_ptr()
+        s.kblk_ptr = self.kblk_ptr.data_ptr()
         return s
 
     def values(self) -> torch.Tensor:
@@ -109,6 +111,8 @@ def _alloc(M, K, mr, dtype, nnz, ncols, device):
         val=torch.zeros(nnz + SLACK, dtype=_VAL_TORCH[dtype], device=device),
         row_scale=(torch.empty(max(M, 1), dtype=torch.float32, device=device)
                    if dtype == L.ROSKO_FP8_E4M3 else None),
+        kblk_ptr=torch.empty(max(P * ((K + L.ROSKO_KSTEP - 1) // L.ROSKO_KSTEP), 1),
+                             dtype=i64, device=device),
     )
 
 
@@ -158,21 +162,32 @@ def pack_transpose(A: torch.Tensor, mr: int = 32) -> PackedMatrix:
     return P
 
 
-def make_plan(cols_per_lane: int | None = None, waves: int | None = None,
-              path: int = L.ROSKO_PATH_SPARSE) -> L.RoskoPlan | None:
-    if cols_per_lane is None and waves is None:
+def make_plan(cols_per_lane: int | None = None, panels_per_wg: int | None = None,
+              k_split: int | None = None, path: int = L.ROSKO_PATH_SPARSE):
+    """A rosko_plan; None (automatic) when nothing is given."""
+    if cols_per_lane is None and panels_per_wg is None and k_split is None:
         return None
     p = L.RoskoPlan()
     p.path = path
     p.cols_per_lane = cols_per_lane or 4
-    p.waves = waves or 2
+    p.panels_per_wg = panels_per_wg or 8
+    p.k_split = k_split or 1
     return p
 
 
+def spmm_workspace_size(P: PackedMatrix, N: int, plan=None) -> int:
+    n = C.c_size_t(0)
+    st = P.struct()
+    L.check(L.lib().rosko_spmm_workspace_size(C.byref(st), N,
+                                              C.byref(plan) if plan is not None else None,
+                                              C.byref(n)))
+    return int(n.value)
+
+
 def spmm(P: PackedMatrix, B: torch.Tensor, C_out: torch.Tensor | None = None, beta: int = 0,
-         plan: L.RoskoPlan | None = None) -> torch.Tensor:
+         plan=None, ws: torch.Tensor | None = None) -> torch.Tensor:
     """C = A B (beta 0) or C += A B (beta 1).  B: K x N float32 or bfloat16."""
-    if not (B.is_cuda and B.dim() == 2 and B.stride(1) == 1):
+    if not (B.is_cuda and B.dim() == 2 and (B.stride(1) == 1 or B.numel() == 0)):
         raise ValueError("B must be a 2-D row-major CUDA tensor")
     if B.dtype == torch.float32:
         bdt = L.ROSKO_F32
@@ -187,25 +202,38 @@ def spmm(P: PackedMatrix, B: torch.Tensor, C_out: torch.Tensor | None = None, be
         if beta:
             raise ValueError("beta = 1 needs C_out")
         C_out = torch.empty((P.M, N), dtype=torch.float32, device=B.device)
+    need = spmm_workspace_size(P, N, plan)
+    if need and (ws is None or ws.numel() < need):
+        ws = torch.empty(need, dtype=torch.uint8, device=B.device)
     st = P.struct()
     pl = C.byref(plan) if plan is not None else None
     L.check(L.lib().rosko_spmm(C.byref(st), _ptr(B), bdt, N, max(B.stride(0), 1), _ptr(C_out),
-                               max(C_out.stride(0), 1), beta, pl, _stream_ptr()))
+                               max(C_out.stride(0), 1), beta, pl,
+                               _ptr(ws) if need else None, ws.numel() if need else 0,
+                               _stream_ptr()))
     return C_out
 
 
 def spmm_backward(P: PackedMatrix, Pt: PackedMatrix | None, B: torch.Tensor, dC: torch.Tensor,
-                  need_dB: bool = True, need_dA: bool = True):
+                  need_dB: bool = True, need_dA: bool = True, ws: torch.Tensor | None = None):
     """(dA in packed order, dB) for C = A B."""
     N = dC.shape[1]
     dB = torch.empty((P.K, N), dtype=torch.float32, device=dC.device) if need_dB else None
     dA = torch.empty(max(P.nnz, 1), dtype=torch.float32, device=dC.device) if need_dA else None
     st = P.struct()
-    stt = Pt.struct() if Pt is not None else None
+    stt = Pt.struct() if (Pt is not None and need_dB) else None
+    need = 0
+    if stt is not None:
+        n = C.c_size_t(0)
+        L.check(L.lib().rosko_spmm_backward_workspace_size(C.byref(stt), N, C.byref(n)))
+        need = int(n.value)
+        if need and (ws is None or ws.numel() < need):
+            ws = torch.empty(need, dtype=torch.uint8, device=dC.device)
     L.check(L.lib().rosko_spmm_backward(
         C.byref(st), C.byref(stt) if stt is not None else None, _ptr(B),
         max(B.stride(0), 1), _ptr(dC), max(dC.stride(0), 1), N, _ptr(dB),
-        max(dB.stride(0), 1) if dB is not None else 1, _ptr(dA), _stream_ptr()))
+        max(dB.stride(0), 1) if dB is not None else 1, _ptr(dA),
+        _ptr(ws) if need else None, ws.numel() if need else 0, _stream_ptr()))
     return (dA[: P.nnz] if dA is not None else None), dB
 
 

@@ -94,7 +94,7 @@ def _packed(M, K, mr, dtype=L.ROSKO_F32, fill=True):
     s.nnz_cap, s.ncols_cap = 10, 10
     if fill:
         for f in ("panel_nz_ptr", "panel_col_ptr", "col_ind", "col_nnz", "col_ptr", "loc",
-                  "val", "row_scale"):
+                  "val", "row_scale", "kblk_ptr"):
             setattr(s, f, 0x1000)
     return s
 
@@ -131,25 +131,25 @@ def test_spmm_argument_checks():
     s = _packed(8, 8, 4)
     # bad beta, bad ldb/ldc, bad B dtype, wrong n_panels, bad plan tile
     assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 16, fake, 16, 2, None,
-                          None) == L.ROSKO_EINVAL
+                          None, 0, None) == L.ROSKO_EINVAL
     assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 8, fake, 16, 0, None,
-                          None) == L.ROSKO_EINVAL
+                          None, 0, None) == L.ROSKO_EINVAL
     assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 16, fake, 15, 0, None,
-                          None) == L.ROSKO_EINVAL
+                          None, 0, None) == L.ROSKO_EINVAL
     assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_FP8_E4M3, 16, 16, fake, 16, 0, None,
-                          None) == L.ROSKO_EUNSUPPORTED
+                          None, 0, None) == L.ROSKO_EUNSUPPORTED
     s.n_panels = 5
     assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 16, fake, 16, 0, None,
-                          None) == L.ROSKO_EINVAL
+                          None, 0, None) == L.ROSKO_EINVAL
     s = _packed(8, 8, 4)
     plan = L.RoskoPlan()
-    plan.path, plan.cols_per_lane, plan.waves = 5, 4, 2
+    plan.path, plan.cols_per_lane, plan.panels_per_wg, plan.k_split = 5, 4, 2, 1
     assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 16, fake, 16, 0, C.byref(plan),
-                          None) == L.ROSKO_EUNSUPPORTED
+                          None, 0, None) == L.ROSKO_EUNSUPPORTED
     # empty problems are valid no-ops and touch no memory
     s0 = _packed(0, 8, 4)
     assert lib.rosko_spmm(C.byref(s0), fake, L.ROSKO_F32, 16, 16, fake, 16, 0, None,
-                          None) == L.ROSKO_OK
+                          None, 0, None) == L.ROSKO_OK
 
 
 def test_backward_argument_checks():
@@ -158,7 +158,36 @@ def test_backward_argument_checks():
     s = _packed(8, 6, 4)
     st = _packed(8, 6, 4)   # wrong: must be 6 x 8
     assert lib.rosko_spmm_backward(C.byref(s), C.byref(st), fake, 16, fake, 16, 16, fake, 16,
-                                   None, None) == L.ROSKO_EINVAL
+                                   None, None, 0, None) == L.ROSKO_EINVAL
     st = _packed(6, 8, 4, dtype=L.ROSKO_BF16)
     assert lib.rosko_spmm_backward(C.byref(s), C.byref(st), fake, 16, fake, 16, 16, fake, 16,
-                                   None, None) == L.ROSKO_EUNSUPPORTED
+                                   None, None, 0, None) == L.ROSKO_EUNSUPPORTED
+
+
+def test_plan_validation_and_workspace_size():
+    lib = L.lib()
+    s = _packed(256, 2304, 32)
+    n = C.c_size_t(0)
+    plan = L.RoskoPlan()
+    plan.path, plan.cols_per_lane, plan.panels_per_wg, plan.k_split = 0, 4, 8, 4
+    assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan), C.byref(n)) == 0
+    assert n.value == 4 * 4 * 256 * 3136
+    plan.k_split = 100   # clamped to the 18 K blocks of 128
+    assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan), C.byref(n)) == 0
+    assert n.value == 4 * 18 * 256 * 3136
+    plan.k_split = 1
+    assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan), C.byref(n)) == 0
+    assert n.value == 0
+    plan.panels_per_wg = 3
+    assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan),
+                                         C.byref(n)) == L.ROSKO_EUNSUPPORTED
+    plan.panels_per_wg, plan.cols_per_lane = 8, 1   # 32 x 1 tile not provided
+    assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan),
+                                         C.byref(n)) == L.ROSKO_EUNSUPPORTED
+    plan.cols_per_lane, plan.k_split = 4, 0
+    assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan),
+                                         C.byref(n)) == L.ROSKO_EINVAL
+    # the automatic plan is valid for every supported panel height
+    for mr in (1, 8, 13, 32, 50, 64, 100, 128):
+        s2 = _packed(300, 1000, mr)
+        assert lib.rosko_spmm_workspace_size(C.byref(s2), 777, None, C.byref(n)) == 0

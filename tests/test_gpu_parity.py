@@ -125,19 +125,19 @@ def test_pack_capacity_overflow_reported():
 # --------------------------------------------------------------------------
 # SpMM, FP32
 # --------------------------------------------------------------------------
-PLANS = [(4, 1), (4, 2), (4, 4), (2, 1), (2, 2)]
+PLANS = [(4, 1, 1), (4, 8, 1), (4, 4, 2), (4, 2, 4), (2, 8, 1), (2, 1, 3)]
 
 
 @pytest.mark.parametrize("plan", PLANS)
 def test_spmm_plain_512(plan):
     """512 x 512 at 90% sparsity times 512 x 512 (the plain FP32 case)."""
-    V, W = plan
-    say(f"spmm plain-512 plan V={V} W={W}")
+    V, G, S = plan
+    say(f"spmm plain-512 plan V={V} G={G} S={S}")
     pr = synth.plain_512()
     ref = O.spmm(pr.A, pr.B)
     scale = O.abs_product(pr.A, pr.B)
     P = ops.pack(dev(pr.A), 32, "f32")
-    C = ops.spmm(P, dev(pr.B), plan=ops.make_plan(V, W)).cpu().numpy()
+    C = ops.spmm(P, dev(pr.B), plan=ops.make_plan(V, G, S)).cpu().numpy()
     e = err(C, ref, scale)
     say(f"  err {e:.3e}")
     assert e <= TOL_F32
@@ -154,9 +154,9 @@ def test_spmm_shapes_ragged(mr, V, N):
     ref = O.spmm(A, B)
     scale = O.abs_product(A, B)
     P = ops.pack(dev(A), mr, "f32")
-    for W in (1, 2, 4):
-        C = ops.spmm(P, dev(B), plan=ops.make_plan(V, W)).cpu().numpy()
-        assert err(C, ref, scale) <= TOL_F32, (W,)
+    for G, S in ((1, 1), (2, 2), (8, 1), (4, 9)):
+        C = ops.spmm(P, dev(B), plan=ops.make_plan(V, G, S)).cpu().numpy()
+        assert err(C, ref, scale) <= TOL_F32, (G, S)
 
 
 def test_spmm_beta_one_and_strides():
@@ -171,7 +171,7 @@ def test_spmm_beta_one_and_strides():
     P = ops.pack(dev(A), 32)
     Bd = dev(Bpad)[:, :130]
     Cd = dev(Cpad)
-    ops.spmm(P, Bd, Cd[:, :130], beta=1)
+    ops.spmm(P, Bd, Cd[:, :130], beta=1, plan=ops.make_plan(4, 2, 2))
     got = Cd.cpu().numpy()
     ref = O.spmm(A, B) + C0.astype(np.float64)
     scale = O.abs_product(A, B) + np.abs(C0)
@@ -211,9 +211,9 @@ def test_spmm_deterministic():
     B = synth.dense_normal(2304, 512, 609)
     P = ops.pack(dev(A), 32)
     Bd = dev(B)
-    for W in (1, 2, 4):
-        c1 = ops.spmm(P, Bd, plan=ops.make_plan(4, W)).cpu().numpy()
-        c2 = ops.spmm(P, Bd, plan=ops.make_plan(4, W)).cpu().numpy()
+    for G, S in ((8, 1), (4, 3), (1, 9)):
+        c1 = ops.spmm(P, Bd, plan=ops.make_plan(4, G, S)).cpu().numpy()
+        c2 = ops.spmm(P, Bd, plan=ops.make_plan(4, G, S)).cpu().numpy()
         assert c1.tobytes() == c2.tobytes()
 
 
@@ -228,10 +228,10 @@ def test_spmm_cnn_layer_sampled(s):
     scale = O.abs_product(pr.A[rows], pr.B)
     P = ops.pack(dev(pr.A), 32)
     Bd = dev(pr.B)
-    for V, W in ((4, 1), (4, 2), (2, 2)):
-        C = ops.spmm(P, Bd, plan=ops.make_plan(V, W))
+    for V, G, S in ((4, 8, 1), (4, 8, 4), (2, 4, 2), (4, 1, 18)):
+        C = ops.spmm(P, Bd, plan=ops.make_plan(V, G, S))
         e = err(C.cpu().numpy()[rows], ref, scale)
-        say(f"  V={V} W={W} err {e:.3e}")
+        say(f"  V={V} G={G} S={S} err {e:.3e}")
         assert e <= TOL_F32
 
 

@@ -416,3 +416,18 @@ def test_adam_first_step_closed_form():
         np.testing.assert_allclose(newp[k], 1 - 0.1 * G[k] / (np.abs(G[k]) + 1e-8), rtol=1e-12)
         np.testing.assert_allclose(m[k], 0.1 * G[k], rtol=1e-12)
         np.testing.assert_allclose(v[k], 0.001 * G[k] ** 2, rtol=1e-12)
+
+
+def test_kblk_ptr_against_searchsorted():
+    # independent route: per panel, np.searchsorted of the block starts in the
+    # panel's ascending col_ind list
+    for seed, mr in ((1, 8), (2, 32), (3, 13)):
+        A = synth.sparse_matrix(70, 700, 0.02, 900 + seed, "column_banded")
+        pk = O.pack(A, mr)
+        kb = O.kblk_ptr(pk, 128)
+        nkb = (700 + 127) // 128
+        for p in range(pk.n_panels):
+            lo, hi = pk.panel_col_ptr[p], pk.panel_col_ptr[p + 1]
+            cols = pk.col_ind[lo:hi]
+            for j in range(nkb):
+                assert kb[p * nkb + j] == lo + np.searchsorted(cols, j * 128, side="left")
