@@ -73,18 +73,28 @@ extern "C" {
  *   loc      [nnz]     uint8   row of the value inside its panel (loc_m)
  *   val      [nnz]     4, 2 or 1 bytes per value by val_dtype (A_p)
  *   row_scale[M]       float   s_m for ROSKO_FP8_E4M3, otherwise unused (may be NULL)
- *   kblk_ptr [n_panels * ceil(K / ROSKO_KSTEP)] int64
- *                              slot of the first kept column of panel p with
- *                              k >= j * ROSKO_KSTEP (the panel's end slot if
- *                              none), at [p * ceil(K / ROSKO_KSTEP) + j]; lets
- *                              a workgroup start a K range inside a panel
- * nnz_cap and ncols_cap are the capacities of the caller's buffers
- * (col_ptr must hold ncols_cap+1 entries).  rosko_spmm reads values in
+ *   rec      [nrec * 16] uint32  column records: the GPU execution copy of
+ *                              the panels.  Every kept column becomes
+ *                              ceil(nnz/12) records of 16 dwords, in packed
+ *                              order: dword 0 = (k << 8) | count (1..12),
+ *                              dwords 1..3 = the values' in-panel rows, one
+ *                              byte each (value t in byte t%4 of dword
+ *                              1 + t/4), dwords 4..15 = the values as FP32
+ *                              bits (BF16 decoded exactly; FP8 as the code's
+ *                              value, without s_m); unused bytes are zero.
+ *                              One scalar load fetches a column.
+ *   kblk_ptr [n_panels * (ceil(K / ROSKO_KSTEP) + 1)] int64
+ *                              at [p * (nkb + 1) + j]: the first record of
+ *                              panel p whose column has k >= j * ROSKO_KSTEP
+ *                              (the panel's end if none); j = nkb is the end
+ *                              of the panel.  Lets a workgroup start a K
+ *                              range inside a panel.
+ * nnz_cap, ncols_cap and nrec_cap are the capacities of the caller's
+ * buffers (col_ptr must hold ncols_cap+1 entries).  rosko_spmm reads values in
  * batches of 8 and row bytes by aligned dwords, so val and loc must stay
  * readable for ROSKO_READ_SLACK entries past nnz (allocate nnz_cap +
  * ROSKO_READ_SLACK entries); the extra entries are never used.  nnz and ncols are written by
  * rosko_pack_query / rosko_pack_result on the host side only. */
-#define ROSKO_READ_SLACK 64
 #define ROSKO_KSTEP 128
 typedef struct rosko_packed {
   int64_t M, K;
@@ -92,8 +102,8 @@ typedef struct rosko_packed {
   int32_t n_panels;    /* ceil(M / mr) */
   int32_t val_dtype;   /* ROSKO_F32 / ROSKO_BF16 / ROSKO_FP8_E4M3 */
   int32_t reserved;
-  int64_t nnz_cap, ncols_cap;
-  int64_t nnz, ncols;  /* host copies when known, else -1 */
+  int64_t nnz_cap, ncols_cap, nrec_cap;
+  int64_t nnz, ncols, nrec;  /* host copies when known, else -1 */
   int64_t *panel_nz_ptr;
   int64_t *panel_col_ptr;
   int32_t *col_ind;
@@ -103,6 +113,7 @@ typedef struct rosko_packed {
   void *val;
   float *row_scale;
   int64_t *kblk_ptr;
+  uint32_t *rec;
 } rosko_packed;
 
 /* ---- execution plan for rosko_spmm ----------------------------------
@@ -140,11 +151,13 @@ typedef struct rosko_plan {
 int32_t rosko_pack_workspace_size(int64_t M, int64_t K, int32_t mr, int32_t transpose,
                                   size_t *bytes);
 
-/* Counts the kept values and kept columns that packing A (device, M x K,
- * row-major, lda >= K) with panel height mr produces.  SYNCHRONISES `stream`
- * to return the two totals in *nnz and *ncols (host).  ws: device workspace. */
+/* Counts the kept values, kept columns and column records that packing A
+ * (device, M x K, row-major, lda >= K) with panel height mr produces.
+ * SYNCHRONISES `stream` to return the totals in *nnz, *ncols and *nrec
+ * (host).  ws: device workspace.  EUNSUPPORTED if K >= 2^24. */
 int32_t rosko_pack_query(const float *A, int64_t M, int64_t K, int64_t lda, int32_t mr,
-                         void *ws, size_t ws_bytes, void *stream, int64_t *nnz, int64_t *ncols);
+                         void *ws, size_t ws_bytes, void *stream, int64_t *nnz, int64_t *ncols,
+                         int64_t *nrec);
 
 /* Packs A (device, M x K, lda >= K) into `out`.  The caller sets out->M, K,
  * mr, val_dtype, the capacities and the buffer pointers; the call sets
@@ -166,7 +179,7 @@ int32_t rosko_pack_transpose(const float *A, int64_t M, int64_t K, int64_t lda, 
  * with transpose != 0.  SYNCHRONISES `stream`. */
 int32_t rosko_pack_transpose_query(const float *A, int64_t M, int64_t K, int64_t lda,
                                    int32_t mr, void *ws, size_t ws_bytes, void *stream,
-                                   int64_t *nnz, int64_t *ncols);
+                                   int64_t *nnz, int64_t *ncols, int64_t *nrec);
 
 /* After rosko_pack / rosko_pack_transpose with the same ws: SYNCHRONISES the
  * stream, stores the totals in packed->nnz / ncols, and returns

@@ -65,7 +65,8 @@ def lib():
         L.ro_grad_dA_packed.argtypes = [i64, i32, p, p, p, p, p, p, i64, p, i64, i64, p]
         L.ro_grad_dA_packed.restype = None
         L.ro_max_threads.argtypes = []; L.ro_max_threads.restype = i32
-        L.ro_kblk_ptr.argtypes = [i64, i64, i32, i32, p, p, p]; L.ro_kblk_ptr.restype = None
+        L.ro_records.argtypes = [i64, i64, i32, i32, i32, p, p, p, p, p, p, p, p]
+        L.ro_records.restype = i64
         _lib = L
     return _lib
 
@@ -160,15 +161,21 @@ def pack(A: np.ndarray, mr: int, dtype: int = F32) -> Packed:
                   None if rs is None else rs[:M])
 
 
-KSTEP = 128   # K-block width of the derived kblk_ptr index
+KSTEP = 128   # K-block width of the derived record index
 
 
-def kblk_ptr(pk: Packed, kstep: int = KSTEP) -> np.ndarray:
+def records(pk: Packed, kstep: int = KSTEP):
+    """(rec [nrec x 16] uint32, rec_kblk [P*(nkb+1)] int64): the column-record
+    copy of the packed panels and its K-block index (see ro_records)."""
+    L = lib()
+    args = (pk.M, pk.K, pk.mr, pk.dtype, kstep, _ptr(pk.panel_col_ptr), _ptr(pk.col_ind),
+            _ptr(pk.col_nnz), _ptr(pk.col_ptr), _ptr(pk.loc), _ptr(pk.val))
+    nrec = L.ro_records(*args, None, None)
     nkb = (pk.K + kstep - 1) // kstep
-    out = np.zeros(max(pk.n_panels * nkb, 1), np.int64)
-    lib().ro_kblk_ptr(pk.M, pk.K, pk.mr, kstep, _ptr(pk.panel_col_ptr), _ptr(pk.col_ind),
-                      _ptr(out))
-    return out[:pk.n_panels * nkb]
+    rec = np.zeros((max(nrec, 1), 16), np.uint32)
+    kb = np.zeros(max(pk.n_panels * (nkb + 1), 1), np.int64)
+    L.ro_records(*args, _ptr(rec), _ptr(kb))
+    return rec[:nrec], kb[:pk.n_panels * (nkb + 1)]
 
 
 def unpack(pk: Packed) -> np.ndarray:

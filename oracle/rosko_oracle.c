@@ -199,21 +199,64 @@ void ro_pack(const float *A, int64_t M, int64_t K, int64_t lda, int32_t mr, int3
   col_ptr[i2] = i1;
 }
 
-/* Derived column index per K block of KSTEP columns: kblk_ptr[p*nkb + j]
- * is the slot of the first kept column of panel p with k >= j*KSTEP (the
- * panel's end slot if there is none), for j < nkb = ceil(K / KSTEP).  A
- * plain scan of the panel's column list. */
-void ro_kblk_ptr(int64_t M, int64_t K, int32_t mr, int32_t kstep,
-                 const int64_t *panel_col_ptr, const int32_t *col_ind, int64_t *kblk_ptr) {
+/* Decoded value of packed entry z as FP32 bits (FP8: the code's value,
+ * without the row scale). */
+static uint32_t decoded_bits(int32_t dtype, const void *val, int64_t z) {
+  float f;
+  if (dtype == RO_F32) f = ((const float *)val)[z];
+  else if (dtype == RO_BF16) f = ro_bf16_decode(((const uint16_t *)val)[z]);
+  else {
+    uint8_t c = ((const uint8_t *)val)[z];
+    if (((c >> 3) & 15) == 15 && (c & 7) == 7) return 0x7FC00000u;
+    f = (float)ro_fp8_decode_d(c);
+  }
+  return bits_of(f);
+}
+
+/* Column records: the GPU execution copy of the packed panels.  Every kept
+ * column becomes ceil(nnz/12) records of 16 dwords, in packed order:
+ *   dword 0      (k << 8) | count (count 1..12 values in this record)
+ *   dwords 1..3  the in-panel rows of the record's values, one byte each,
+ *                value t in byte t%4 of dword 1 + t/4 (unused bytes 0)
+ *   dwords 4..15 the values as FP32 bits (decoded; unused slots 0)
+ * rec_kblk[p*(nkb+1) + j] is the first record of panel p whose column has
+ * k >= j*kstep (the panel's end if none), for j = 0..nkb, nkb = ceil(K/kstep).
+ * Returns the number of records. */
+int64_t ro_records(int64_t M, int64_t K, int32_t mr, int32_t dtype, int32_t kstep,
+                   const int64_t *panel_col_ptr, const int32_t *col_ind, const int32_t *col_nnz,
+                   const int64_t *col_ptr, const uint8_t *loc, const void *val,
+                   uint32_t *rec, int64_t *rec_kblk) {
   int64_t P = (M + mr - 1) / mr;
   int64_t nkb = (K + kstep - 1) / kstep;
+  int64_t r = 0;
   for (int64_t p = 0; p < P; ++p) {
-    for (int64_t j = 0; j < nkb; ++j) {
-      int64_t c = panel_col_ptr[p];
-      while (c < panel_col_ptr[p + 1] && col_ind[c] < j * kstep) ++c;
-      kblk_ptr[p * nkb + j] = c;
+    int64_t j = 0;
+    for (int64_t c = panel_col_ptr[p]; c < panel_col_ptr[p + 1]; ++c) {
+      while (j <= nkb && j * kstep <= col_ind[c]) {
+        if (rec_kblk) rec_kblk[p * (nkb + 1) + j] = r;
+        ++j;
+      }
+      for (int64_t first = 0; first < col_nnz[c]; first += 12) {
+        int64_t cnt = col_nnz[c] - first < 12 ? col_nnz[c] - first : 12;
+        if (rec) {
+          uint32_t *d = rec + r * 16;
+          for (int q = 0; q < 16; ++q) d[q] = 0u;
+          d[0] = ((uint32_t)col_ind[c] << 8) | (uint32_t)cnt;
+          for (int64_t t = 0; t < cnt; ++t) {
+            int64_t z = col_ptr[c] + first + t;
+            d[1 + t / 4] |= (uint32_t)loc[z] << (8 * (t % 4));
+            d[4 + t] = decoded_bits(dtype, val, z);
+          }
+        }
+        ++r;
+      }
+    }
+    while (j <= nkb) {
+      if (rec_kblk) rec_kblk[p * (nkb + 1) + j] = r;
+      ++j;
     }
   }
+  return r;
 }
 
 /* Decoded value of packed entry z as a double. */

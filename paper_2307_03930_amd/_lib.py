@@ -25,7 +25,6 @@ ROSKO_FP8_E4M3 = 2
 ROSKO_PATH_AUTO = -1
 ROSKO_PATH_SPARSE = 0
 ROSKO_KSTEP = 128
-ROSKO_READ_SLACK = 64
 
 
 class RoskoPacked(C.Structure):
@@ -33,12 +32,12 @@ class RoskoPacked(C.Structure):
         ("M", C.c_int64), ("K", C.c_int64),
         ("mr", C.c_int32), ("n_panels", C.c_int32),
         ("val_dtype", C.c_int32), ("reserved", C.c_int32),
-        ("nnz_cap", C.c_int64), ("ncols_cap", C.c_int64),
-        ("nnz", C.c_int64), ("ncols", C.c_int64),
+        ("nnz_cap", C.c_int64), ("ncols_cap", C.c_int64), ("nrec_cap", C.c_int64),
+        ("nnz", C.c_int64), ("ncols", C.c_int64), ("nrec", C.c_int64),
         ("panel_nz_ptr", C.c_void_p), ("panel_col_ptr", C.c_void_p),
         ("col_ind", C.c_void_p), ("col_nnz", C.c_void_p), ("col_ptr", C.c_void_p),
         ("loc", C.c_void_p), ("val", C.c_void_p), ("row_scale", C.c_void_p),
-        ("kblk_ptr", C.c_void_p),
+        ("kblk_ptr", C.c_void_p), ("rec", C.c_void_p),
     ]
 
 
@@ -68,9 +67,10 @@ _P, _I64, _I32, _SZ = C.c_void_p, C.c_int64, C.c_int32, C.c_size_t
 SIGNATURES = {
     "rosko_pack_workspace_size": (_I32, [_I64, _I64, _I32, _I32, C.POINTER(_SZ)]),
     "rosko_pack_query": (_I32, [_P, _I64, _I64, _I64, _I32, _P, _SZ, _P,
-                                C.POINTER(_I64), C.POINTER(_I64)]),
+                                C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
     "rosko_pack_transpose_query": (_I32, [_P, _I64, _I64, _I64, _I32, _P, _SZ, _P,
-                                          C.POINTER(_I64), C.POINTER(_I64)]),
+                                          C.POINTER(_I64), C.POINTER(_I64),
+                                          C.POINTER(_I64)]),
     "rosko_pack": (_I32, [_P, _I64, _I64, _I64, _I32, _I32, _P, _SZ, C.POINTER(RoskoPacked), _P]),
     "rosko_pack_transpose": (_I32, [_P, _I64, _I64, _I64, _I32, _I32, _P, _SZ,
                                     C.POINTER(RoskoPacked), _P]),

@@ -52,7 +52,11 @@ static int32_t check_packed_for_write(const rosko_packed* out, int64_t R, int64_
              (long long)out->M, (long long)out->K, out->mr, (long long)R, (long long)S, mr);
   RK_REQUIRE(dt == ROSKO_F32 || dt == ROSKO_BF16 || dt == ROSKO_FP8_E4M3, ROSKO_EUNSUPPORTED,
              "value dtype %d not supported", dt);
-  RK_REQUIRE(out->nnz_cap >= 0 && out->ncols_cap >= 0, ROSKO_EINVAL, "negative capacity");
+  RK_REQUIRE(out->nnz_cap >= 0 && out->ncols_cap >= 0 && out->nrec_cap >= 0, ROSKO_EINVAL,
+             "negative capacity");
+  RK_REQUIRE(S < (int64_t(1) << 24), ROSKO_EUNSUPPORTED, "K = %lld >= 2^24 columns",
+             (long long)S);
+  RK_REQUIRE(out->nrec_cap == 0 || out->rec, ROSKO_EINVAL, "record array is null");
   RK_REQUIRE(out->panel_nz_ptr && out->panel_col_ptr && out->col_ptr, ROSKO_EINVAL,
              "packed pointer arrays are null");
   RK_REQUIRE(out->ncols_cap == 0 || (out->col_ind && out->col_nnz), ROSKO_EINVAL,
@@ -61,7 +65,7 @@ static int32_t check_packed_for_write(const rosko_packed* out, int64_t R, int64_
              "packed value arrays are null");
   RK_REQUIRE(dt != ROSKO_FP8_E4M3 || R == 0 || out->row_scale, ROSKO_EINVAL,
              "FP8 packing needs row_scale");
-  RK_REQUIRE(R == 0 || S == 0 || out->kblk_ptr, ROSKO_EINVAL, "kblk_ptr is null");
+  RK_REQUIRE(R == 0 || out->kblk_ptr, ROSKO_EINVAL, "kblk_ptr is null");
   return ROSKO_OK;
 }
 
@@ -84,7 +88,8 @@ static int32_t check_packed_for_read(const rosko_packed* A) {
              "packed value arrays are null");
   RK_REQUIRE(A->val_dtype != ROSKO_FP8_E4M3 || A->M == 0 || A->row_scale, ROSKO_EINVAL,
              "FP8 values need row_scale");
-  RK_REQUIRE(A->M == 0 || A->K == 0 || A->kblk_ptr, ROSKO_EINVAL, "kblk_ptr is null");
+  RK_REQUIRE(A->M == 0 || A->kblk_ptr, ROSKO_EINVAL, "kblk_ptr is null");
+  RK_REQUIRE(A->nrec_cap == 0 || A->rec, ROSKO_EINVAL, "record array is null");
   return ROSKO_OK;
 }
 
@@ -121,12 +126,14 @@ int32_t rosko_pack_workspace_size(int64_t M, int64_t K, int32_t mr, int32_t tran
 
 int32_t rosko_pack_query(const float* A, int64_t M, int64_t K, int64_t lda, int32_t mr,
                          void* ws, size_t ws_bytes, void* stream, int64_t* nnz,
-                         int64_t* ncols) {
+                         int64_t* ncols, int64_t* nrec) {
   clear_error();
   int32_t st = check_dense(A, M, K, lda, "A");
   if (st) return st;
   if ((st = check_mr(mr))) return st;
-  RK_REQUIRE(nnz && ncols, ROSKO_EINVAL, "nnz / ncols outputs are null");
+  RK_REQUIRE(nnz && ncols && nrec, ROSKO_EINVAL, "nnz / ncols / nrec outputs are null");
+  RK_REQUIRE(K < (int64_t(1) << 24), ROSKO_EUNSUPPORTED, "K = %lld >= 2^24 columns",
+             (long long)K);
   const PackWs L = pack_ws_layout(M, K, mr, false);
   RK_REQUIRE(ws != nullptr && ws_bytes >= L.bytes, ROSKO_ESMALLBUF,
              "workspace %zu bytes < %zu", ws_bytes, L.bytes);
@@ -139,17 +146,20 @@ int32_t rosko_pack_query(const float* A, int64_t M, int64_t K, int64_t lda, int3
   ROSKO_HIP_CHECK(hipStreamSynchronize(s));
   *nnz = tot[0];
   *ncols = tot[1];
+  *nrec = tot[3];
   return ROSKO_OK;
 }
 
 int32_t rosko_pack_transpose_query(const float* A, int64_t M, int64_t K, int64_t lda,
                                    int32_t mr, void* ws, size_t ws_bytes, void* stream,
-                                   int64_t* nnz, int64_t* ncols) {
+                                   int64_t* nnz, int64_t* ncols, int64_t* nrec) {
   clear_error();
   int32_t st = check_dense(A, M, K, lda, "A");
   if (st) return st;
   if ((st = check_mr(mr))) return st;
-  RK_REQUIRE(nnz && ncols, ROSKO_EINVAL, "nnz / ncols outputs are null");
+  RK_REQUIRE(nnz && ncols && nrec, ROSKO_EINVAL, "nnz / ncols / nrec outputs are null");
+  RK_REQUIRE(M < (int64_t(1) << 24), ROSKO_EUNSUPPORTED, "M = %lld >= 2^24 columns of A^T",
+             (long long)M);
   const PackWs L = pack_ws_layout(K, M, mr, true);
   RK_REQUIRE(ws != nullptr && ws_bytes >= L.bytes, ROSKO_ESMALLBUF,
              "workspace %zu bytes < %zu", ws_bytes, L.bytes);
@@ -164,6 +174,7 @@ int32_t rosko_pack_transpose_query(const float* A, int64_t M, int64_t K, int64_t
   ROSKO_HIP_CHECK(hipStreamSynchronize(s));
   *nnz = tot[0];
   *ncols = tot[1];
+  *nrec = tot[3];
   return ROSKO_OK;
 }
 
@@ -175,6 +186,7 @@ static int32_t pack_common(const float* A, int64_t R, int64_t S, int64_t lda, in
   out->val_dtype = val_dtype;
   out->nnz = -1;
   out->ncols = -1;
+  out->nrec = -1;
   (void)hipGetLastError();
   if (val_dtype == ROSKO_FP8_E4M3) {
     if ((st = launch_row_scale(A, R, S, lda, out->row_scale, s))) return st;
@@ -232,10 +244,13 @@ int32_t rosko_pack_result(const void* ws, size_t ws_bytes, rosko_packed* packed,
   ROSKO_HIP_CHECK(hipStreamSynchronize(s));
   packed->nnz = tot[0];
   packed->ncols = tot[1];
+  packed->nrec = tot[3];
   RK_REQUIRE(tot[2] == 0, ROSKO_ESMALLBUF,
-             "packing needs %lld values / %lld columns, capacities are %lld / %lld",
-             (long long)tot[0], (long long)tot[1], (long long)packed->nnz_cap,
-             (long long)packed->ncols_cap);
+             "packing needs %lld values / %lld columns / %lld records, capacities are "
+             "%lld / %lld / %lld",
+             (long long)tot[0], (long long)tot[1], (long long)tot[3],
+             (long long)packed->nnz_cap, (long long)packed->ncols_cap,
+             (long long)packed->nrec_cap);
   return ROSKO_OK;
 }
 

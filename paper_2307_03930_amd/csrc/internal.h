@@ -38,14 +38,15 @@ void clear_error();
 // R x S matrix (R rows split into panels of mr) given as rows x cols.
 struct PackWs {
   size_t counts;       // int32 [P*S]        values per (panel, column)
-  size_t tile_sums;    // int64 [2*NT]       (values, kept columns) per tile
-  size_t tile_offs;    // int64 [2*NT]       exclusive prefix of tile_sums
-  size_t totals;       // int64 [4]          nnz, ncols, overflow flag, spare
+  size_t tile_sums;    // int64 [3*NT]       (values, kept columns, records) per tile
+  size_t tile_offs;    // int64 [3*NT]       exclusive prefix of tile_sums
+  size_t totals;       // int64 [4]          nnz, ncols, overflow flag, nrec
   size_t transposed;   // float [R*S]        dense transpose (transpose packing only)
   size_t bytes;        // total
   int64_t P, NT;
 };
 constexpr int kPackTile = 1024;      // (panel, column) pairs per scan tile
+constexpr int kRecVals = 12;         // values per 16-dword column record
 constexpr int kPackThreads = 256;
 PackWs pack_ws_layout(int64_t R, int64_t S, int32_t mr, bool transpose);
 
@@ -66,14 +67,9 @@ int32_t launch_transpose(const float* A, int64_t M, int64_t K, int64_t lda, floa
 // Kernel arguments of the row-skipping SpMM (device pointers of the packed
 // matrix, B and C).
 struct SpmmArgs {
-  const int64_t* panel_col_ptr;
-  const int32_t* col_ind;
-  const int32_t* col_nnz;
-  const int64_t* col_ptr;
-  const uint8_t* loc;
-  const void* val;
-  const float* row_scale;
-  const int64_t* kblk_ptr;
+  const uint32_t* rec;          // column records, 16 dwords each
+  const float* row_scale;       // FP8 row scales, else null
+  const int64_t* kblk_ptr;      // record index per (panel, K block)
   const void* B;
   float* C;
   float* ws;           // k_split x M x N partial tiles (k_split > 1)
@@ -85,14 +81,10 @@ struct SpmmArgs {
   int32_t vec;         // B/C rows allow V-wide vector access (alignment, N % V)
   int32_t ws_vec;      // workspace rows allow V-wide vector access
 };
-// One dispatcher per (value dtype, B dtype); H = register-tile height,
-// V = columns per lane, G = panels (wavefronts) per workgroup.
-int32_t spmm_dispatch_f32_f32(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
-int32_t spmm_dispatch_f32_bf16(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
-int32_t spmm_dispatch_bf16_f32(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
-int32_t spmm_dispatch_bf16_bf16(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
-int32_t spmm_dispatch_fp8_f32(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
-int32_t spmm_dispatch_fp8_bf16(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
+// One dispatcher per B dtype; H = register-tile height, V = columns per
+// lane, G = panels (wavefronts) per workgroup.
+int32_t spmm_dispatch_bf32(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
+int32_t spmm_dispatch_bbf16(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
 
 // Plan helpers (spmm.hip): the automatic plan, validation/normalisation of a
 // caller's plan, and the workspace a plan needs.

@@ -50,36 +50,53 @@ __device__ __forceinline__ uint8_t enc_fp8(float y) {
   return (uint8_t)(sign | code);
 }
 
-// Inclusive wave prefix sum of a pair, then exclusive block prefix.
-struct Pair { int64_t a, b; };
+// Values, kept columns and column records of a range of (panel, column)
+// pairs; the scans below carry all three.
+struct Tri { int64_t a, b, c; };
 
-__device__ __forceinline__ Pair wave_incl_scan(Pair v) {
+// Records a kept column of `cnt` values occupies.
+__device__ __forceinline__ int64_t n_records(int cnt) {
+  return (cnt + kRecVals - 1) / kRecVals;
+}
+
+// Inclusive wave prefix sum, then exclusive block prefix.
+__device__ __forceinline__ Tri wave_incl_scan(Tri v) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     int64_t ta = __shfl_up(v.a, d, 64);
     int64_t tb = __shfl_up(v.b, d, 64);
-    if (lane >= d) { v.a += ta; v.b += tb; }
+    int64_t tc = __shfl_up(v.c, d, 64);
+    if (lane >= d) { v.a += ta; v.b += tb; v.c += tc; }
   }
   return v;
 }
 
 // Exclusive scan across a block of blockDim.x threads (multiple of 64, at
 // most 1024).  Returns the thread's exclusive prefix; *total gets the sum.
-__device__ Pair block_excl_scan(Pair v, Pair* total) {
-  __shared__ Pair wsum[16];
+__device__ Tri block_excl_scan(Tri v, Tri* total) {
+  __shared__ Tri wsum[16];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  Pair inc = wave_incl_scan(v);
+  Tri inc = wave_incl_scan(v);
   if (lane == 63) wsum[wid] = inc;
   __syncthreads();
-  Pair base{0, 0}, tot{0, 0};
+  Tri base{0, 0, 0}, tot{0, 0, 0};
   for (int w = 0; w < nw; ++w) {
-    if (w < wid) { base.a += wsum[w].a; base.b += wsum[w].b; }
-    tot.a += wsum[w].a; tot.b += wsum[w].b;
+    if (w < wid) { base.a += wsum[w].a; base.b += wsum[w].b; base.c += wsum[w].c; }
+    tot.a += wsum[w].a; tot.b += wsum[w].b; tot.c += wsum[w].c;
   }
   __syncthreads();
   *total = tot;
-  return Pair{base.a + inc.a - v.a, base.b + inc.b - v.b};
+  return Tri{base.a + inc.a - v.a, base.b + inc.b - v.b, base.c + inc.c - v.c};
+}
+
+// FP32 value of a packed value (FP8: the code's value, unscaled), as bits.
+__device__ __forceinline__ uint32_t dec_bf16(uint16_t h) { return (uint32_t)h << 16; }
+__device__ __forceinline__ uint32_t dec_fp8(uint8_t c) {
+  const uint32_t e = (c >> 3) & 15u, m = c & 7u, s = (uint32_t)(c & 0x80u) << 24;
+  if (e == 15 && m == 7) return 0x7FC00000u;
+  if (e == 0) return s | __float_as_uint((float)m * 0.001953125f);     // m * 2^-9
+  return s | ((e + 120u) << 23) | (m << 20);                            // (1+m/8) 2^(e-7)
 }
 
 // ------------------------------------------------------------------ count
@@ -91,7 +108,7 @@ k_pack_count(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
              int64_t P, int32_t* __restrict__ counts, int64_t* __restrict__ tile_sums) {
   const int64_t total = P * S;
   const int64_t f0 = (int64_t)blockIdx.x * kPackTile;
-  int64_t my_nnz = 0, my_cols = 0;
+  int64_t my_nnz = 0, my_cols = 0, my_recs = 0;
 #pragma unroll
   for (int j = 0; j < kPackTile / kPackThreads; ++j) {
     const int64_t f = f0 + threadIdx.x + (int64_t)kPackThreads * j;
@@ -111,13 +128,15 @@ k_pack_count(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
       counts[f] = c;
       my_nnz += c;
       my_cols += (c != 0);
+      my_recs += n_records(c);
     }
   }
-  Pair tot;
-  (void)block_excl_scan(Pair{my_nnz, my_cols}, &tot);
+  Tri tot;
+  (void)block_excl_scan(Tri{my_nnz, my_cols, my_recs}, &tot);
   if (threadIdx.x == 0) {
-    tile_sums[2 * blockIdx.x] = tot.a;
-    tile_sums[2 * blockIdx.x + 1] = tot.b;
+    tile_sums[3 * blockIdx.x] = tot.a;
+    tile_sums[3 * blockIdx.x + 1] = tot.b;
+    tile_sums[3 * blockIdx.x + 2] = tot.c;
   }
 }
 
@@ -127,31 +146,36 @@ k_pack_count(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
 __global__ void __launch_bounds__(1024)
 k_pack_scan(const int64_t* __restrict__ tile_sums, int64_t* __restrict__ tile_offs, int64_t NT,
             int64_t* __restrict__ totals, int64_t P, int64_t S, int64_t nnz_cap,
-            int64_t ncols_cap, int64_t* __restrict__ panel_nz_ptr,
-            int64_t* __restrict__ panel_col_ptr, int64_t* __restrict__ col_ptr) {
-  Pair carry{0, 0};
+            int64_t ncols_cap, int64_t nrec_cap, int64_t* __restrict__ panel_nz_ptr,
+            int64_t* __restrict__ panel_col_ptr, int64_t* __restrict__ col_ptr,
+            int64_t* __restrict__ kblk_ptr) {
+  Tri carry{0, 0, 0};
   for (int64_t base = 0; base < NT; base += 1024) {
     const int64_t i = base + threadIdx.x;
-    Pair v{0, 0};
-    if (i < NT) v = Pair{tile_sums[2 * i], tile_sums[2 * i + 1]};
-    Pair tot;
-    Pair e = block_excl_scan(v, &tot);
+    Tri v{0, 0, 0};
+    if (i < NT) v = Tri{tile_sums[3 * i], tile_sums[3 * i + 1], tile_sums[3 * i + 2]};
+    Tri tot;
+    Tri e = block_excl_scan(v, &tot);
     if (i < NT) {
-      tile_offs[2 * i] = carry.a + e.a;
-      tile_offs[2 * i + 1] = carry.b + e.b;
+      tile_offs[3 * i] = carry.a + e.a;
+      tile_offs[3 * i + 1] = carry.b + e.b;
+      tile_offs[3 * i + 2] = carry.c + e.c;
     }
     carry.a += tot.a;
     carry.b += tot.b;
+    carry.c += tot.c;
   }
+  const int64_t nkb = (S + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
   if (threadIdx.x == 0) {
     totals[0] = carry.a;
     totals[1] = carry.b;
-    totals[2] = (carry.a > nnz_cap || carry.b > ncols_cap) ? 1 : 0;
-    totals[3] = 0;
+    totals[2] = (carry.a > nnz_cap || carry.b > ncols_cap || carry.c > nrec_cap) ? 1 : 0;
+    totals[3] = carry.c;
     if (panel_nz_ptr) {
       panel_nz_ptr[P] = carry.a;
       panel_col_ptr[P] = carry.b;
       if (carry.b <= ncols_cap) col_ptr[carry.b] = carry.a;
+      if (P > 0) kblk_ptr[(P - 1) * (nkb + 1) + nkb] = carry.c;   // end of the last panel
     }
   }
   // With no columns at all every panel starts at 0 (the write pass, which
@@ -160,6 +184,7 @@ k_pack_scan(const int64_t* __restrict__ tile_sums, int64_t* __restrict__ tile_of
     for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
       panel_nz_ptr[p] = 0;
       panel_col_ptr[p] = 0;
+      kblk_ptr[p] = 0;        // nkb = 0: one entry (the end) per panel
     }
   }
 }
@@ -173,11 +198,13 @@ k_pack_write(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
              int64_t* __restrict__ panel_col_ptr, int32_t* __restrict__ col_ind,
              int32_t* __restrict__ col_nnz, int64_t* __restrict__ col_ptr,
              uint8_t* __restrict__ loc, void* __restrict__ val,
-             const float* __restrict__ row_scale, int64_t* __restrict__ kblk_ptr) {
+             const float* __restrict__ row_scale, int64_t* __restrict__ kblk_ptr,
+             int64_t nrec_cap, uint32_t* __restrict__ rec) {
   const int64_t total = P * S;
   const int64_t nkb = (S + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
   const int64_t f0 = (int64_t)blockIdx.x * kPackTile;
-  Pair carry{tile_offs[2 * blockIdx.x], tile_offs[2 * blockIdx.x + 1]};
+  Tri carry{tile_offs[3 * blockIdx.x], tile_offs[3 * blockIdx.x + 1],
+            tile_offs[3 * blockIdx.x + 2]};
   // The tile is visited as four rows of 256 flattened indices; within a row
   // thread x holds f0 + 256*j + x, so a block scan per row plus the carry of
   // the rows before gives the exclusive prefix in flattened order.
@@ -185,21 +212,25 @@ k_pack_write(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
   for (int j = 0; j < kPackTile / kPackThreads; ++j) {
     const int64_t f = f0 + (int64_t)kPackThreads * j + threadIdx.x;
     const int c = (f < total) ? counts[f] : 0;
-    Pair tot;
-    Pair e = block_excl_scan(Pair{c, c != 0}, &tot);
+    Tri tot;
+    Tri e = block_excl_scan(Tri{c, c != 0, n_records(c)}, &tot);
     const int64_t nz_off = carry.a + e.a;
     const int64_t col_slot = carry.b + e.b;
+    const int64_t rec_off = carry.c + e.c;
     carry.a += tot.a;
     carry.b += tot.b;
+    carry.c += tot.c;
     if (f >= total) continue;
     const int64_t p = f / S, k = f - p * S;
     if (k == 0) {
       panel_nz_ptr[p] = nz_off;
       panel_col_ptr[p] = col_slot;
     }
-    // the exclusive column prefix at a block start is the first kept column
-    // of the panel with k >= that start (or the panel's end)
-    if (k % ROSKO_KSTEP == 0) kblk_ptr[p * nkb + k / ROSKO_KSTEP] = col_slot;
+    // the exclusive record prefix at a block start is the first record of
+    // the panel with k >= that start (or the panel's end); at k = 0 it is
+    // also the end of the previous panel
+    if (k % ROSKO_KSTEP == 0) kblk_ptr[p * (nkb + 1) + k / ROSKO_KSTEP] = rec_off;
+    if (k == 0 && p > 0) kblk_ptr[(p - 1) * (nkb + 1) + nkb] = rec_off;
     if (c == 0) continue;
     if (col_slot < ncols_cap) {
       col_ind[col_slot] = (int32_t)k;
@@ -210,21 +241,47 @@ k_pack_write(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
     const int rows = (int)((R - r0) < mr ? (R - r0) : mr);
     const float* col = A + r0 * lda + k;
     int64_t z = nz_off;
+    // column records: header, row bytes, FP32 values (unused slots zero)
+    int in_rec = 0;
+    int64_t r = rec_off;
+    uint32_t lw[3] = {0u, 0u, 0u};
+    auto flush = [&](int cnt) {
+      if (r < nrec_cap) {
+        uint32_t* d = rec + r * 16;
+        d[0] = ((uint32_t)k << 8) | (uint32_t)cnt;
+        d[1] = lw[0];
+        d[2] = lw[1];
+        d[3] = lw[2];
+        for (int t = cnt; t < kRecVals; ++t) d[4 + t] = 0u;
+      }
+      lw[0] = lw[1] = lw[2] = 0u;
+      ++r;
+    };
     for (int i = 0; i < rows; ++i) {
       const float x = col[(int64_t)i * lda];
       if (!kept(x)) continue;
+      uint32_t vbits;
+      if (DT == ROSKO_F32) {
+        vbits = __float_as_uint(x);
+      } else if (DT == ROSKO_BF16) {
+        const uint16_t h = enc_bf16(x);
+        vbits = dec_bf16(h);
+        if (z < nnz_cap) reinterpret_cast<uint16_t*>(val)[z] = h;
+      } else {
+        const uint8_t q = enc_fp8(__fdiv_rn(x, row_scale[r0 + i]));
+        vbits = dec_fp8(q);
+        if (z < nnz_cap) reinterpret_cast<uint8_t*>(val)[z] = q;
+      }
       if (z < nnz_cap) {
         loc[z] = (uint8_t)i;
-        if (DT == ROSKO_F32) {
-          reinterpret_cast<float*>(val)[z] = x;
-        } else if (DT == ROSKO_BF16) {
-          reinterpret_cast<uint16_t*>(val)[z] = enc_bf16(x);
-        } else {
-          reinterpret_cast<uint8_t*>(val)[z] = enc_fp8(__fdiv_rn(x, row_scale[r0 + i]));
-        }
+        if (DT == ROSKO_F32) reinterpret_cast<float*>(val)[z] = x;
       }
+      lw[in_rec >> 2] |= (uint32_t)i << (8 * (in_rec & 3));
+      if (r < nrec_cap) rec[r * 16 + 4 + in_rec] = vbits;
       ++z;
+      if (++in_rec == kRecVals) { flush(kRecVals); in_rec = 0; }
     }
+    if (in_rec) flush(in_rec);
   }
 }
 
@@ -281,8 +338,8 @@ PackWs pack_ws_layout(int64_t R, int64_t S, int32_t mr, bool transpose) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = (size_t)round_up(off + bytes, 256); return o; };
   L.counts = take(sizeof(int32_t) * (size_t)(L.P * S));
-  L.tile_sums = take(sizeof(int64_t) * 2 * (size_t)L.NT);
-  L.tile_offs = take(sizeof(int64_t) * 2 * (size_t)L.NT);
+  L.tile_sums = take(sizeof(int64_t) * 3 * (size_t)L.NT);
+  L.tile_offs = take(sizeof(int64_t) * 3 * (size_t)L.NT);
   L.totals = take(sizeof(int64_t) * 4);
   L.transposed = transpose ? take(sizeof(float) * (size_t)(R * S)) : 0;
   L.bytes = off;
@@ -308,8 +365,9 @@ int32_t launch_pack_count_scan(const float* A, int64_t R, int64_t S, int64_t lda
   }
   hipLaunchKernelGGL(k_pack_scan, dim3(1), dim3(1024), 0, s, tsum, toff, L.NT, totals, L.P, S,
                      out ? out->nnz_cap : INT64_MAX, out ? out->ncols_cap : INT64_MAX,
+                     out ? out->nrec_cap : INT64_MAX,
                      out ? out->panel_nz_ptr : nullptr, out ? out->panel_col_ptr : nullptr,
-                     out ? out->col_ptr : nullptr);
+                     out ? out->col_ptr : nullptr, out ? out->kblk_ptr : nullptr);
   ROSKO_LAUNCH_CHECK("k_pack_scan");
   return ROSKO_OK;
 }
@@ -325,7 +383,8 @@ int32_t launch_pack_write(const float* A, int64_t R, int64_t S, int64_t lda, int
   hipLaunchKernelGGL(k_pack_write<DT>, dim3((unsigned)L.NT), dim3(kPackThreads), 0, s, A, R, \
                      S, lda, mr, L.P, counts, toff, out->nnz_cap, out->ncols_cap,            \
                      out->panel_nz_ptr, out->panel_col_ptr, out->col_ind, out->col_nnz,      \
-                     out->col_ptr, out->loc, out->val, out->row_scale, out->kblk_ptr)
+                     out->col_ptr, out->loc, out->val, out->row_scale, out->kblk_ptr,       \
+                     out->nrec_cap, out->rec)
   if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_F32);
   else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_BF16);
   else ROSKO_WRITE(ROSKO_FP8_E4M3);

@@ -148,13 +148,8 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
                            int64_t ldb, float* C, int64_t ldc, int32_t beta,
                            const rosko_plan& plan, float* ws, size_t ws_bytes, hipStream_t s) {
   SpmmArgs g{};
-  g.panel_col_ptr = A->panel_col_ptr;
-  g.col_ind = A->col_ind;
-  g.col_nnz = A->col_nnz;
-  g.col_ptr = A->col_ptr;
-  g.loc = A->loc;
-  g.val = A->val;
-  g.row_scale = A->row_scale;
+  g.rec = A->rec;
+  g.row_scale = (A->val_dtype == ROSKO_FP8_E4M3) ? A->row_scale : nullptr;
   g.kblk_ptr = A->kblk_ptr;
   g.B = B;
   g.C = C;
@@ -182,13 +177,8 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
     }
   }
   const int H = tile_height(A->mr);
-  const bool bf = (b_dtype == ROSKO_BF16);
-  int32_t st;
-  switch (A->val_dtype) {
-    case ROSKO_F32: st = bf ? spmm_dispatch_f32_bf16(g, H, V, G, s) : spmm_dispatch_f32_f32(g, H, V, G, s); break;
-    case ROSKO_BF16: st = bf ? spmm_dispatch_bf16_bf16(g, H, V, G, s) : spmm_dispatch_bf16_f32(g, H, V, G, s); break;
-    default: st = bf ? spmm_dispatch_fp8_bf16(g, H, V, G, s) : spmm_dispatch_fp8_f32(g, H, V, G, s); break;
-  }
+  const int32_t st = (b_dtype == ROSKO_BF16) ? spmm_dispatch_bbf16(g, H, V, G, s)
+                                             : spmm_dispatch_bf32(g, H, V, G, s);
   if (st != ROSKO_OK || g.k_split == 1) return st;
   const int64_t blocks = std::min<int64_t>(ceil_div(A->M * N, 256), 4096);
   hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)blocks), dim3(256), 0, s, ws, g.k_split,

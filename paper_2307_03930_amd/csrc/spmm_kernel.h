@@ -14,59 +14,69 @@ struct Tile { f32x32 t[NT]; };
 
 #define RK_STR2(x) #x
 #define RK_STR(x) RK_STR2(x)
-#define RK_FMA(REG, BOP) "v_fma_f32 v" RK_STR(REG) ", %[a], %[" BOP "], v" RK_STR(REG) "\n\t"
-#define RK_ON "s_set_gpr_idx_on %[r], gpr_idx(SRC2,DST)\n\t"
+// acc(row M0, column j) += a * b_j, with relative addressing of the addend
+// and the result; REG is the VGPR holding row 0 of column j.
+#define RK_FMA(REG, A, B) "v_fma_f32 v" RK_STR(REG) ", %[" A "], %[" B "], v" RK_STR(REG) "\n\t"
 #define RK_OFF "s_set_gpr_idx_off"
 #define RK_OUT1(T) "+{v[64:95]}"(T.t[0])
 #define RK_OUT2(T) "+{v[64:95]}"(T.t[0]), "+{v[96:127]}"(T.t[1])
 #define RK_OUT4(T) \
   "+{v[64:95]}"(T.t[0]), "+{v[96:127]}"(T.t[1]), "+{v[128:159]}"(T.t[2]), "+{v[160:191]}"(T.t[3])
+#define RK_IN4 [b0] "v"(b[0]), [b1] "v"(b[1]), [b2] "v"(b[2]), [b3] "v"(b[3])
+#define RK_IN2 [b0] "v"(b[0]), [b1] "v"(b[1])
+#define RK_IN1 [b0] "v"(b[0])
 
-// acc(row r, column j) += a * b[j] for j < V; r already masked to MR-1.
-template <int MR, int V> struct Fma;
+// Rec<MR, V>::run applies all values (1..12) of one column record to the
+// register tile in a single asm block: the record's three row words w1..w3
+// (bytes already masked to MR-1) feed s_set_gpr_idx_on one byte at a time,
+// and the block ends early, through its own branch, after `cnt` values.
+// One asm site per record keeps the tile in its pinned registers (several
+// sites in different branches made the allocator shuttle the tile around).
+// Index mode is off again at the end of the block.
+template <int MR, int V> struct Rec;
 
-#define RK_DEF_FMA4(MR_, NT_, R0, R1, R2, R3)                                            \
-  template <> struct Fma<MR_, 4> {                                                      \
-    static __device__ __forceinline__ void run(Tile<NT_>& T, uint32_t r, float a,       \
-                                               const float* b) {                       \
-      asm volatile(RK_ON RK_FMA(R0, "b0") RK_FMA(R1, "b1") RK_FMA(R2, "b2")             \
-                       RK_FMA(R3, "b3") RK_OFF                                          \
-                   : RK_OUT##NT_(T)                                                     \
-                   : [r] "s"(r), [a] "s"(a), [b0] "v"(b[0]), [b1] "v"(b[1]),            \
-                     [b2] "v"(b[2]), [b3] "v"(b[3])                                     \
-                   : "m0");                                                             \
-    }                                                                                   \
-  };
-#define RK_DEF_FMA2(MR_, NT_, R0, R1)                                                    \
-  template <> struct Fma<MR_, 2> {                                                      \
-    static __device__ __forceinline__ void run(Tile<NT_>& T, uint32_t r, float a,       \
-                                               const float* b) {                       \
-      asm volatile(RK_ON RK_FMA(R0, "b0") RK_FMA(R1, "b1") RK_OFF                       \
-                   : RK_OUT##NT_(T)                                                     \
-                   : [r] "s"(r), [a] "s"(a), [b0] "v"(b[0]), [b1] "v"(b[1])             \
-                   : "m0");                                                             \
-    }                                                                                   \
-  };
-#define RK_DEF_FMA1(MR_, NT_)                                                            \
-  template <> struct Fma<MR_, 1> {                                                      \
-    static __device__ __forceinline__ void run(Tile<NT_>& T, uint32_t r, float a,       \
-                                               const float* b) {                       \
-      asm volatile(RK_ON RK_FMA(64, "b0") RK_OFF                                         \
-                   : RK_OUT##NT_(T)                                                     \
-                   : [r] "s"(r), [a] "s"(a), [b0] "v"(b[0])                             \
-                   : "m0");                                                             \
-    }                                                                                   \
+#define RK_ON1 "s_set_gpr_idx_on %[w1], gpr_idx(SRC2,DST)\n\t"
+#define RK_ON2 "s_set_gpr_idx_on %[w2], gpr_idx(SRC2,DST)\n\t"
+#define RK_ON3 "s_set_gpr_idx_on %[w3], gpr_idx(SRC2,DST)\n\t"
+#define RK_SH(W) "s_lshr_b32 %[" W "], %[" W "], 8\n\t"
+#define RK_IF(N) "s_cmp_lt_u32 %[cnt], " #N "\n\ts_cbranch_scc1 .Lrk_end%=\n\t"
+#define RK_BODY(FL)                                                                   \
+  RK_ON1 FL("a0") RK_IF(2) RK_SH("w1") RK_ON1 FL("a1") RK_IF(3) RK_SH("w1") RK_ON1  \
+  FL("a2") RK_IF(4) RK_SH("w1") RK_ON1 FL("a3")                                     \
+  RK_IF(5) RK_ON2 FL("a4") RK_IF(6) RK_SH("w2") RK_ON2 FL("a5") RK_IF(7) RK_SH("w2") \
+  RK_ON2 FL("a6") RK_IF(8) RK_SH("w2") RK_ON2 FL("a7")                              \
+  RK_IF(9) RK_ON3 FL("a8") RK_IF(10) RK_SH("w3") RK_ON3 FL("a9") RK_IF(11)           \
+  RK_SH("w3") RK_ON3 FL("a10") RK_IF(12) RK_SH("w3") RK_ON3 FL("a11")               \
+  ".Lrk_end%=:\n\t" RK_OFF
+
+#define RK_REC(MR_, V_, NT_, FL, IN)                                                      \
+  template <> struct Rec<MR_, V_> {                                                      \
+    static __device__ __forceinline__ void run(Tile<NT_>& T, uint32_t cnt, uint32_t w1,  \
+                                               uint32_t w2, uint32_t w3, const float* a, \
+                                               const float* b) {                         \
+      asm volatile(RK_BODY(FL)                                                           \
+                   : RK_OUT##NT_(T), [w1] "+s"(w1), [w2] "+s"(w2), [w3] "+s"(w3)          \
+                   : [cnt] "s"(cnt), [a0] "s"(a[0]), [a1] "s"(a[1]), [a2] "s"(a[2]),      \
+                     [a3] "s"(a[3]), [a4] "s"(a[4]), [a5] "s"(a[5]), [a6] "s"(a[6]),      \
+                     [a7] "s"(a[7]), [a8] "s"(a[8]), [a9] "s"(a[9]), [a10] "s"(a[10]),    \
+                     [a11] "s"(a[11]), IN                                                \
+                   : "m0", "scc");                                                       \
+    }                                                                                    \
   };
 
-RK_DEF_FMA4(8, 1, 64, 72, 80, 88)
-RK_DEF_FMA4(16, 2, 64, 80, 96, 112)
-RK_DEF_FMA4(32, 4, 64, 96, 128, 160)
-RK_DEF_FMA2(16, 1, 64, 80)
-RK_DEF_FMA2(32, 2, 64, 96)
-RK_DEF_FMA2(64, 4, 64, 128)
-RK_DEF_FMA1(32, 1)
-RK_DEF_FMA1(64, 2)
-RK_DEF_FMA1(128, 4)
+#define RK_FL_8x4(A) RK_FMA(64, A, "b0") RK_FMA(72, A, "b1") RK_FMA(80, A, "b2") RK_FMA(88, A, "b3")
+#define RK_FL_16x4(A) RK_FMA(64, A, "b0") RK_FMA(80, A, "b1") RK_FMA(96, A, "b2") RK_FMA(112, A, "b3")
+#define RK_FL_32x4(A) RK_FMA(64, A, "b0") RK_FMA(96, A, "b1") RK_FMA(128, A, "b2") RK_FMA(160, A, "b3")
+#define RK_FL_32x2(A) RK_FMA(64, A, "b0") RK_FMA(96, A, "b1")
+#define RK_FL_64x2(A) RK_FMA(64, A, "b0") RK_FMA(128, A, "b1")
+#define RK_FL_128x1(A) RK_FMA(64, A, "b0")
+
+RK_REC(8, 4, 1, RK_FL_8x4, RK_IN4)
+RK_REC(16, 4, 2, RK_FL_16x4, RK_IN4)
+RK_REC(32, 4, 4, RK_FL_32x4, RK_IN4)
+RK_REC(32, 2, 2, RK_FL_32x2, RK_IN2)
+RK_REC(64, 2, 4, RK_FL_64x2, RK_IN2)
+RK_REC(128, 1, 4, RK_FL_128x1, RK_IN1)
 
 template <int MR, int V> constexpr int tile_nt() { return (MR * V) / 32; }
 
@@ -78,68 +88,6 @@ using cptr = const __attribute__((address_space(4))) T*;
 template <typename T>
 __device__ __forceinline__ cptr<T> as_const(const void* p) {
   return (cptr<T>)(p);
-}
-
-// ----------------------------------------------------------- value decode
-// Packed value z as FP32 (FP8: the code's value; the row scale is applied
-// to the finished sums).  All arguments are wave-uniform, so these become
-// scalar loads and scalar bit operations.
-template <int TA> __device__ __forceinline__ float load_a(const void* val, int64_t z);
-template <> __device__ __forceinline__ float load_a<ROSKO_F32>(const void* val, int64_t z) {
-  return as_const<float>(val)[z];
-}
-template <> __device__ __forceinline__ float load_a<ROSKO_BF16>(const void* val, int64_t z) {
-  const uint32_t w = as_const<uint32_t>(val)[z >> 1];
-  return __uint_as_float((z & 1) ? (w & 0xFFFF0000u) : (w << 16));
-}
-template <> __device__ __forceinline__ float load_a<ROSKO_FP8_E4M3>(const void* val, int64_t z) {
-  const uint32_t w = as_const<uint32_t>(val)[z >> 2];
-  const uint32_t c = (w >> (8 * (uint32_t)(z & 3))) & 0xFFu;
-  const uint32_t e = (c >> 3) & 15u, m = c & 7u, s = (c & 0x80u) << 24;
-  uint32_t bits;
-  if (e == 0) bits = __float_as_uint((float)m * 0.001953125f);        // m * 2^-9
-  else if (e == 15 && m == 7) bits = 0x7FC00000u;                      // NaN
-  else bits = ((e + 120u) << 23) | (m << 20);                          // (1+m/8) 2^(e-7)
-  return __uint_as_float(bits | s);
-}
-
-// Rows within the panel (one byte each) of packed values z .. z+7, masked
-// to MR-1: two dword pairs cover the 8 bytes wherever z falls in a dword.
-template <int MR>
-__device__ __forceinline__ void load_loc8(const uint8_t* loc, int64_t z, uint32_t* r) {
-  cptr<uint32_t> lw = as_const<uint32_t>(loc);
-  const int64_t q = z >> 2;
-  const uint32_t sh = 8u * (uint32_t)(z & 3);
-  const uint64_t lo = (uint64_t)lw[q] | ((uint64_t)lw[q + 1] << 32);
-  const uint64_t hi = (uint64_t)lw[q + 1] | ((uint64_t)lw[q + 2] << 32);
-  const uint32_t L0 = (uint32_t)(lo >> sh), L1 = (uint32_t)(hi >> sh);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    r[t] = (L0 >> (8 * t)) & (uint32_t)(MR - 1);
-    r[t + 4] = (L1 >> (8 * t)) & (uint32_t)(MR - 1);
-  }
-}
-
-// ----------------------------------------------------------- B / C access
-// The same 8 row bytes, split in two steps so the scalar loads can be in
-// flight while other work runs: load_locw fetches the dwords that hold bytes
-// z .. z+7, loc_from_words extracts them (after the loads have landed).
-struct LocWords { uint32_t w0, w1, w2, sh; };
-__device__ __forceinline__ LocWords load_locw(const uint8_t* loc, int64_t z) {
-  cptr<uint32_t> lw = as_const<uint32_t>(loc);
-  const int64_t q = z >> 2;
-  return LocWords{lw[q], lw[q + 1], lw[q + 2], 8u * (uint32_t)(z & 3)};
-}
-template <int MR>
-__device__ __forceinline__ void loc_from_words(const LocWords& w, uint32_t* r) {
-  const uint64_t lo = (uint64_t)w.w0 | ((uint64_t)w.w1 << 32);
-  const uint64_t hi = (uint64_t)w.w1 | ((uint64_t)w.w2 << 32);
-  const uint32_t L0 = (uint32_t)(lo >> w.sh), L1 = (uint32_t)(hi >> w.sh);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    r[t] = (L0 >> (8 * t)) & (uint32_t)(MR - 1);
-    r[t + 4] = (L1 >> (8 * t)) & (uint32_t)(MR - 1);
-  }
 }
 
 // ------------------------------------------------------------ B staging
@@ -157,6 +105,29 @@ template <> struct Unit<ROSKO_F32, 1> { using T = float; };
 template <> struct Unit<ROSKO_BF16, 4> { using T = uint2; };
 template <> struct Unit<ROSKO_BF16, 2> { using T = uint32_t; };
 template <> struct Unit<ROSKO_BF16, 1> { using T = uint16_t; };
+
+// Element j of a unit, by value (no address taken, so no private memory).
+template <int TB, int V>
+__device__ __forceinline__ void set_elem(typename Unit<TB, V>::T& u, int j,
+                                         typename BElem<TB>::T x) {
+  if constexpr (TB == ROSKO_F32) {
+    if constexpr (V == 4) { if (j == 0) u.x = x; else if (j == 1) u.y = x; else if (j == 2) u.z = x; else u.w = x; }
+    else if constexpr (V == 2) { if (j == 0) u.x = x; else u.y = x; }
+    else u = x;
+  } else {
+    if constexpr (V == 4) {
+      if (j == 0) u.x = (u.x & 0xFFFF0000u) | x;
+      else if (j == 1) u.x = (u.x & 0x0000FFFFu) | ((uint32_t)x << 16);
+      else if (j == 2) u.y = (u.y & 0xFFFF0000u) | x;
+      else u.y = (u.y & 0x0000FFFFu) | ((uint32_t)x << 16);
+    } else if constexpr (V == 2) {
+      if (j == 0) u = (u & 0xFFFF0000u) | x;
+      else u = (u & 0x0000FFFFu) | ((uint32_t)x << 16);
+    } else {
+      u = x;
+    }
+  }
+}
 
 // Issue the load of unit `u` of B row `row` (columns col0 .. col0+V-1)
 // without consuming it: out-of-range addresses are clamped to B's first
@@ -176,14 +147,15 @@ __device__ __forceinline__ void issue_unit(const void* __restrict__ B, int64_t l
     *dst = *reinterpret_cast<const U*>(base + (in ? row * ldb + col0 : 0));
     *ok = in ? ((1u << V) - 1u) : 0u;
   } else {
-    E* e = reinterpret_cast<E*>(dst);
     uint32_t m = 0;
+    U u;
 #pragma unroll
     for (int j = 0; j < V; ++j) {
       const bool in = row_ok && col0 + j < N;
-      e[j] = base[in ? row * ldb + col0 + j : 0];
+      set_elem<TB, V>(u, j, base[in ? row * ldb + col0 + j : 0]);
       m |= in ? (1u << j) : 0u;
     }
+    *dst = u;
     *ok = m;
   }
 }
@@ -192,10 +164,25 @@ __device__ __forceinline__ void issue_unit(const void* __restrict__ B, int64_t l
 template <int TB, int V>
 __device__ __forceinline__ typename Unit<TB, V>::T masked_unit(typename Unit<TB, V>::T u,
                                                                uint32_t ok) {
-  using E = typename BElem<TB>::T;
-  E* e = reinterpret_cast<E*>(&u);
-#pragma unroll
-  for (int j = 0; j < V; ++j) e[j] = ((ok >> j) & 1u) ? e[j] : E(0);
+  if constexpr (TB == ROSKO_F32) {
+    if constexpr (V == 4) {
+      u.x = (ok & 1u) ? u.x : 0.0f; u.y = (ok & 2u) ? u.y : 0.0f;
+      u.z = (ok & 4u) ? u.z : 0.0f; u.w = (ok & 8u) ? u.w : 0.0f;
+    } else if constexpr (V == 2) {
+      u.x = (ok & 1u) ? u.x : 0.0f; u.y = (ok & 2u) ? u.y : 0.0f;
+    } else {
+      u = (ok & 1u) ? u : 0.0f;
+    }
+  } else {
+    if constexpr (V == 4) {
+      u.x &= ((ok & 1u) ? 0x0000FFFFu : 0u) | ((ok & 2u) ? 0xFFFF0000u : 0u);
+      u.y &= ((ok & 4u) ? 0x0000FFFFu : 0u) | ((ok & 8u) ? 0xFFFF0000u : 0u);
+    } else if constexpr (V == 2) {
+      u &= ((ok & 1u) ? 0x0000FFFFu : 0u) | ((ok & 2u) ? 0xFFFF0000u : 0u);
+    } else {
+      u = (ok & 1u) ? u : (uint16_t)0;
+    }
+  }
   return u;
 }
 
@@ -251,19 +238,25 @@ template <int V, int G> constexpr int stage_rows() {
   return r > 64 ? 64 : r;
 }
 
-constexpr int kChunk = 8;   // values fetched per scalar batch
+typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
 
-// Per-column state of the pipelined column walk: the column's metadata and
-// its first batch of values and row bytes.
-struct ColState {
-  int32_t k, n;
-  float a[kChunk];
-  LocWords w;
-};
+// Byte-wise mask keeping every row byte of a record word below MR.
+template <int MR> constexpr uint32_t row_mask() { return (uint32_t)(MR - 1) * 0x01010101u; }
+
+// All values (1..12) of a column record.
+template <int MR, int V, int NT>
+__device__ __forceinline__ void apply_record(Tile<NT>& acc, const u32x16& R, uint32_t cnt,
+                                             const float* b) {
+  constexpr uint32_t m = row_mask<MR>();
+  float a[12];
+#pragma unroll
+  for (int t = 0; t < 12; ++t) a[t] = __uint_as_float(R[4 + t]);
+  Rec<MR, V>::run(acc, cnt, R[1] & m, R[2] & m, R[3] & m, a, b);
+}
 
 // One workgroup: panels [pg*G, pg*G+G) (one wavefront each), columns
 // [chunk*64V, chunk*64V + 64V), K range of split s.
-template <int MR, int V, int G, int TA, int TB, bool VEC>
+template <int MR, int V, int G, int TB, bool VEC>
 __global__ void __launch_bounds__(64 * G)
 k_spmm_sparse(SpmmArgs g) {
   constexpr int NT = tile_nt<MR, V>();
@@ -283,7 +276,6 @@ k_spmm_sparse(SpmmArgs g) {
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t p = pg * G + wid;
   const bool active = p < g.n_panels;
-  constexpr bool vec = VEC;
   const int64_t col_base = chunk * (64 * V);
   const int64_t n0 = col_base + (int64_t)lane * V;
 
@@ -293,32 +285,17 @@ k_spmm_sparse(SpmmArgs g) {
   const int64_t k_lo = blo * ROSKO_KSTEP;
   const int64_t k_hi = min(g.K, bhi * ROSKO_KSTEP);
 
-  cptr<int64_t> panel_col_ptr = as_const<int64_t>(g.panel_col_ptr);
-  cptr<int32_t> col_ind = as_const<int32_t>(g.col_ind);
-  cptr<int32_t> col_nnz = as_const<int32_t>(g.col_nnz);
-  cptr<int64_t> col_ptr = as_const<int64_t>(g.col_ptr);
+  // this panel's records whose column lies in [k_lo, k_hi)
+  // (32-bit record cursor relative to the panel's first record, so the walk
+  // needs no 64-bit scalar arithmetic or VALU compares)
   cptr<int64_t> kblk = as_const<int64_t>(g.kblk_ptr);
-
-  // Column walk, carried across K blocks, software pipelined so that each
-  // column waits once, for loads issued one column earlier: the metadata
-  // (k, count) of the column after next, the first batch of values and row
-  // bytes of the next column, and the B row of the next column (read from
-  // LDS at the end of the current one).  Two state slots swap roles from
-  // column to column (the loop body is unrolled twice), so no register that
-  // a load is still filling is touched before that wait.
-  int64_t c = 0, c_end = 0, z = 0;
-  ColState SA, SB;
-  SA.k = SB.k = INT32_MAX;
-  SA.n = SB.n = 0;
+  cptr<u32x16> recs = as_const<u32x16>(g.rec);
+  uint32_t r = 0, r_end = 0;
   if (active && k_lo < k_hi) {
-    c = kblk[p * nkb + blo];
-    c_end = (bhi < nkb) ? kblk[p * nkb + bhi] : panel_col_ptr[p + 1];
-    z = col_ptr[c];
-    if (c < c_end) { SA.k = col_ind[c]; SA.n = col_nnz[c]; }
-    if (c + 1 < c_end) { SB.k = col_ind[c + 1]; SB.n = col_nnz[c + 1]; }
-#pragma unroll
-    for (int t = 0; t < kChunk; ++t) SA.a[t] = load_a<TA>(g.val, z + t);
-    SA.w = load_locw(g.loc, z);
+    const int64_t r0 = kblk[p * (nkb + 1)];
+    recs = recs + r0;
+    r = (uint32_t)(kblk[p * (nkb + 1) + blo] - r0);
+    r_end = (uint32_t)(kblk[p * (nkb + 1) + bhi] - r0);
   }
 
   Tile<NT> acc;
@@ -332,64 +309,36 @@ k_spmm_sparse(SpmmArgs g) {
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
       const int u = threadIdx.x + i * 64 * G;          // unit index in the block
-      const int r = u >> 6, uc = u & 63;
-      const int64_t row = kb0 + r;
+      const int rr = u >> 6, uc = u & 63;
+      const int64_t row = kb0 + rr;
       issue_unit<TB, V, VEC>(g.B, g.ldb, row, row < k_hi, col_base + (int64_t)uc * V, g.N,
                              &regs[i], &okbits[i]);
     }
   };
 
+  // Record walk.  The record of the current column was requested one column
+  // earlier (two slots swap roles from column to column, so no register a
+  // load is still filling is touched early): wait for it, read the B row its
+  // column selects from LDS, request the next record, apply the values.
+  // Returns false when the walk leaves this K block or the panel's range;
+  // the current record then stays in X.
   float b[V];
-  // One column: X holds the current column, Y.k/Y.n the next column's
-  // metadata.  Returns false when the next column is past this K block or
-  // past the panel's range (its state is then in Y).
-  auto column = [&](ColState& X, ColState& Y, const U* buf, int64_t kb0, int64_t kb1) -> bool {
-    // Everything this column needs (its B row, metadata, first values) was
-    // requested one column ago: wait here, so the prefetch issued next stays
-    // in flight during the FMAs (scalar loads retire out of order, so any
-    // later wait would be a full lgkmcnt(0) draining the prefetch too).
-    // 0xC07F: lgkmcnt 0, vmcnt and expcnt unrestricted.
-    __builtin_amdgcn_s_waitcnt(0xC07F);
-    const int32_t ncur = X.n;
-    uint32_t rv[kChunk];
-    loc_from_words<MR>(X.w, rv);
-    // prefetch: first values of column c+1, metadata of column c+2
-#pragma unroll
-    for (int t = 0; t < kChunk; ++t) Y.a[t] = load_a<TA>(g.val, z + ncur + t);
-    Y.w = load_locw(g.loc, z + ncur);
-    if (c + 2 < c_end) { X.k = col_ind[c + 2]; X.n = col_nnz[c + 2]; }
-    else { X.k = INT32_MAX; X.n = 0; }
-#pragma unroll
-    for (int t = 0; t < kChunk; ++t) {
-      if (t < ncur) {
-        const uint32_t r = __builtin_amdgcn_readfirstlane(rv[t]);
-        const float a = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(X.a[t])));
-        Fma<MR, V>::run(acc, r, a, b);
-      }
-    }
-    for (int base = kChunk; base < ncur; base += kChunk) {
-      float ax[kChunk];
-      uint32_t rx[kChunk];
-#pragma unroll
-      for (int t = 0; t < kChunk; ++t) ax[t] = load_a<TA>(g.val, z + base + t);
-      loc_from_words<MR>(load_locw(g.loc, z + base), rx);
-      const int rem = ncur - base;
-#pragma unroll
-      for (int t = 0; t < kChunk; ++t) {
-        if (t < rem) {
-          const uint32_t r = __builtin_amdgcn_readfirstlane(rx[t]);
-          const float a = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(ax[t])));
-          Fma<MR, V>::run(acc, r, a, b);
-        }
-      }
-    }
-    z += ncur;
-    ++c;
-    if (c >= c_end || Y.k >= kb1) return false;
-    unit_to_float<TB, V>(buf[(Y.k - kb0) * 64 + lane], b);
-    return true;
+  auto column = [&](u32x16& X, u32x16& Y, const U* buf, int32_t kb0, int32_t kb1) -> bool {
+    __builtin_amdgcn_s_waitcnt(0xC07F);                 // lgkmcnt(0): X has landed
+    const uint32_t hdr = X[0];
+    const int32_t k = (int32_t)(hdr >> 8);
+    const uint32_t cnt = hdr & 0xFFu;
+    if (k >= kb1) return false;
+    unit_to_float<TB, V>(buf[(k - kb0) * 64 + lane], b);
+    __builtin_amdgcn_s_waitcnt(0xC07F);                 // the B row (no load pending)
+    if (r + 1 < r_end) Y = recs[r + 1];                 // in flight during the FMAs
+    apply_record<MR, V>(acc, X, cnt, b);
+    ++r;
+    return r < r_end;
   };
 
+  u32x16 RA, RB;
+  if (r < r_end) RA = recs[r];
   if (nblk > 0) fetch(k_lo);
   for (int64_t ib = 0; ib < nblk; ++ib) {
     U* buf = stage + (ib & 1) * (KB * 64);
@@ -398,14 +347,12 @@ k_spmm_sparse(SpmmArgs g) {
     __syncthreads();
     const int64_t kb0 = k_lo + ib * KB;
     if (ib + 1 < nblk) fetch(kb0 + KB);                // next block in flight
-    const int64_t kb1 = min(kb0 + KB, k_hi);
-    if (active && c < c_end && SA.k < kb1) {
-      unit_to_float<TB, V>(buf[(SA.k - kb0) * 64 + lane], b);
+    const int32_t kb0_32 = (int32_t)kb0;
+    const int32_t kb1 = (int32_t)min(kb0 + KB, k_hi);
+    if (active && r < r_end) {
       while (true) {
-        // after a stop in the first half the current column lives in SB and
-        // the next column's metadata in SA: swap so the walk resumes from SA
-        if (!column(SA, SB, buf, kb0, kb1)) { ColState t = SA; SA = SB; SB = t; break; }
-        if (!column(SB, SA, buf, kb0, kb1)) break;
+        if (!column(RA, RB, buf, kb0_32, kb1)) break;
+        if (!column(RB, RA, buf, kb0_32, kb1)) { RA = RB; break; }
       }
     }
   }
@@ -414,23 +361,24 @@ k_spmm_sparse(SpmmArgs g) {
   // ---- epilogue: one split -> C (row scale, beta); several -> partials
   const int rows = (int)min((int64_t)g.mr, g.M - p * g.mr);
   cptr<float> row_scale = as_const<float>(g.row_scale);
+  const bool scaled = g.row_scale != nullptr;
 #pragma unroll
-  for (int r = 0; r < MR; ++r) {
-    if (r < rows) {
-      const int64_t row = p * g.mr + r;
+  for (int q = 0; q < MR; ++q) {
+    if (q < rows) {
+      const int64_t row = p * g.mr + q;
       float v[V];
 #pragma unroll
       for (int j = 0; j < V; ++j) {
-        const int idx = j * MR + r;
+        const int idx = j * MR + q;
         v[j] = acc.t[idx >> 5][idx & 31];
       }
       if (g.k_split == 1) {
-        if (TA == ROSKO_FP8_E4M3) {
+        if (scaled) {
           const float sc = row_scale[row];
 #pragma unroll
           for (int j = 0; j < V; ++j) v[j] *= sc;
         }
-        store_c<V>(g.C, row * g.ldc, n0, g.N, vec, v, g.beta);
+        store_c<V>(g.C, row * g.ldc, n0, g.N, VEC, v, g.beta);
       } else {
         store_c<V>(g.ws, (s * g.M + row) * g.N, n0, g.N, g.ws_vec != 0, v, 0);
       }
@@ -438,7 +386,7 @@ k_spmm_sparse(SpmmArgs g) {
   }
 }
 
-template <int MR, int V, int G, int TA, int TB>
+template <int MR, int V, int G, int TB>
 int32_t launch_one(const SpmmArgs& g, hipStream_t st) {
   const int64_t n_pg = (g.n_panels + G - 1) / G;
   const int64_t nb = n_pg * g.n_chunks * g.k_split;
@@ -450,22 +398,22 @@ int32_t launch_one(const SpmmArgs& g, hipStream_t st) {
   constexpr int KB = stage_rows<V, G>();
   const size_t lds = 2 * (size_t)KB * 64 * sizeof(typename Unit<TB, V>::T);
   if (g.vec)
-    hipLaunchKernelGGL((k_spmm_sparse<MR, V, G, TA, TB, true>), dim3((unsigned)nb), dim3(64 * G),
-                       lds, st, g);
+    hipLaunchKernelGGL((k_spmm_sparse<MR, V, G, TB, true>), dim3((unsigned)nb), dim3(64 * G), lds,
+                       st, g);
   else
-    hipLaunchKernelGGL((k_spmm_sparse<MR, V, G, TA, TB, false>), dim3((unsigned)nb),
-                       dim3(64 * G), lds, st, g);
+    hipLaunchKernelGGL((k_spmm_sparse<MR, V, G, TB, false>), dim3((unsigned)nb), dim3(64 * G),
+                       lds, st, g);
   ROSKO_LAUNCH_CHECK("k_spmm_sparse");
   return ROSKO_OK;
 }
 
-template <int MR, int V, int TA, int TB>
+template <int MR, int V, int TB>
 int32_t dispatch_g(const SpmmArgs& g, int G, hipStream_t s) {
   switch (G) {
-    case 1: return launch_one<MR, V, 1, TA, TB>(g, s);
-    case 2: return launch_one<MR, V, 2, TA, TB>(g, s);
-    case 4: return launch_one<MR, V, 4, TA, TB>(g, s);
-    case 8: return launch_one<MR, V, 8, TA, TB>(g, s);
+    case 1: return launch_one<MR, V, 1, TB>(g, s);
+    case 2: return launch_one<MR, V, 2, TB>(g, s);
+    case 4: return launch_one<MR, V, 4, TB>(g, s);
+    case 8: return launch_one<MR, V, 8, TB>(g, s);
     default: break;
   }
   set_error("unsupported panels per workgroup %d (1, 2, 4 or 8)", G);
@@ -474,14 +422,14 @@ int32_t dispatch_g(const SpmmArgs& g, int G, hipStream_t s) {
 
 // Supported (tile height, columns per lane) pairs keep the register tile at
 // 32, 64 or 128 VGPRs.
-template <int TA, int TB>
+template <int TB>
 int32_t dispatch_tile(const SpmmArgs& g, int H, int V, int G, hipStream_t s) {
-  if (H == 8 && V == 4) return dispatch_g<8, 4, TA, TB>(g, G, s);
-  if (H == 16 && V == 4) return dispatch_g<16, 4, TA, TB>(g, G, s);
-  if (H == 32 && V == 4) return dispatch_g<32, 4, TA, TB>(g, G, s);
-  if (H == 32 && V == 2) return dispatch_g<32, 2, TA, TB>(g, G, s);
-  if (H == 64 && V == 2) return dispatch_g<64, 2, TA, TB>(g, G, s);
-  if (H == 128 && V == 1) return dispatch_g<128, 1, TA, TB>(g, G, s);
+  if (H == 8 && V == 4) return dispatch_g<8, 4, TB>(g, G, s);
+  if (H == 16 && V == 4) return dispatch_g<16, 4, TB>(g, G, s);
+  if (H == 32 && V == 4) return dispatch_g<32, 4, TB>(g, G, s);
+  if (H == 32 && V == 2) return dispatch_g<32, 2, TB>(g, G, s);
+  if (H == 64 && V == 2) return dispatch_g<64, 2, TB>(g, G, s);
+  if (H == 128 && V == 1) return dispatch_g<128, 1, TB>(g, G, s);
   set_error("unsupported register tile: height %d with %d columns per lane", H, V);
   return ROSKO_EUNSUPPORTED;
 }

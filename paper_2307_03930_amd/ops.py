@@ -18,9 +18,6 @@ from . import _lib as L
 DTYPES = {"f32": L.ROSKO_F32, "bf16": L.ROSKO_BF16, "fp8": L.ROSKO_FP8_E4M3}
 _VAL_TORCH = {L.ROSKO_F32: torch.float32, L.ROSKO_BF16: torch.int16,
               L.ROSKO_FP8_E4M3: torch.uint8}
-# reads of a column batch may run up to 8 values / 12 bytes past a column's
-# end, so value and row arrays carry this many spare entries
-SLACK = L.ROSKO_READ_SLACK
 
 
 def _stream_ptr(stream=None) -> C.c_void_p:
@@ -48,6 +45,7 @@ class PackedMatrix:
     val_dtype: int
     nnz: int
     ncols: int
+    nrec: int
     panel_nz_ptr: torch.Tensor
     panel_col_ptr: torch.Tensor
     col_ind: torch.Tensor
@@ -57,6 +55,7 @@ class PackedMatrix:
     val: torch.Tensor
     row_scale: torch.Tensor | None
     kblk_ptr: torch.Tensor
+    rec: torch.Tensor
 
     @property
     def n_panels(self) -> int:
@@ -66,8 +65,8 @@ class PackedMatrix:
         s = L.RoskoPacked()
         s.M, s.K, s.mr, s.n_panels = self.M, self.K, self.mr, self.n_panels
         s.val_dtype = self.val_dtype
-        s.nnz_cap, s.ncols_cap = self.nnz, self.ncols
-        s.nnz, s.ncols = self.nnz, self.ncols
+        s.nnz_cap, s.ncols_cap, s.nrec_cap = self.nnz, self.ncols, self.nrec
+        s.nnz, s.ncols, s.nrec = self.nnz, self.ncols, self.nrec
         s.panel_nz_ptr = self.panel_nz_ptr.data_ptr()
         s.panel_col_ptr = self.panel_col_ptr.data_ptr()
         s.col_ind = self.col_ind.data_ptr()
@@ -77,6 +76,7 @@ class PackedMatrix:
         s.val = self.val.data_ptr()
         s.row_scale = 0 if self.row_scale is None else self.row_scale.data_ptr()
         s.kblk_ptr = self.kblk_ptr.data_ptr()
+        s.rec = self.rec.data_ptr()
         return s
 
     def values(self) -> torch.Tensor:
@@ -97,35 +97,36 @@ def _check_dense(A: torch.Tensor, name: str):
         raise ValueError(f"{name} must be row-major with unit column stride")
 
 
-def _alloc(M, K, mr, dtype, nnz, ncols, device):
+def _alloc(M, K, mr, dtype, nnz, ncols, nrec, device):
     P = (M + mr - 1) // mr
+    nkb = (K + L.ROSKO_KSTEP - 1) // L.ROSKO_KSTEP
     i64, i32 = torch.int64, torch.int32
     return PackedMatrix(
-        M=M, K=K, mr=mr, val_dtype=dtype, nnz=nnz, ncols=ncols,
+        M=M, K=K, mr=mr, val_dtype=dtype, nnz=nnz, ncols=ncols, nrec=nrec,
         panel_nz_ptr=torch.empty(P + 1, dtype=i64, device=device),
         panel_col_ptr=torch.empty(P + 1, dtype=i64, device=device),
         col_ind=torch.empty(max(ncols, 1), dtype=i32, device=device),
         col_nnz=torch.empty(max(ncols, 1), dtype=i32, device=device),
         col_ptr=torch.empty(ncols + 1, dtype=i64, device=device),
-        loc=torch.zeros(nnz + SLACK, dtype=torch.uint8, device=device),
-        val=torch.zeros(nnz + SLACK, dtype=_VAL_TORCH[dtype], device=device),
+        loc=torch.zeros(max(nnz, 1), dtype=torch.uint8, device=device),
+        val=torch.zeros(max(nnz, 1), dtype=_VAL_TORCH[dtype], device=device),
         row_scale=(torch.empty(max(M, 1), dtype=torch.float32, device=device)
                    if dtype == L.ROSKO_FP8_E4M3 else None),
-        kblk_ptr=torch.empty(max(P * ((K + L.ROSKO_KSTEP - 1) // L.ROSKO_KSTEP), 1),
-                             dtype=i64, device=device),
+        kblk_ptr=torch.empty(max(P * (nkb + 1), 1), dtype=i64, device=device),
+        rec=torch.empty((max(nrec, 1), 16), dtype=torch.int32, device=device),
     )
 
 
 def pack_query(A: torch.Tensor, mr: int, ws: torch.Tensor | None = None):
-    """(nnz, ncols) of packing A with panel height mr.  Synchronises."""
+    """(nnz, ncols, nrec) of packing A with panel height mr.  Synchronises."""
     _check_dense(A, "A")
     M, K = A.shape
     if ws is None:
         ws = torch.empty(max(workspace_size(M, K, mr), 1), dtype=torch.uint8, device=A.device)
-    nnz, ncols = C.c_int64(0), C.c_int64(0)
+    nnz, ncols, nrec = C.c_int64(0), C.c_int64(0), C.c_int64(0)
     L.check(L.lib().rosko_pack_query(_ptr(A), M, K, max(A.stride(0), 1), mr, _ptr(ws), ws.numel(),
-                                     _stream_ptr(), C.byref(nnz), C.byref(ncols)))
-    return int(nnz.value), int(ncols.value)
+                                     _stream_ptr(), C.byref(nnz), C.byref(ncols), C.byref(nrec)))
+    return int(nnz.value), int(ncols.value), int(nrec.value)
 
 
 def pack(A: torch.Tensor, mr: int = 32, dtype="f32") -> PackedMatrix:
@@ -134,8 +135,8 @@ def pack(A: torch.Tensor, mr: int = 32, dtype="f32") -> PackedMatrix:
     dt = _dtype_code(dtype)
     M, K = A.shape
     ws = torch.empty(max(workspace_size(M, K, mr), 1), dtype=torch.uint8, device=A.device)
-    nnz, ncols = pack_query(A, mr, ws)
-    P = _alloc(M, K, mr, dt, nnz, ncols, A.device)
+    nnz, ncols, nrec = pack_query(A, mr, ws)
+    P = _alloc(M, K, mr, dt, nnz, ncols, nrec, A.device)
     st = P.struct()
     L.check(L.lib().rosko_pack(_ptr(A), M, K, max(A.stride(0), 1), mr, dt, _ptr(ws), ws.numel(),
                                C.byref(st), _stream_ptr()))
@@ -149,12 +150,12 @@ def pack_transpose(A: torch.Tensor, mr: int = 32) -> PackedMatrix:
     M, K = A.shape
     ws = torch.empty(max(workspace_size(M, K, mr, transpose=True), 1), dtype=torch.uint8,
                      device=A.device)
-    nnz, ncols = C.c_int64(0), C.c_int64(0)
+    nnz, ncols, nrec = C.c_int64(0), C.c_int64(0), C.c_int64(0)
     L.check(L.lib().rosko_pack_transpose_query(_ptr(A), M, K, max(A.stride(0), 1), mr,
                                                _ptr(ws), ws.numel(), _stream_ptr(),
-                                               C.byref(nnz), C.byref(ncols)))
-    nnz, ncols = int(nnz.value), int(ncols.value)
-    P = _alloc(K, M, mr, L.ROSKO_F32, nnz, ncols, A.device)
+                                               C.byref(nnz), C.byref(ncols), C.byref(nrec)))
+    nnz, ncols, nrec = int(nnz.value), int(ncols.value), int(nrec.value)
+    P = _alloc(K, M, mr, L.ROSKO_F32, nnz, ncols, nrec, A.device)
     st = P.struct()
     L.check(L.lib().rosko_pack_transpose(_ptr(A), M, K, max(A.stride(0), 1), mr, L.ROSKO_F32, _ptr(ws),
                                          ws.numel(), C.byref(st), _stream_ptr()))

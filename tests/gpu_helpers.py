@@ -30,7 +30,8 @@ def packed_to_np(P: ops.PackedMatrix) -> dict:
         "col_ptr": P.col_ptr[: P.ncols + 1].cpu().numpy(),
         "loc": P.loc[: P.nnz].cpu().numpy(),
         "val": P.val[: P.nnz].cpu().numpy(),
-        "kblk_ptr": P.kblk_ptr[: P.n_panels * ((P.K + 127) // 128)].cpu().numpy(),
+        "kblk_ptr": P.kblk_ptr[: P.n_panels * ((P.K + 127) // 128 + 1)].cpu().numpy(),
+        "rec": P.rec[: P.nrec].cpu().numpy().view(np.uint32),
     }
     if P.row_scale is not None:
         out["row_scale"] = P.row_scale[: P.M].cpu().numpy()
@@ -49,7 +50,10 @@ def assert_pack_equal(P: ops.PackedMatrix, ref: O.Packed) -> None:
     assert g["val"].tobytes() == ref.val.tobytes()
     if ref.row_scale is not None:
         assert g["row_scale"].tobytes() == ref.row_scale.tobytes()
-    assert np.array_equal(g["kblk_ptr"], O.kblk_ptr(ref, 128))
+    rec, kb = O.records(ref, 128)
+    assert P.nrec == len(rec)
+    assert np.array_equal(g["kblk_ptr"], kb)
+    assert np.array_equal(g["rec"], rec)
 
 
 def err(C_hat, C_ref, scale) -> float:

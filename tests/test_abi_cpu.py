@@ -72,29 +72,33 @@ def test_query_argument_checks():
     nnz, nc = C.c_int64(0), C.c_int64(0)
     fake = C.c_void_p(0x1000)   # never dereferenced: every call below fails its checks first
     # negative size
+    nr = C.c_int64(0)
     assert lib.rosko_pack_query(fake, -1, 4, 4, 8, fake, 1 << 20, None, C.byref(nnz),
-                                C.byref(nc)) == L.ROSKO_EINVAL
+                                C.byref(nc), C.byref(nr)) == L.ROSKO_EINVAL
     # lda < K
     assert lib.rosko_pack_query(fake, 4, 8, 4, 8, fake, 1 << 20, None, C.byref(nnz),
-                                C.byref(nc)) == L.ROSKO_EINVAL
+                                C.byref(nc), C.byref(nr)) == L.ROSKO_EINVAL
     # null matrix with nonzero size
     assert lib.rosko_pack_query(None, 4, 4, 4, 8, fake, 1 << 20, None, C.byref(nnz),
-                                C.byref(nc)) == L.ROSKO_EINVAL
+                                C.byref(nc), C.byref(nr)) == L.ROSKO_EINVAL
     # workspace too small
     assert lib.rosko_pack_query(fake, 4, 4, 4, 8, fake, 1, None, C.byref(nnz),
-                                C.byref(nc)) == L.ROSKO_ESMALLBUF
+                                C.byref(nc), C.byref(nr)) == L.ROSKO_ESMALLBUF
     # null outputs
     assert lib.rosko_pack_query(fake, 4, 4, 4, 8, fake, 1 << 20, None, None,
-                                None) == L.ROSKO_EINVAL
+                                None, None) == L.ROSKO_EINVAL
+    # K too wide for the 24-bit column field of the records
+    assert lib.rosko_pack_query(fake, 4, 1 << 24, 1 << 24, 8, fake, 1 << 40, None,
+                                C.byref(nnz), C.byref(nc), C.byref(nr)) == L.ROSKO_EUNSUPPORTED
 
 
 def _packed(M, K, mr, dtype=L.ROSKO_F32, fill=True):
     s = L.RoskoPacked()
     s.M, s.K, s.mr, s.n_panels, s.val_dtype = M, K, mr, (M + mr - 1) // mr, dtype
-    s.nnz_cap, s.ncols_cap = 10, 10
+    s.nnz_cap, s.ncols_cap, s.nrec_cap = 10, 10, 10
     if fill:
         for f in ("panel_nz_ptr", "panel_col_ptr", "col_ind", "col_nnz", "col_ptr", "loc",
-                  "val", "row_scale", "kblk_ptr"):
+                  "val", "row_scale", "kblk_ptr", "rec"):
             setattr(s, f, 0x1000)
     return s
 
@@ -119,6 +123,12 @@ def test_pack_argument_checks():
     s3.val = None
     assert lib.rosko_pack(fake, 8, 8, 8, 4, L.ROSKO_F32, fake, 1 << 20, C.byref(s3),
                           None) == L.ROSKO_EINVAL
+    # null record stream
+    s5 = _packed(8, 8, 4)
+    s5.rec = None
+    assert lib.rosko_pack(fake, 8, 8, 8, 4, L.ROSKO_F32, fake, 1 << 20, C.byref(s5),
+                          None) == L.ROSKO_EINVAL
+    assert b"rec" in lib.rosko_last_error()
     # transpose packing wants the K x M shape
     s4 = _packed(8, 6, 4)
     assert lib.rosko_pack_transpose(fake, 8, 6, 6, 4, L.ROSKO_F32, fake, 1 << 20, C.byref(s4),

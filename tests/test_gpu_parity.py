@@ -101,11 +101,14 @@ def test_pack_capacity_overflow_reported():
     say("pack capacity overflow")
     A = synth.sparse_matrix(64, 256, 0.2, 506)
     Ad = dev(A)
-    nnz, ncols = ops.pack_query(Ad, 16)
-    P = ops._alloc(64, 256, 16, L.ROSKO_F32, nnz // 2, ncols // 2, Ad.device)
-    # sentinels just past the capacities (the arrays carry spare entries)
+    nnz, ncols, nrec = ops.pack_query(Ad, 16)
+    # capacities of half the need; the buffers themselves are larger, with
+    # sentinels past the capacities that must survive
+    P = ops._alloc(64, 256, 16, L.ROSKO_F32, nnz, ncols, nrec, Ad.device)
+    P.nnz, P.ncols, P.nrec = nnz // 2, ncols // 2, nrec // 2
     P.val[nnz // 2:] = 7.0
     P.loc[nnz // 2:] = 7
+    P.rec[nrec // 2:] = 7
     ws = torch.empty(ops.workspace_size(64, 256, 16), dtype=torch.uint8, device="cuda")
     st = P.struct()
     L.check(L.lib().rosko_pack(C.c_void_p(Ad.data_ptr()), 64, 256, 256, 16, L.ROSKO_F32,
@@ -114,8 +117,9 @@ def test_pack_capacity_overflow_reported():
     rc = L.lib().rosko_pack_result(C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(st),
                                    ops._stream_ptr())
     assert rc == L.ROSKO_ESMALLBUF
-    assert st.nnz == nnz and st.ncols == ncols
+    assert st.nnz == nnz and st.ncols == ncols and st.nrec == nrec
     assert bool((P.val[nnz // 2:] == 7.0).all()) and bool((P.loc[nnz // 2:] == 7).all())
+    assert bool((P.rec[nrec // 2:] == 7).all())
     # the kept prefix is still the oracle's
     ref = O.pack(A, 16)
     got = P.val[: nnz // 2].cpu().numpy()

@@ -418,16 +418,37 @@ def test_adam_first_step_closed_form():
         np.testing.assert_allclose(v[k], 0.001 * G[k] ** 2, rtol=1e-12)
 
 
-def test_kblk_ptr_against_searchsorted():
-    # independent route: per panel, np.searchsorted of the block starts in the
-    # panel's ascending col_ind list
-    for seed, mr in ((1, 8), (2, 32), (3, 13)):
-        A = synth.sparse_matrix(70, 700, 0.02, 900 + seed, "column_banded")
-        pk = O.pack(A, mr)
-        kb = O.kblk_ptr(pk, 128)
+def test_records_against_independent_rebuild():
+    # independent route: rebuild every record from a plain list of
+    # (panel, k, row, value) entries made with np.nonzero on each panel
+    for seed, mr, dt in ((1, 8, O.F32), (2, 32, O.BF16), (3, 13, O.FP8), (4, 64, O.F32)):
+        A = synth.sparse_matrix(70, 700, 0.05 if seed != 4 else 0.4, 900 + seed,
+                                "column_banded")
+        pk = O.pack(A, mr, dt)
+        rec, kb = O.records(pk, 128)
+        deq = O.unpack(pk)
+        if dt == O.FP8:
+            deq = deq / np.repeat(pk.row_scale[:, None], 700, axis=1)
+        expect, kbx = [], []
         nkb = (700 + 127) // 128
         for p in range(pk.n_panels):
-            lo, hi = pk.panel_col_ptr[p], pk.panel_col_ptr[p + 1]
-            cols = pk.col_ind[lo:hi]
-            for j in range(nkb):
-                assert kb[p * nkb + j] == lo + np.searchsorted(cols, j * 128, side="left")
+            panel = A[p * mr:(p + 1) * mr]
+            bits = panel.view(np.uint32) & np.uint32(0x7FFFFFFF)
+            ks, ms = np.nonzero(bits.T)
+            starts = []
+            for k in np.unique(ks):
+                rows = ms[ks == k]
+                for f in range(0, len(rows), 12):
+                    part = rows[f:f + 12]
+                    d = np.zeros(16, np.uint32)
+                    d[0] = (int(k) << 8) | len(part)
+                    for t, m in enumerate(part):
+                        d[1 + t // 4] |= np.uint32(int(m) << (8 * (t % 4)))
+                        d[4 + t] = np.float32(deq[p * mr + m, k]).view(np.uint32)
+                    starts.append(int(k))
+                    expect.append(d)
+            base = len(expect) - len(starts)
+            for j in range(nkb + 1):
+                kbx.append(base + int(np.searchsorted(np.array(starts, int), j * 128)))
+        assert np.array_equal(rec, np.array(expect, np.uint32).reshape(-1, 16))
+        assert np.array_equal(kb, np.array(kbx, np.int64))
