@@ -77,7 +77,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip cold/dense timings")
     ap.add_argument("--cols-per-lane", type=int, default=None)
-    ap.add_argument("--panels-per-wg", type=int, default=None)
+    ap.add_argument("--waves-per-tile", type=int, default=None)
     ap.add_argument("--k-split", type=int, default=None)
     args = ap.parse_args()
 
@@ -99,7 +99,7 @@ def main():
     N = B_np.shape[1]
     B = torch.from_numpy(B_np).to(dev)
     As = [torch.from_numpy(a).to(dev) for a in As_np]
-    plan = ops.make_plan(args.cols_per_lane, args.panels_per_wg, args.k_split)
+    plan = ops.make_plan(args.cols_per_lane, args.waves_per_tile, args.k_split)
 
     # buffers sized once (the sizing query synchronises; the step does not)
     packs, wss, Cs, sws = [], [], [], []

@@ -117,28 +117,30 @@ typedef struct rosko_packed {
 } rosko_packed;
 
 /* ---- execution plan for rosko_spmm ----------------------------------
- * A workgroup holds `panels_per_wg` panels (one wavefront each, with its C
- * tile in VGPRs) and one chunk of 64*cols_per_lane columns; it stages the B
- * rows of its K range through LDS in blocks shared by its panels.  K is cut
- * into `k_split` ranges (on ROSKO_KSTEP boundaries) handled by different
- * workgroups; with k_split > 1 their partial tiles go to the workspace and a
- * second kernel adds them in a fixed order (so results do not depend on
- * timing) and applies the FP8 row scale and beta.
- * path:          ROSKO_PATH_SPARSE (row-skipping vector kernel), or
- *                ROSKO_PATH_AUTO to let the library choose everything.
- * cols_per_lane: 1, 2 or 4.  The register tile (panel height rounded up to
- *                8/16/32/64/128, times cols_per_lane) must be one of 8x4,
- *                16x4, 32x4, 32x2, 64x2, 128x1; other pairs return
- *                ROSKO_EUNSUPPORTED.  Panel heights above 128 are packed but
- *                not multiplied by this path.
- * panels_per_wg: 1, 2, 4 or 8.
- * k_split:       1 .. ceil(K / ROSKO_KSTEP) (larger values are clamped).  */
+ * A wavefront owns one panel and one chunk of 64*cols_per_lane columns of C,
+ * with its C tile in VGPRs, and applies a run of the panel's column records.
+ * Each panel's records are cut into k_split * waves_per_tile runs of equal
+ * length.  The waves_per_tile wavefronts of one workgroup take consecutive
+ * runs and add their tiles through LDS; with k_split > 1 the workgroups'
+ * tiles go to the workspace and a second kernel adds them in a fixed order
+ * (so results do not depend on timing) and applies the FP8 row scale and
+ * beta.
+ * path:           ROSKO_PATH_SPARSE (row-skipping vector kernel), or
+ *                 ROSKO_PATH_AUTO to let the library choose everything.
+ * cols_per_lane:  1, 2 or 4.  The register tile (panel height rounded up to
+ *                 8/16/32/64/128, times cols_per_lane) must be one of 8x4,
+ *                 16x4, 32x4, 32x2, 64x2, 128x1; other pairs return
+ *                 ROSKO_EUNSUPPORTED.  Panel heights above 128 are packed but
+ *                 not multiplied by this path.
+ * waves_per_tile: 1, 2 or 4.
+ * k_split:        1 .. ROSKO_MAX_K_SPLIT (larger values are clamped).  */
 #define ROSKO_PATH_AUTO (-1)
 #define ROSKO_PATH_SPARSE 0
+#define ROSKO_MAX_K_SPLIT 64
 typedef struct rosko_plan {
   int32_t path;
   int32_t cols_per_lane;
-  int32_t panels_per_wg;
+  int32_t waves_per_tile;
   int32_t k_split;
 } rosko_plan;
 
@@ -223,7 +225,7 @@ int32_t rosko_spmm_backward(const rosko_packed *A, const rosko_packed *At, const
 /* ---- errors ----------------------------------------------------------- */
 const char *rosko_status_str(int32_t status);
 const char *rosko_last_error(void);   /* per host thread; "" if none */
-int32_t rosko_abi_version(void);      /* 1 */
+int32_t rosko_abi_version(void);      /* 2 */
 
 #ifdef __cplusplus
 }

@@ -95,7 +95,7 @@ static int32_t check_packed_for_read(const rosko_packed* A) {
 
 extern "C" {
 
-int32_t rosko_abi_version(void) { return 1; }
+int32_t rosko_abi_version(void) { return 2; }
 
 const char* rosko_last_error(void) { return g_err; }
 

@@ -75,16 +75,17 @@ struct SpmmArgs {
   float* ws;           // k_split x M x N partial tiles (k_split > 1)
   int64_t M, K, N, ldb, ldc;
   int64_t n_chunks;    // ceil(N / (64 * cols_per_lane))
+  int64_t nrec;        // records of the whole matrix (host copy), or -1
   int32_t mr, n_panels;
   int32_t beta;
   int32_t k_split;
   int32_t vec;         // B/C rows allow V-wide vector access (alignment, N % V)
   int32_t ws_vec;      // workspace rows allow V-wide vector access
 };
-// One dispatcher per B dtype; H = register-tile height, V = columns per
-// lane, G = panels (wavefronts) per workgroup.
-int32_t spmm_dispatch_bf32(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
-int32_t spmm_dispatch_bbf16(const SpmmArgs& g, int H, int V, int G, hipStream_t s);
+// One dispatcher per B dtype; MRt = register-tile height, V = columns per
+// lane, H = wavefronts per tile.
+int32_t spmm_dispatch_bf32(const SpmmArgs& g, int MRt, int V, int H, hipStream_t s);
+int32_t spmm_dispatch_bbf16(const SpmmArgs& g, int MRt, int V, int H, hipStream_t s);
 
 // Plan helpers (spmm.hip): the automatic plan, validation/normalisation of a
 // caller's plan, and the workspace a plan needs.

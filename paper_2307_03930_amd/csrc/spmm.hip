@@ -1,28 +1,33 @@
 // Row-skipping outer-product SpMM on gfx950 (Alg. 2, Sec. 4.2) -- host side.
 //
-// Kernel (spmm_kernel.h): a workgroup owns up to 8 panels (one wavefront
-// each) and one chunk of 64*V columns of C.  It walks its K range in blocks
-// of B rows that all its threads load together into LDS (double-buffered,
-// so the next block is in flight while the current one is used); each
-// wavefront then walks its panel's kept columns inside the block: it reads
-// the B row segment its column selects from LDS and, for every value of the
-// column, multiply-accumulates it into C-tile row loc.  Rows whose A entry is
-// zero are never touched -- the row skipping -- and a staged B row is reused
-// by every value of the column and by every panel of the workgroup.  The C
-// tile stays in VGPRs for the whole K range (the K-first schedule of Sec. 2.2
-// / 4.2) and is written once.
+// Kernel (spmm_kernel.h).  A wavefront owns one panel (mr rows) and one
+// chunk of 64*V columns of C, its C tile held in VGPRs for its whole run of
+// the panel's column records (the K-first schedule of Sec. 2.2 / 4.2).  Per
+// kept column it reads the B row segment the column selects (V elements per
+// lane) and, for every value of the column, multiply-accumulates it into
+// tile row loc; rows whose A entry is zero are never touched -- the row
+// skipping -- and the B segment is reused by every value of the column.
+//
+// The column's data arrives as one 64-byte record per column (packing writes
+// it beside the canonical arrays): header (k, count), row bytes, values.  A
+// wavefront loads a record as a single VGPR (lane l holds dword l & 15) and
+// the B segment with one vector load, several columns ahead of their use, so
+// a column never waits on a dependent load round trip.
 //
 // The C row is a run-time index, yet the tile must stay in registers.  The
 // tile is pinned to the fixed VGPR range v[64 : 64+MR*V) through inline-asm
-// register constraints, row r of column j at v[64 + j*MR + r].  Every value
-// of A is applied by one asm block: s_set_gpr_idx_on with the (wave-uniform)
-// row index turns on relative addressing for the FMA's addend and result,
-// V v_fma_f32 follow, and s_set_gpr_idx_off ends the mode.  The row index is
-// masked to MR-1 so the relative access can never leave the pinned range.
+// register constraints, row r of column j at v[64 + j*MR + r].  For every
+// value, s_set_gpr_idx_on with the (wave-uniform) row byte turns on relative
+// addressing of the FMA's accumulator, and V v_fmac_f32 follow whose A
+// operand is the value's lane of the record VGPR broadcast by DPP
+// row_newbcast.  Row bytes are masked to MR-1 so the relative access can
+// never leave the pinned range.
 //
-// Small M x N outputs cannot fill the GPU with whole-K tiles, so K may be cut
-// into k_split ranges; partial tiles then go to a workspace and
-// k_reduce_splits adds them in split order (no atomics, reproducible).
+// Small M x N outputs cannot fill the GPU with one wavefront per tile, so a
+// panel's records are cut into k_split * H equal runs: H wavefronts of one
+// workgroup add their tiles through LDS in a fixed order, and with
+// k_split > 1 the workgroups' tiles go to a workspace that k_reduce_splits
+// adds in split order (no atomics, so results are reproducible).
 #include <algorithm>
 
 #include "internal.h"
@@ -42,19 +47,50 @@ k_fill_zero(float* __restrict__ C, int64_t M, int64_t N, int64_t ldc) {
 
 // Split-K epilogue: C[m][n] = (beta ? C[m][n] : 0) + s_m * sum_s ws[s][m][n],
 // the partials added in split order (fixed, so the result is reproducible).
+// blockIdx.y strides over rows; a thread handles 4 consecutive columns with
+// float4 accesses when VEC (N, ldc and the pointers allow it).
+template <bool VEC>
 __global__ void __launch_bounds__(256)
 k_reduce_splits(const float* __restrict__ ws, int32_t S, int64_t M, int64_t N,
                 const float* __restrict__ row_scale, float* __restrict__ C, int64_t ldc,
                 int32_t beta) {
-  const int64_t total = M * N;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * 256) {
-    const int64_t m = i / N, n = i - m * N;
-    float acc = ws[i];
-    for (int32_t s = 1; s < S; ++s) acc += ws[(int64_t)s * total + i];
-    if (row_scale) acc *= row_scale[m];
+  const int64_t MN = M * N;
+  const int64_t n = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (n >= N) return;
+  for (int64_t m = blockIdx.y; m < M; m += gridDim.y) {
+    const float* src = ws + m * N + n;
     float* c = C + m * ldc + n;
-    *c = beta ? *c + acc : acc;
+    const float sc = row_scale ? row_scale[m] : 1.0f;
+    if (VEC) {
+      float4 acc = *reinterpret_cast<const float4*>(src);
+      int32_t s = 1;
+      for (; s + 4 <= S; s += 4) {
+        float4 x[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x[t] = *reinterpret_cast<const float4*>(src + (s + t) * MN);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          acc.x += x[t].x; acc.y += x[t].y; acc.z += x[t].z; acc.w += x[t].w;
+        }
+      }
+      for (; s < S; ++s) {
+        const float4 x = *reinterpret_cast<const float4*>(src + s * MN);
+        acc.x += x.x; acc.y += x.y; acc.z += x.z; acc.w += x.w;
+      }
+      if (row_scale) { acc.x *= sc; acc.y *= sc; acc.z *= sc; acc.w *= sc; }
+      if (beta) {
+        const float4 o = *reinterpret_cast<const float4*>(c);
+        acc.x += o.x; acc.y += o.y; acc.z += o.z; acc.w += o.w;
+      }
+      *reinterpret_cast<float4*>(c) = acc;
+    } else {
+      for (int j = 0; j < 4 && n + j < N; ++j) {
+        float acc = src[j];
+        for (int32_t s = 1; s < S; ++s) acc += src[s * MN + j];
+        if (row_scale) acc *= sc;
+        c[j] = beta ? c[j] + acc : acc;
+      }
+    }
   }
 }
 
@@ -73,7 +109,6 @@ bool tile_supported(int H, int V) {
          (H == 64 && V == 2) || (H == 128 && V == 1);
 }
 
-int64_t n_kblocks(int64_t K) { return (K + ROSKO_KSTEP - 1) / ROSKO_KSTEP; }
 
 }  // namespace
 
@@ -86,31 +121,37 @@ int32_t launch_fill_zero(float* C, int64_t M, int64_t N, int64_t ldc, hipStream_
 }
 
 // The analytic fallback plan.  The register tile is the widest the panel
-// height allows (128 accumulators per lane).  Panels of one workgroup share
-// each staged block of B rows, so a workgroup takes as many panels as exist
-// up to 8.  K is then split until the grid has about two workgroups per
-// compute unit, within the K blocks available and a workspace of at most
-// 4x the output.
+// height allows (128 accumulators per lane), narrowed when N is small.  The
+// grid should hold about two wavefronts per SIMD (2048 on 256 CUs): when the
+// (panel, chunk) tiles are fewer, each tile gets up to 4 wavefronts in its
+// workgroup, then up to 8 workgroups (k_split), as long as a wavefront keeps
+// at least kMinRun records (records per panel estimated from nrec, or from
+// nnz at about 8 values per record when nrec is unknown).
 rosko_plan auto_plan(const rosko_packed* A, int64_t N) {
   rosko_plan p{};
   p.path = ROSKO_PATH_SPARSE;
-  const int H = tile_height(A->mr);
-  p.cols_per_lane = (H <= 32) ? 4 : (H == 64 ? 2 : 1);
-  if (H == 32 && N <= 128) p.cols_per_lane = 2;
-  const int64_t P = A->n_panels;
-  p.panels_per_wg = P >= 8 ? 8 : (P >= 4 ? 4 : (P >= 2 ? 2 : 1));
-  const int64_t n_pg = ceil_div(P, p.panels_per_wg);
-  const int64_t chunks = ceil_div(N, 64 * p.cols_per_lane);
-  const int64_t target = 512;
-  int64_t S = ceil_div(target, std::max<int64_t>(1, n_pg * chunks));
-  S = std::min<int64_t>(S, std::max<int64_t>(1, n_kblocks(A->K)));
-  S = std::min<int64_t>(S, 4);
-  p.k_split = (int32_t)std::max<int64_t>(1, S);
+  const int MRt = tile_height(A->mr);
+  p.cols_per_lane = (MRt <= 32) ? 4 : (MRt == 64 ? 2 : 1);
+  if (MRt == 32 && N <= 128) p.cols_per_lane = 2;
+  const int64_t P = std::max<int64_t>(1, A->n_panels);
+  const int64_t chunks = std::max<int64_t>(1, ceil_div(N, 64 * p.cols_per_lane));
+  const int64_t tiles = P * chunks;
+  constexpr int64_t kTargetWaves = 2048, kMinRun = 48;
+  int64_t per_panel = 1 << 30;
+  if (A->nrec >= 0) per_panel = A->nrec / P;
+  else if (A->nnz >= 0) per_panel = A->nnz / (8 * P);
+  const int64_t max_parts = std::max<int64_t>(1, per_panel / kMinRun);
+  int64_t want = std::max<int64_t>(1, kTargetWaves / tiles);
+  want = std::min(want, max_parts);
+  const int H = want >= 4 ? 4 : (want >= 2 ? 2 : 1);
+  int64_t S = std::max<int64_t>(1, want / H);
+  S = std::min<int64_t>(S, 8);
+  p.waves_per_tile = H;
+  p.k_split = (int32_t)S;
   return p;
 }
 
 int32_t normalize_plan(const rosko_packed* A, int64_t N, rosko_plan* p) {
-  (void)N;
   if (p->path == ROSKO_PATH_AUTO) {
     *p = auto_plan(A, N);
     return ROSKO_OK;
@@ -119,23 +160,22 @@ int32_t normalize_plan(const rosko_packed* A, int64_t N, rosko_plan* p) {
     set_error("plan path %d not supported", p->path);
     return ROSKO_EUNSUPPORTED;
   }
-  const int H = tile_height(A->mr);
-  if (!tile_supported(H, p->cols_per_lane)) {
+  const int MRt = tile_height(A->mr);
+  if (!tile_supported(MRt, p->cols_per_lane)) {
     set_error("unsupported register tile: mr %d (height %d) with %d columns per lane", A->mr,
-              H, p->cols_per_lane);
+              MRt, p->cols_per_lane);
     return ROSKO_EUNSUPPORTED;
   }
-  const int G = p->panels_per_wg;
-  if (G != 1 && G != 2 && G != 4 && G != 8) {
-    set_error("unsupported panels per workgroup %d (1, 2, 4 or 8)", G);
+  const int H = p->waves_per_tile;
+  if (H != 1 && H != 2 && H != 4) {
+    set_error("unsupported waves per tile %d (1, 2 or 4)", H);
     return ROSKO_EUNSUPPORTED;
   }
   if (p->k_split < 1) {
     set_error("k_split %d < 1", p->k_split);
     return ROSKO_EINVAL;
   }
-  const int64_t nkb = std::max<int64_t>(1, n_kblocks(A->K));
-  if (p->k_split > nkb) p->k_split = (int32_t)nkb;
+  if (p->k_split > ROSKO_MAX_K_SPLIT) p->k_split = ROSKO_MAX_K_SPLIT;
   return ROSKO_OK;
 }
 
@@ -162,12 +202,16 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
   g.mr = A->mr;
   g.n_panels = A->n_panels;
   g.beta = beta;
-  const int V = plan.cols_per_lane, G = plan.panels_per_wg;
+  const int V = plan.cols_per_lane, H = plan.waves_per_tile;
   g.k_split = std::max(1, plan.k_split);
+  g.nrec = A->nrec;
   g.n_chunks = ceil_div(N, 64 * V);
   const size_t eb = (b_dtype == ROSKO_F32) ? 4 : 2;
+  // vector path: aligned V-wide rows, and B within the 32-bit offsets of the
+  // buffer loads; otherwise element loads with clamped indices
   g.vec = (ldb % V == 0) && (ldc % V == 0) && (N % V == 0) &&
-          ((uintptr_t)B % (eb * V) == 0) && ((uintptr_t)C % (4 * V) == 0);
+          ((uintptr_t)B % (eb * V) == 0) && ((uintptr_t)C % (4 * V) == 0) &&
+          ((uint64_t)A->K * (uint64_t)ldb * eb < (1ull << 32));
   g.ws_vec = (N % V == 0) && ((uintptr_t)ws % (4 * V) == 0);
   if (g.k_split > 1) {
     const size_t need = spmm_ws_bytes(A, N, plan);
@@ -176,14 +220,21 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
       return ROSKO_ESMALLBUF;
     }
   }
-  const int H = tile_height(A->mr);
-  const int32_t st = (b_dtype == ROSKO_BF16) ? spmm_dispatch_bbf16(g, H, V, G, s)
-                                             : spmm_dispatch_bf32(g, H, V, G, s);
+  const int MRt = tile_height(A->mr);
+  const int32_t st = (b_dtype == ROSKO_BF16) ? spmm_dispatch_bbf16(g, MRt, V, H, s)
+                                             : spmm_dispatch_bf32(g, MRt, V, H, s);
   if (st != ROSKO_OK || g.k_split == 1) return st;
-  const int64_t blocks = std::min<int64_t>(ceil_div(A->M * N, 256), 4096);
-  hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)blocks), dim3(256), 0, s, ws, g.k_split,
-                     A->M, N, A->val_dtype == ROSKO_FP8_E4M3 ? A->row_scale : nullptr, C, ldc,
-                     beta);
+  const bool rvec = (N % 4 == 0) && (ldc % 4 == 0) && ((uintptr_t)C % 16 == 0) &&
+                    ((uintptr_t)ws % 16 == 0);
+  const dim3 grid((unsigned)ceil_div(ceil_div(N, 4), 256),
+                  (unsigned)std::min<int64_t>(A->M, 65535));
+  const float* rs = A->val_dtype == ROSKO_FP8_E4M3 ? A->row_scale : nullptr;
+  if (rvec)
+    hipLaunchKernelGGL(k_reduce_splits<true>, grid, dim3(256), 0, s, ws, g.k_split, A->M, N,
+                       rs, C, ldc, beta);
+  else
+    hipLaunchKernelGGL(k_reduce_splits<false>, grid, dim3(256), 0, s, ws, g.k_split, A->M, N,
+                       rs, C, ldc, beta);
   ROSKO_LAUNCH_CHECK("k_reduce_splits");
   return ROSKO_OK;
 }

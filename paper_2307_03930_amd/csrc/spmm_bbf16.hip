@@ -3,7 +3,7 @@
 #include "spmm_kernel.h"
 
 namespace rosko {
-int32_t spmm_dispatch_bbf16(const SpmmArgs& g, int H, int V, int G, hipStream_t s) {
-  return dispatch_tile<ROSKO_BF16>(g, H, V, G, s);
+int32_t spmm_dispatch_bbf16(const SpmmArgs& g, int MRt, int V, int H, hipStream_t s) {
+  return dispatch_tile<ROSKO_BF16>(g, MRt, V, H, s);
 }
 }  // namespace rosko

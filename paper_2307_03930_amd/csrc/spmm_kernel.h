@@ -1,5 +1,6 @@
-// Kernel template of the row-skipping SpMM; included by the per-dtype
-// translation units spmm_<values>_<B>.hip.  See spmm.hip for the design.
+// Kernel template of the row-skipping SpMM (Alg. 2); included by the
+// per-B-dtype translation units spmm_b<dtype>.hip.  See spmm.hip for the
+// host side and the design notes.
 #pragma once
 #include "internal.h"
 
@@ -9,80 +10,82 @@ namespace {
 typedef float f32x32 __attribute__((ext_vector_type(32)));
 
 // ---------------------------------------------------------------- tile
+// The C tile of one wavefront: MR rows x V columns per lane, column j of row
+// r in VGPR base + j*MR + r, pinned by the asm constraints below so that a
+// row index can select the register at run time.  The base is v40 for the
+// 128-register tiles (so the kernel fits in 168 VGPRs, three wavefronts per
+// SIMD) and v32 for the smaller ones.
 template <int NT>
 struct Tile { f32x32 t[NT]; };
 
 #define RK_STR2(x) #x
 #define RK_STR(x) RK_STR2(x)
-// acc(row M0, column j) += a * b_j, with relative addressing of the addend
-// and the result; REG is the VGPR holding row 0 of column j.
-#define RK_FMA(REG, A, B) "v_fma_f32 v" RK_STR(REG) ", %[" A "], %[" B "], v" RK_STR(REG) "\n\t"
-#define RK_OFF "s_set_gpr_idx_off"
-#define RK_OUT1(T) "+{v[64:95]}"(T.t[0])
-#define RK_OUT2(T) "+{v[64:95]}"(T.t[0]), "+{v[96:127]}"(T.t[1])
+// acc(row, column j) += value * b_j.  The value is lane SLOT of each 16-lane
+// row of the record register, broadcast by DPP; the accumulator register is
+// relative (index mode on SRC2 and DST); REG is the VGPR of row 0 of column j.
+#define RK_FMA(REG, SLOT, B)                                                         \
+  "v_fmac_f32_dpp v" RK_STR(REG) ", %[vr], %[" B "] row_newbcast:" RK_STR(SLOT)      \
+  " row_mask:0xf bank_mask:0xf\n\t"
+#define RK_OUT1(T) "+{v[32:63]}"(T.t[0])
+#define RK_OUT2(T) "+{v[32:63]}"(T.t[0]), "+{v[64:95]}"(T.t[1])
 #define RK_OUT4(T) \
-  "+{v[64:95]}"(T.t[0]), "+{v[96:127]}"(T.t[1]), "+{v[128:159]}"(T.t[2]), "+{v[160:191]}"(T.t[3])
+  "+{v[40:71]}"(T.t[0]), "+{v[72:103]}"(T.t[1]), "+{v[104:135]}"(T.t[2]), "+{v[136:167]}"(T.t[3])
 #define RK_IN4 [b0] "v"(b[0]), [b1] "v"(b[1]), [b2] "v"(b[2]), [b3] "v"(b[3])
 #define RK_IN2 [b0] "v"(b[0]), [b1] "v"(b[1])
 #define RK_IN1 [b0] "v"(b[0])
 
-// Rec<MR, V>::run applies all values (1..12) of one column record to the
-// register tile in a single asm block: the record's three row words w1..w3
-// (bytes already masked to MR-1) feed s_set_gpr_idx_on one byte at a time,
-// and the block ends early, through its own branch, after `cnt` values.
-// One asm site per record keeps the tile in its pinned registers (several
-// sites in different branches made the allocator shuttle the tile around).
-// Index mode is off again at the end of the block.
+// Rec<MR, V>::run applies the 1..12 values of one column record to the
+// register tile in a single asm block.  The record sits in one VGPR, lane l
+// holding dword (l & 15): dword 0 the header, dwords 1..3 the row bytes,
+// dwords 4..15 the values.  A row word is read into an SGPR (v_readlane,
+// index mode off), masked to MR-1 per byte, and fed to s_set_gpr_idx_on one
+// byte at a time; the block leaves through its own branch after `cnt`
+// values.  The leading s_nop gives the DPP reads the two wait states they
+// need after any VALU write of their operands.
 template <int MR, int V> struct Rec;
 
-#define RK_ON1 "s_set_gpr_idx_on %[w1], gpr_idx(SRC2,DST)\n\t"
-#define RK_ON2 "s_set_gpr_idx_on %[w2], gpr_idx(SRC2,DST)\n\t"
-#define RK_ON3 "s_set_gpr_idx_on %[w3], gpr_idx(SRC2,DST)\n\t"
-#define RK_SH(W) "s_lshr_b32 %[" W "], %[" W "], 8\n\t"
+#define RK_ON "s_set_gpr_idx_on %[w], gpr_idx(SRC2,DST)\n\t"
+#define RK_SH "s_lshr_b32 %[w], %[w], 8\n\t"
 #define RK_IF(N) "s_cmp_lt_u32 %[cnt], " #N "\n\ts_cbranch_scc1 .Lrk_end%=\n\t"
-#define RK_BODY(FL)                                                                   \
-  RK_ON1 FL("a0") RK_IF(2) RK_SH("w1") RK_ON1 FL("a1") RK_IF(3) RK_SH("w1") RK_ON1  \
-  FL("a2") RK_IF(4) RK_SH("w1") RK_ON1 FL("a3")                                     \
-  RK_IF(5) RK_ON2 FL("a4") RK_IF(6) RK_SH("w2") RK_ON2 FL("a5") RK_IF(7) RK_SH("w2") \
-  RK_ON2 FL("a6") RK_IF(8) RK_SH("w2") RK_ON2 FL("a7")                              \
-  RK_IF(9) RK_ON3 FL("a8") RK_IF(10) RK_SH("w3") RK_ON3 FL("a9") RK_IF(11)           \
-  RK_SH("w3") RK_ON3 FL("a10") RK_IF(12) RK_SH("w3") RK_ON3 FL("a11")               \
-  ".Lrk_end%=:\n\t" RK_OFF
+#define RK_WORD(LANE, MASK)                                          \
+  "s_set_gpr_idx_off\n\tv_readlane_b32 %[w], %[vr], " #LANE "\n\t" \
+  "s_and_b32 %[w], %[w], " MASK "\n\t"
+#define RK_BODY(FL, MASK)                                                                \
+  "s_nop 1\n\tv_readlane_b32 %[w], %[vr], 1\n\ts_and_b32 %[w], %[w], " MASK "\n\t"      \
+  RK_ON FL(4) RK_IF(2) RK_SH RK_ON FL(5) RK_IF(3) RK_SH RK_ON FL(6) RK_IF(4) RK_SH RK_ON \
+  FL(7) RK_IF(5) RK_WORD(2, MASK) RK_ON FL(8) RK_IF(6) RK_SH RK_ON FL(9) RK_IF(7) RK_SH  \
+  RK_ON FL(10) RK_IF(8) RK_SH RK_ON FL(11) RK_IF(9) RK_WORD(3, MASK) RK_ON FL(12)        \
+  RK_IF(10) RK_SH RK_ON FL(13) RK_IF(11) RK_SH RK_ON FL(14) RK_IF(12) RK_SH RK_ON FL(15) \
+  ".Lrk_end%=:\n\ts_set_gpr_idx_off"
 
-#define RK_REC(MR_, V_, NT_, FL, IN)                                                      \
+#define RK_REC(MR_, V_, NT_, FL, IN, MASK)                                                \
   template <> struct Rec<MR_, V_> {                                                      \
-    static __device__ __forceinline__ void run(Tile<NT_>& T, uint32_t cnt, uint32_t w1,  \
-                                               uint32_t w2, uint32_t w3, const float* a, \
+    static __device__ __forceinline__ void run(Tile<NT_>& T, uint32_t vr, uint32_t cnt,  \
                                                const float* b) {                         \
-      asm volatile(RK_BODY(FL)                                                           \
-                   : RK_OUT##NT_(T), [w1] "+s"(w1), [w2] "+s"(w2), [w3] "+s"(w3)          \
-                   : [cnt] "s"(cnt), [a0] "s"(a[0]), [a1] "s"(a[1]), [a2] "s"(a[2]),      \
-                     [a3] "s"(a[3]), [a4] "s"(a[4]), [a5] "s"(a[5]), [a6] "s"(a[6]),      \
-                     [a7] "s"(a[7]), [a8] "s"(a[8]), [a9] "s"(a[9]), [a10] "s"(a[10]),    \
-                     [a11] "s"(a[11]), IN                                                \
+      uint32_t w;                                                                        \
+      asm volatile(RK_BODY(FL, MASK)                                                     \
+                   : RK_OUT##NT_(T), [w] "=&s"(w)                                        \
+                   : [vr] "v"(vr), [cnt] "s"(cnt), IN                                    \
                    : "m0", "scc");                                                       \
     }                                                                                    \
   };
 
-#define RK_FL_8x4(A) RK_FMA(64, A, "b0") RK_FMA(72, A, "b1") RK_FMA(80, A, "b2") RK_FMA(88, A, "b3")
-#define RK_FL_16x4(A) RK_FMA(64, A, "b0") RK_FMA(80, A, "b1") RK_FMA(96, A, "b2") RK_FMA(112, A, "b3")
-#define RK_FL_32x4(A) RK_FMA(64, A, "b0") RK_FMA(96, A, "b1") RK_FMA(128, A, "b2") RK_FMA(160, A, "b3")
-#define RK_FL_32x2(A) RK_FMA(64, A, "b0") RK_FMA(96, A, "b1")
-#define RK_FL_64x2(A) RK_FMA(64, A, "b0") RK_FMA(128, A, "b1")
-#define RK_FL_128x1(A) RK_FMA(64, A, "b0")
+#define RK_FL_8x4(S) RK_FMA(32, S, "b0") RK_FMA(40, S, "b1") RK_FMA(48, S, "b2") RK_FMA(56, S, "b3")
+#define RK_FL_16x4(S) RK_FMA(32, S, "b0") RK_FMA(48, S, "b1") RK_FMA(64, S, "b2") RK_FMA(80, S, "b3")
+#define RK_FL_32x2(S) RK_FMA(32, S, "b0") RK_FMA(64, S, "b1")
+#define RK_FL_32x4(S) RK_FMA(40, S, "b0") RK_FMA(72, S, "b1") RK_FMA(104, S, "b2") RK_FMA(136, S, "b3")
+#define RK_FL_64x2(S) RK_FMA(40, S, "b0") RK_FMA(104, S, "b1")
+#define RK_FL_128x1(S) RK_FMA(40, S, "b0")
 
-RK_REC(8, 4, 1, RK_FL_8x4, RK_IN4)
-RK_REC(16, 4, 2, RK_FL_16x4, RK_IN4)
-RK_REC(32, 4, 4, RK_FL_32x4, RK_IN4)
-RK_REC(32, 2, 2, RK_FL_32x2, RK_IN2)
-RK_REC(64, 2, 4, RK_FL_64x2, RK_IN2)
-RK_REC(128, 1, 4, RK_FL_128x1, RK_IN1)
+RK_REC(8, 4, 1, RK_FL_8x4, RK_IN4, "0x07070707")
+RK_REC(16, 4, 2, RK_FL_16x4, RK_IN4, "0x0f0f0f0f")
+RK_REC(32, 2, 2, RK_FL_32x2, RK_IN2, "0x1f1f1f1f")
+RK_REC(32, 4, 4, RK_FL_32x4, RK_IN4, "0x1f1f1f1f")
+RK_REC(64, 2, 4, RK_FL_64x2, RK_IN2, "0x3f3f3f3f")
+RK_REC(128, 1, 4, RK_FL_128x1, RK_IN1, "0x7f7f7f7f")
 
 template <int MR, int V> constexpr int tile_nt() { return (MR * V) / 32; }
 
-// The packed arrays are read-only for the whole kernel, so they are read
-// through the constant address space: wave-uniform indices then become
-// scalar loads into SGPRs instead of vector loads plus v_readfirstlane.
 template <typename T>
 using cptr = const __attribute__((address_space(4))) T*;
 template <typename T>
@@ -90,15 +93,10 @@ __device__ __forceinline__ cptr<T> as_const(const void* p) {
   return (cptr<T>)(p);
 }
 
-// ------------------------------------------------------------ B staging
-// B rows of the current K block are staged in LDS as [row][unit], one unit
-// = the V consecutive elements a lane multiplies (64 units per row), in B's
-// own element type.
-template <int TB> struct BElem;
-template <> struct BElem<ROSKO_F32> { using T = float; };
-template <> struct BElem<ROSKO_BF16> { using T = uint16_t; };
-
-template <int TB, int V> struct Unit;    // raw storage of one unit
+// ------------------------------------------------------------ B access
+// One lane reads V consecutive elements of a B row ("unit"), in B's own
+// element type, and widens them to FP32 when the record is applied.
+template <int TB, int V> struct Unit;
 template <> struct Unit<ROSKO_F32, 4> { using T = float4; };
 template <> struct Unit<ROSKO_F32, 2> { using T = float2; };
 template <> struct Unit<ROSKO_F32, 1> { using T = float; };
@@ -106,96 +104,61 @@ template <> struct Unit<ROSKO_BF16, 4> { using T = uint2; };
 template <> struct Unit<ROSKO_BF16, 2> { using T = uint32_t; };
 template <> struct Unit<ROSKO_BF16, 1> { using T = uint16_t; };
 
-// Element j of a unit, by value (no address taken, so no private memory).
-template <int TB, int V>
-__device__ __forceinline__ void set_elem(typename Unit<TB, V>::T& u, int j,
-                                         typename BElem<TB>::T x) {
-  if constexpr (TB == ROSKO_F32) {
-    if constexpr (V == 4) { if (j == 0) u.x = x; else if (j == 1) u.y = x; else if (j == 2) u.z = x; else u.w = x; }
-    else if constexpr (V == 2) { if (j == 0) u.x = x; else u.y = x; }
-    else u = x;
-  } else {
-    if constexpr (V == 4) {
-      if (j == 0) u.x = (u.x & 0xFFFF0000u) | x;
-      else if (j == 1) u.x = (u.x & 0x0000FFFFu) | ((uint32_t)x << 16);
-      else if (j == 2) u.y = (u.y & 0xFFFF0000u) | x;
-      else u.y = (u.y & 0x0000FFFFu) | ((uint32_t)x << 16);
-    } else if constexpr (V == 2) {
-      if (j == 0) u = (u & 0xFFFF0000u) | x;
-      else u = (u & 0x0000FFFFu) | ((uint32_t)x << 16);
-    } else {
-      u = x;
-    }
-  }
-}
+template <int TB> struct BElem;
+template <> struct BElem<ROSKO_F32> { using T = float; };
+template <> struct BElem<ROSKO_BF16> { using T = uint16_t; };
 
-// Issue the load of unit `u` of B row `row` (columns col0 .. col0+V-1)
-// without consuming it: out-of-range addresses are clamped to B's first
-// element, and `ok` (one bit per element) records which elements are real.
-// The zero fill is applied only when the unit is written to LDS, after the
-// current block's compute, so the loads of a block overlap each other and
-// that compute instead of each waiting for the previous one.
+// Unit of row k at this lane's columns.  VEC: one aligned vector load at a
+// column clamped into [0, N-V]; otherwise V element loads, each clamped into
+// [0, N-1].  Clamped lanes read valid memory; their C columns are never stored.
 template <int TB, int V, bool VEC>
-__device__ __forceinline__ void issue_unit(const void* __restrict__ B, int64_t ldb, int64_t row,
-                                           bool row_ok, int64_t col0, int64_t N,
-                                           typename Unit<TB, V>::T* dst, uint32_t* ok) {
+__device__ __forceinline__ typename Unit<TB, V>::T load_unit(const void* __restrict__ B,
+                                                             int64_t ldb, uint32_t k,
+                                                             int64_t col, int64_t N) {
   using E = typename BElem<TB>::T;
   using U = typename Unit<TB, V>::T;
-  const E* base = reinterpret_cast<const E*>(B);
+  const E* row = reinterpret_cast<const E*>(B) + (int64_t)k * ldb;
   if constexpr (VEC) {
-    const bool in = row_ok && col0 < N;
-    *dst = *reinterpret_cast<const U*>(base + (in ? row * ldb + col0 : 0));
-    *ok = in ? ((1u << V) - 1u) : 0u;
+    const int64_t c = col < N - V ? col : N - V;
+    return *reinterpret_cast<const U*>(row + c);
   } else {
-    uint32_t m = 0;
-    U u;
+    E e[V];
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-      const bool in = row_ok && col0 + j < N;
-      set_elem<TB, V>(u, j, base[in ? row * ldb + col0 + j : 0]);
-      m |= in ? (1u << j) : 0u;
+      const int64_t c = col + j < N ? col + j : N - 1;
+      e[j] = row[c];
     }
-    *dst = u;
-    *ok = m;
-  }
-}
-
-// The unit with its out-of-range elements replaced by zero.
-template <int TB, int V>
-__device__ __forceinline__ typename Unit<TB, V>::T masked_unit(typename Unit<TB, V>::T u,
-                                                               uint32_t ok) {
-  if constexpr (TB == ROSKO_F32) {
-    if constexpr (V == 4) {
-      u.x = (ok & 1u) ? u.x : 0.0f; u.y = (ok & 2u) ? u.y : 0.0f;
-      u.z = (ok & 4u) ? u.z : 0.0f; u.w = (ok & 8u) ? u.w : 0.0f;
-    } else if constexpr (V == 2) {
-      u.x = (ok & 1u) ? u.x : 0.0f; u.y = (ok & 2u) ? u.y : 0.0f;
+    U u;
+    if constexpr (TB == ROSKO_F32) {
+      if constexpr (V == 4) u = make_float4(e[0], e[1], e[2], e[3]);
+      else if constexpr (V == 2) u = make_float2(e[0], e[1]);
+      else u = e[0];
     } else {
-      u = (ok & 1u) ? u : 0.0f;
+      if constexpr (V == 4)
+        u = make_uint2((uint32_t)e[0] | ((uint32_t)e[1] << 16),
+                       (uint32_t)e[2] | ((uint32_t)e[3] << 16));
+      else if constexpr (V == 2) u = (uint32_t)e[0] | ((uint32_t)e[1] << 16);
+      else u = e[0];
     }
-  } else {
-    if constexpr (V == 4) {
-      u.x &= ((ok & 1u) ? 0x0000FFFFu : 0u) | ((ok & 2u) ? 0xFFFF0000u : 0u);
-      u.y &= ((ok & 4u) ? 0x0000FFFFu : 0u) | ((ok & 8u) ? 0xFFFF0000u : 0u);
-    } else if constexpr (V == 2) {
-      u &= ((ok & 1u) ? 0x0000FFFFu : 0u) | ((ok & 2u) ? 0xFFFF0000u : 0u);
-    } else {
-      u = (ok & 1u) ? u : (uint16_t)0;
-    }
+    return u;
   }
-  return u;
 }
 
 template <int TB, int V>
 __device__ __forceinline__ void unit_to_float(typename Unit<TB, V>::T u, float* b) {
   if constexpr (TB == ROSKO_F32) {
-    const float* f = reinterpret_cast<const float*>(&u);
-#pragma unroll
-    for (int j = 0; j < V; ++j) b[j] = f[j];
+    if constexpr (V == 4) { b[0] = u.x; b[1] = u.y; b[2] = u.z; b[3] = u.w; }
+    else if constexpr (V == 2) { b[0] = u.x; b[1] = u.y; }
+    else b[0] = u;
   } else {
-    const uint16_t* h = reinterpret_cast<const uint16_t*>(&u);
-#pragma unroll
-    for (int j = 0; j < V; ++j) b[j] = __uint_as_float((uint32_t)h[j] << 16);
+    if constexpr (V == 4) {
+      b[0] = __uint_as_float(u.x << 16); b[1] = __uint_as_float(u.x & 0xFFFF0000u);
+      b[2] = __uint_as_float(u.y << 16); b[3] = __uint_as_float(u.y & 0xFFFF0000u);
+    } else if constexpr (V == 2) {
+      b[0] = __uint_as_float(u << 16); b[1] = __uint_as_float(u & 0xFFFF0000u);
+    } else {
+      b[0] = __uint_as_float((uint32_t)u << 16);
+    }
   }
 }
 
@@ -223,141 +186,143 @@ __device__ __forceinline__ void store_c(float* __restrict__ C, int64_t off, int6
   }
 }
 
-// Blocks are dealt to the 8 XCDs round-robin; remap so that consecutive
-// tile ids (which share B rows) run on the same XCD and hit its L2.
+// Workgroups are dealt to the 8 XCDs round-robin; remap so that consecutive
+// ids (the panels of one column chunk and K part, which read the same B
+// rows) run on the same XCD and share its L2.
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
   const int64_t q = nb >> 3, rem = nb & 7, x = b & 7, pos = b >> 3;
   const int64_t start = (x < rem) ? x * (q + 1) : rem * (q + 1) + (x - rem) * q;
   return start + pos;
 }
 
-// Rows per staged K block: at most 8 units per thread, at most 64 rows, and
-// a divisor of ROSKO_KSTEP so K ranges never split a block.
-template <int V, int G> constexpr int stage_rows() {
-  constexpr int r = 8 * G;           // units per row = 64; threads = 64*G
-  return r > 64 ? 64 : r;
+// Tile element (row q, column j) of a lane, for the epilogue (constant
+// indices after unrolling).
+template <int MR, int NT>
+__device__ __forceinline__ float tile_at(const Tile<NT>& acc, int q, int j) {
+  const int idx = j * MR + q;
+  return acc.t[idx >> 5][idx & 31];
 }
-
-typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
-
-// Byte-wise mask keeping every row byte of a record word below MR.
-template <int MR> constexpr uint32_t row_mask() { return (uint32_t)(MR - 1) * 0x01010101u; }
-
-// All values (1..12) of a column record.
+// LDS image of one tile: row q, lane l, column j at (q*64 + l)*V + j, so a
+// wavefront moves a row as 64 consecutive V-vectors.
 template <int MR, int V, int NT>
-__device__ __forceinline__ void apply_record(Tile<NT>& acc, const u32x16& R, uint32_t cnt,
-                                             const float* b) {
-  constexpr uint32_t m = row_mask<MR>();
-  float a[12];
+__device__ __forceinline__ void tile_to_lds(const Tile<NT>& acc, float* buf, int lane) {
 #pragma unroll
-  for (int t = 0; t < 12; ++t) a[t] = __uint_as_float(R[4 + t]);
-  Rec<MR, V>::run(acc, cnt, R[1] & m, R[2] & m, R[3] & m, a, b);
+  for (int q = 0; q < MR; ++q)
+#pragma unroll
+    for (int j = 0; j < V; ++j) buf[(q * 64 + lane) * V + j] = tile_at<MR>(acc, q, j);
+}
+// buf += tile, element by element (each lane touches only its own slots).
+template <int MR, int V, int NT>
+__device__ __forceinline__ void tile_accumulate_lds(const Tile<NT>& acc, float* buf, int lane) {
+#pragma unroll
+  for (int q = 0; q < MR; ++q)
+#pragma unroll
+    for (int j = 0; j < V; ++j) buf[(q * 64 + lane) * V + j] += tile_at<MR>(acc, q, j);
 }
 
-// One workgroup: panels [pg*G, pg*G+G) (one wavefront each), columns
-// [chunk*64V, chunk*64V + 64V), K range of split s.
-template <int MR, int V, int G, int TB, bool VEC>
-__global__ void __launch_bounds__(64 * G)
-k_spmm_sparse(SpmmArgs g) {
+// Records of B rows in flight per wavefront.
+constexpr int kDepth = 4;
+
+#include "spmm_loop.inc"
+
+// One workgroup: H wavefronts on one (panel, column chunk) tile; split s of
+// k_split.  The panel's records are cut into k_split*H equal runs (by record
+// count, so the waves get the same work); wavefront w takes run s*H + w,
+// keeps its partial tile in VGPRs, and the H tiles are added through LDS in a
+// fixed order.  Each wavefront streams its records and the B rows they name
+// with vector loads, kDepth records ahead of the FMAs, so no step waits on a
+// single load round trip.
+template <int MR, int V, int H, int TB, bool VEC>
+__global__ void __launch_bounds__(64 * H)
+k_spmm_rows(SpmmArgs g) {
   constexpr int NT = tile_nt<MR, V>();
-  constexpr int KB = stage_rows<V, G>();
-  constexpr int NL = KB * 64 / (64 * G);               // units per thread per block
+  constexpr int D = kDepth;
   using U = typename Unit<TB, V>::T;
-  extern __shared__ __align__(16) unsigned char smem[];
-  U* stage = reinterpret_cast<U*>(smem);                // [2][KB][64]
+  extern __shared__ __align__(16) float red[];
 
-  const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t n_pg = (g.n_panels + G - 1) / G;
-  const int64_t pg = tile % n_pg;
-  const int64_t cs = tile / n_pg;
-  const int64_t chunk = cs % g.n_chunks;
-  const int64_t s = cs / g.n_chunks;
+  const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t p = bid % g.n_panels;
+  const int64_t rest = bid / g.n_panels;
+  const int64_t s = rest % g.k_split;
+  const int64_t chunk = rest / g.k_split;
   const int lane = threadIdx.x & 63;
-  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t p = pg * G + wid;
-  const bool active = p < g.n_panels;
-  const int64_t col_base = chunk * (64 * V);
-  const int64_t n0 = col_base + (int64_t)lane * V;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t n0 = chunk * (64 * V) + (int64_t)lane * V;
 
-  // K range of this split, on ROSKO_KSTEP boundaries
+  // this wavefront's run of the panel's records
   const int64_t nkb = (g.K + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
-  const int64_t blo = (nkb * s) / g.k_split, bhi = (nkb * (s + 1)) / g.k_split;
-  const int64_t k_lo = blo * ROSKO_KSTEP;
-  const int64_t k_hi = min(g.K, bhi * ROSKO_KSTEP);
-
-  // this panel's records whose column lies in [k_lo, k_hi)
-  // (32-bit record cursor relative to the panel's first record, so the walk
-  // needs no 64-bit scalar arithmetic or VALU compares)
   cptr<int64_t> kblk = as_const<int64_t>(g.kblk_ptr);
-  cptr<u32x16> recs = as_const<u32x16>(g.rec);
-  uint32_t r = 0, r_end = 0;
-  if (active && k_lo < k_hi) {
-    const int64_t r0 = kblk[p * (nkb + 1)];
-    recs = recs + r0;
-    r = (uint32_t)(kblk[p * (nkb + 1) + blo] - r0);
-    r_end = (uint32_t)(kblk[p * (nkb + 1) + bhi] - r0);
-  }
+  const int64_t r0 = kblk[p * (nkb + 1)], r1 = kblk[p * (nkb + 1) + nkb];
+  const int64_t parts = (int64_t)g.k_split * H, part = s * H + w;
+  const int64_t a = r0 + (r1 - r0) * part / parts;
+  const int64_t e = r0 + (r1 - r0) * (part + 1) / parts;
+  const int32_t n = (int32_t)(e - a);
+  const uint32_t* rp = g.rec + a * 16 + (lane & 15);
 
   Tile<NT> acc;
 #pragma unroll
   for (int q = 0; q < NT; ++q) acc.t[q] = (f32x32)(0.0f);
 
-  const int64_t nblk = (k_hi > k_lo) ? (k_hi - k_lo + KB - 1) / KB : 0;
-  U regs[NL];
-  uint32_t okbits[NL];
-  auto fetch = [&](int64_t kb0) {
+  if (n > 0) {
+    if constexpr (VEC) {
+      // the record loop in one asm block (spmm_loop.inc); buffer loads with
+      // 32-bit offsets from this run's first record and from B
+      constexpr uint32_t esz = TB == ROSKO_F32 ? 4 : 2;
+      const __amdgpu_buffer_rsrc_t rr =
+          __builtin_amdgcn_make_buffer_rsrc((void*)(g.rec + a * 16), 0, -1, 0x00020000);
+      const __amdgpu_buffer_rsrc_t rb =
+          __builtin_amdgcn_make_buffer_rsrc((void*)g.B, 0, -1, 0x00020000);
+      const int64_t cl = n0 < g.N - V ? n0 : g.N - V;
+      RkLoop<MR, V, TB>::run(acc, (uint32_t)n, rr, rb, (uint32_t)(g.ldb * esz),
+                             (uint32_t)(g.K - 1), (uint32_t)(lane & 15) * 4u,
+                             (uint32_t)(cl * esz));
+    } else {
+      auto rec_load = [&](int32_t i) -> uint32_t {
+        return rp[16 * (int64_t)(i < n ? i : n - 1)];
+      };
+      uint32_t RV[2 * D];
+      uint32_t HD[D];
+      U BV[D];
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      const int u = threadIdx.x + i * 64 * G;          // unit index in the block
-      const int rr = u >> 6, uc = u & 63;
-      const int64_t row = kb0 + rr;
-      issue_unit<TB, V, VEC>(g.B, g.ldb, row, row < k_hi, col_base + (int64_t)uc * V, g.N,
-                             &regs[i], &okbits[i]);
-    }
-  };
-
-  // Record walk.  The record of the current column was requested one column
-  // earlier (two slots swap roles from column to column, so no register a
-  // load is still filling is touched early): wait for it, read the B row its
-  // column selects from LDS, request the next record, apply the values.
-  // Returns false when the walk leaves this K block or the panel's range;
-  // the current record then stays in X.
-  float b[V];
-  auto column = [&](u32x16& X, u32x16& Y, const U* buf, int32_t kb0, int32_t kb1) -> bool {
-    __builtin_amdgcn_s_waitcnt(0xC07F);                 // lgkmcnt(0): X has landed
-    const uint32_t hdr = X[0];
-    const int32_t k = (int32_t)(hdr >> 8);
-    const uint32_t cnt = hdr & 0xFFu;
-    if (k >= kb1) return false;
-    unit_to_float<TB, V>(buf[(k - kb0) * 64 + lane], b);
-    __builtin_amdgcn_s_waitcnt(0xC07F);                 // the B row (no load pending)
-    if (r + 1 < r_end) Y = recs[r + 1];                 // in flight during the FMAs
-    apply_record<MR, V>(acc, X, cnt, b);
-    ++r;
-    return r < r_end;
-  };
-
-  u32x16 RA, RB;
-  if (r < r_end) RA = recs[r];
-  if (nblk > 0) fetch(k_lo);
-  for (int64_t ib = 0; ib < nblk; ++ib) {
-    U* buf = stage + (ib & 1) * (KB * 64);
+      for (int j = 0; j < D; ++j) RV[j] = rec_load(j);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) buf[threadIdx.x + i * 64 * G] = masked_unit<TB, V>(regs[i], okbits[i]);
-    __syncthreads();
-    const int64_t kb0 = k_lo + ib * KB;
-    if (ib + 1 < nblk) fetch(kb0 + KB);                // next block in flight
-    const int32_t kb0_32 = (int32_t)kb0;
-    const int32_t kb1 = (int32_t)min(kb0 + KB, k_hi);
-    if (active && r < r_end) {
-      while (true) {
-        if (!column(RA, RB, buf, kb0_32, kb1)) break;
-        if (!column(RB, RA, buf, kb0_32, kb1)) { RA = RB; break; }
+      for (int j = 0; j < D; ++j) {
+        HD[j] = __builtin_amdgcn_readfirstlane(RV[j]);
+        BV[j] = load_unit<TB, V, false>(g.B, g.ldb, HD[j] >> 8, n0, g.N);
+        RV[D + j] = rec_load(D + j);
+      }
+      for (int32_t base = 0; base < n; base += 2 * D) {
+#pragma unroll
+        for (int u = 0; u < 2 * D; ++u) {
+          const int32_t i = base + u;
+          if (i >= n) break;
+          float b[V];
+          unit_to_float<TB, V>(BV[u % D], b);
+          Rec<MR, V>::run(acc, RV[u], HD[u % D] & 0xFFu, b);
+          const uint32_t h2 = __builtin_amdgcn_readfirstlane(RV[(u + D) % (2 * D)]);
+          HD[u % D] = h2;
+          BV[u % D] = load_unit<TB, V, false>(g.B, g.ldb, h2 >> 8, n0, g.N);
+          RV[u] = rec_load(i + 2 * D);
+        }
       }
     }
   }
 
-  if (!active) return;
+  // ---- add the H partial tiles in a fixed order: t0 + t1 for H = 2,
+  // (t0 + t2) + (t1 + t3) for H = 4.  The register tile is only read here,
+  // so it needs no second copy.
+  constexpr int TS = MR * 64 * V;  // floats per tile image
+  if constexpr (H == 4) {
+    if (w >= 2) tile_to_lds<MR, V>(acc, red + (w - 2) * TS, lane);
+    __syncthreads();
+    if (w < 2) tile_accumulate_lds<MR, V>(acc, red + w * TS, lane);
+    __syncthreads();
+  } else if constexpr (H == 2) {
+    if (w == 1) tile_to_lds<MR, V>(acc, red, lane);
+    __syncthreads();
+  }
+  if (w != 0) return;
+
   // ---- epilogue: one split -> C (row scale, beta); several -> partials
   const int rows = (int)min((int64_t)g.mr, g.M - p * g.mr);
   cptr<float> row_scale = as_const<float>(g.row_scale);
@@ -369,8 +334,10 @@ k_spmm_sparse(SpmmArgs g) {
       float v[V];
 #pragma unroll
       for (int j = 0; j < V; ++j) {
-        const int idx = j * MR + q;
-        v[j] = acc.t[idx >> 5][idx & 31];
+        const int o = (q * 64 + lane) * V + j;
+        if constexpr (H == 4) v[j] = red[o] + red[TS + o];
+        else if constexpr (H == 2) v[j] = tile_at<MR>(acc, q, j) + red[o];
+        else v[j] = tile_at<MR>(acc, q, j);
       }
       if (g.k_split == 1) {
         if (scaled) {
@@ -386,51 +353,48 @@ k_spmm_sparse(SpmmArgs g) {
   }
 }
 
-template <int MR, int V, int G, int TB>
+template <int MR, int V, int H, int TB>
 int32_t launch_one(const SpmmArgs& g, hipStream_t st) {
-  const int64_t n_pg = (g.n_panels + G - 1) / G;
-  const int64_t nb = n_pg * g.n_chunks * g.k_split;
+  const int64_t nb = (int64_t)g.n_panels * g.n_chunks * g.k_split;
   if (nb == 0) return ROSKO_OK;
   if (nb > INT32_MAX) {
     set_error("spmm grid too large (%lld workgroups)", (long long)nb);
     return ROSKO_EUNSUPPORTED;
   }
-  constexpr int KB = stage_rows<V, G>();
-  const size_t lds = 2 * (size_t)KB * 64 * sizeof(typename Unit<TB, V>::T);
+  const size_t lds = (H == 4 ? 2 : (H == 2 ? 1 : 0)) * (size_t)MR * 64 * V * sizeof(float);
   if (g.vec)
-    hipLaunchKernelGGL((k_spmm_sparse<MR, V, G, TB, true>), dim3((unsigned)nb), dim3(64 * G), lds,
+    hipLaunchKernelGGL((k_spmm_rows<MR, V, H, TB, true>), dim3((unsigned)nb), dim3(64 * H), lds,
                        st, g);
   else
-    hipLaunchKernelGGL((k_spmm_sparse<MR, V, G, TB, false>), dim3((unsigned)nb), dim3(64 * G),
+    hipLaunchKernelGGL((k_spmm_rows<MR, V, H, TB, false>), dim3((unsigned)nb), dim3(64 * H),
                        lds, st, g);
-  ROSKO_LAUNCH_CHECK("k_spmm_sparse");
+  ROSKO_LAUNCH_CHECK("k_spmm_rows");
   return ROSKO_OK;
 }
 
 template <int MR, int V, int TB>
-int32_t dispatch_g(const SpmmArgs& g, int G, hipStream_t s) {
-  switch (G) {
+int32_t dispatch_h(const SpmmArgs& g, int H, hipStream_t s) {
+  switch (H) {
     case 1: return launch_one<MR, V, 1, TB>(g, s);
     case 2: return launch_one<MR, V, 2, TB>(g, s);
     case 4: return launch_one<MR, V, 4, TB>(g, s);
-    case 8: return launch_one<MR, V, 8, TB>(g, s);
     default: break;
   }
-  set_error("unsupported panels per workgroup %d (1, 2, 4 or 8)", G);
+  set_error("unsupported waves per tile %d (1, 2 or 4)", H);
   return ROSKO_EUNSUPPORTED;
 }
 
 // Supported (tile height, columns per lane) pairs keep the register tile at
 // 32, 64 or 128 VGPRs.
 template <int TB>
-int32_t dispatch_tile(const SpmmArgs& g, int H, int V, int G, hipStream_t s) {
-  if (H == 8 && V == 4) return dispatch_g<8, 4, TB>(g, G, s);
-  if (H == 16 && V == 4) return dispatch_g<16, 4, TB>(g, G, s);
-  if (H == 32 && V == 4) return dispatch_g<32, 4, TB>(g, G, s);
-  if (H == 32 && V == 2) return dispatch_g<32, 2, TB>(g, G, s);
-  if (H == 64 && V == 2) return dispatch_g<64, 2, TB>(g, G, s);
-  if (H == 128 && V == 1) return dispatch_g<128, 1, TB>(g, G, s);
-  set_error("unsupported register tile: height %d with %d columns per lane", H, V);
+int32_t dispatch_tile(const SpmmArgs& g, int MRt, int V, int H, hipStream_t s) {
+  if (MRt == 8 && V == 4) return dispatch_h<8, 4, TB>(g, H, s);
+  if (MRt == 16 && V == 4) return dispatch_h<16, 4, TB>(g, H, s);
+  if (MRt == 32 && V == 4) return dispatch_h<32, 4, TB>(g, H, s);
+  if (MRt == 32 && V == 2) return dispatch_h<32, 2, TB>(g, H, s);
+  if (MRt == 64 && V == 2) return dispatch_h<64, 2, TB>(g, H, s);
+  if (MRt == 128 && V == 1) return dispatch_h<128, 1, TB>(g, H, s);
+  set_error("unsupported register tile: height %d with %d columns per lane", MRt, V);
   return ROSKO_EUNSUPPORTED;
 }
 

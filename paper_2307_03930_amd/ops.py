@@ -163,15 +163,15 @@ def pack_transpose(A: torch.Tensor, mr: int = 32) -> PackedMatrix:
     return P
 
 
-def make_plan(cols_per_lane: int | None = None, panels_per_wg: int | None = None,
+def make_plan(cols_per_lane: int | None = None, waves_per_tile: int | None = None,
               k_split: int | None = None, path: int = L.ROSKO_PATH_SPARSE):
     """A rosko_plan; None (automatic) when nothing is given."""
-    if cols_per_lane is None and panels_per_wg is None and k_split is None:
+    if cols_per_lane is None and waves_per_tile is None and k_split is None:
         return None
     p = L.RoskoPlan()
     p.path = path
     p.cols_per_lane = cols_per_lane or 4
-    p.panels_per_wg = panels_per_wg or 8
+    p.waves_per_tile = waves_per_tile or 1
     p.k_split = k_split or 1
     return p
 

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.rosko_abi_version() == 1
+    assert lib.rosko_abi_version() == 2
     assert lib.rosko_status_str(L.ROSKO_EINVAL) == b"ROSKO_EINVAL"
     assert lib.rosko_status_str(123) == b"ROSKO_UNKNOWN"
 
@@ -153,7 +153,7 @@ def test_spmm_argument_checks():
                           None, 0, None) == L.ROSKO_EINVAL
     s = _packed(8, 8, 4)
     plan = L.RoskoPlan()
-    plan.path, plan.cols_per_lane, plan.panels_per_wg, plan.k_split = 5, 4, 2, 1
+    plan.path, plan.cols_per_lane, plan.waves_per_tile, plan.k_split = 5, 4, 2, 1
     assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 16, fake, 16, 0, C.byref(plan),
                           None, 0, None) == L.ROSKO_EUNSUPPORTED
     # empty problems are valid no-ops and touch no memory
@@ -179,19 +179,19 @@ def test_plan_validation_and_workspace_size():
     s = _packed(256, 2304, 32)
     n = C.c_size_t(0)
     plan = L.RoskoPlan()
-    plan.path, plan.cols_per_lane, plan.panels_per_wg, plan.k_split = 0, 4, 8, 4
+    plan.path, plan.cols_per_lane, plan.waves_per_tile, plan.k_split = 0, 4, 4, 4
     assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan), C.byref(n)) == 0
     assert n.value == 4 * 4 * 256 * 3136
-    plan.k_split = 100   # clamped to the 18 K blocks of 128
+    plan.k_split = 1000   # clamped to ROSKO_MAX_K_SPLIT
     assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan), C.byref(n)) == 0
-    assert n.value == 4 * 18 * 256 * 3136
+    assert n.value == 4 * 64 * 256 * 3136
     plan.k_split = 1
     assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan), C.byref(n)) == 0
     assert n.value == 0
-    plan.panels_per_wg = 3
+    plan.waves_per_tile = 3
     assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan),
                                          C.byref(n)) == L.ROSKO_EUNSUPPORTED
-    plan.panels_per_wg, plan.cols_per_lane = 8, 1   # 32 x 1 tile not provided
+    plan.waves_per_tile, plan.cols_per_lane = 4, 1   # 32 x 1 tile not provided
     assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan),
                                          C.byref(n)) == L.ROSKO_EUNSUPPORTED
     plan.cols_per_lane, plan.k_split = 4, 0

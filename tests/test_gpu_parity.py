@@ -129,19 +129,19 @@ def test_pack_capacity_overflow_reported():
 # --------------------------------------------------------------------------
 # SpMM, FP32
 # --------------------------------------------------------------------------
-PLANS = [(4, 1, 1), (4, 8, 1), (4, 4, 2), (4, 2, 4), (2, 8, 1), (2, 1, 3)]
+PLANS = [(4, 1, 1), (4, 4, 1), (4, 2, 2), (4, 4, 4), (2, 1, 3), (2, 4, 7)]
 
 
 @pytest.mark.parametrize("plan", PLANS)
 def test_spmm_plain_512(plan):
     """512 x 512 at 90% sparsity times 512 x 512 (the plain FP32 case)."""
-    V, G, S = plan
-    say(f"spmm plain-512 plan V={V} G={G} S={S}")
+    V, H, S = plan
+    say(f"spmm plain-512 plan V={V} H={H} S={S}")
     pr = synth.plain_512()
     ref = O.spmm(pr.A, pr.B)
     scale = O.abs_product(pr.A, pr.B)
     P = ops.pack(dev(pr.A), 32, "f32")
-    C = ops.spmm(P, dev(pr.B), plan=ops.make_plan(V, G, S)).cpu().numpy()
+    C = ops.spmm(P, dev(pr.B), plan=ops.make_plan(V, H, S)).cpu().numpy()
     e = err(C, ref, scale)
     say(f"  err {e:.3e}")
     assert e <= TOL_F32
@@ -158,9 +158,9 @@ def test_spmm_shapes_ragged(mr, V, N):
     ref = O.spmm(A, B)
     scale = O.abs_product(A, B)
     P = ops.pack(dev(A), mr, "f32")
-    for G, S in ((1, 1), (2, 2), (8, 1), (4, 9)):
-        C = ops.spmm(P, dev(B), plan=ops.make_plan(V, G, S)).cpu().numpy()
-        assert err(C, ref, scale) <= TOL_F32, (G, S)
+    for H, S in ((1, 1), (2, 2), (4, 1), (4, 9)):
+        C = ops.spmm(P, dev(B), plan=ops.make_plan(V, H, S)).cpu().numpy()
+        assert err(C, ref, scale) <= TOL_F32, (H, S)
 
 
 def test_spmm_beta_one_and_strides():
@@ -215,10 +215,23 @@ def test_spmm_deterministic():
     B = synth.dense_normal(2304, 512, 609)
     P = ops.pack(dev(A), 32)
     Bd = dev(B)
-    for G, S in ((8, 1), (4, 3), (1, 9)):
-        c1 = ops.spmm(P, Bd, plan=ops.make_plan(4, G, S)).cpu().numpy()
-        c2 = ops.spmm(P, Bd, plan=ops.make_plan(4, G, S)).cpu().numpy()
+    for H, S in ((4, 1), (4, 3), (1, 9)):
+        c1 = ops.spmm(P, Bd, plan=ops.make_plan(4, H, S)).cpu().numpy()
+        c2 = ops.spmm(P, Bd, plan=ops.make_plan(4, H, S)).cpu().numpy()
         assert c1.tobytes() == c2.tobytes()
+
+
+def test_spmm_more_runs_than_records():
+    """Few records and many runs: most wavefronts get an empty run."""
+    say("spmm empty runs")
+    A = synth.sparse_matrix(70, 40, 0.02, 611)
+    B = synth.dense_normal(40, 300, 612)
+    ref = O.spmm(A, B)
+    scale = O.abs_product(A, B)
+    P = ops.pack(dev(A), 32)
+    for V, H, S in ((4, 4, 64), (2, 2, 33), (4, 1, 5)):
+        C = ops.spmm(P, dev(B), plan=ops.make_plan(V, H, S)).cpu().numpy()
+        assert err(C, ref, scale) <= TOL_F32, (V, H, S)
 
 
 @pytest.mark.parametrize("s", synth.CNN_SPARSITIES)
@@ -232,10 +245,10 @@ def test_spmm_cnn_layer_sampled(s):
     scale = O.abs_product(pr.A[rows], pr.B)
     P = ops.pack(dev(pr.A), 32)
     Bd = dev(pr.B)
-    for V, G, S in ((4, 8, 1), (4, 8, 4), (2, 4, 2), (4, 1, 18)):
-        C = ops.spmm(P, Bd, plan=ops.make_plan(V, G, S))
+    for V, H, S in ((4, 4, 1), (4, 4, 4), (2, 2, 2), (4, 1, 18)):
+        C = ops.spmm(P, Bd, plan=ops.make_plan(V, H, S))
         e = err(C.cpu().numpy()[rows], ref, scale)
-        say(f"  V={V} G={G} S={S} err {e:.3e}")
+        say(f"  V={V} H={H} S={S} err {e:.3e}")
         assert e <= TOL_F32
 
 
