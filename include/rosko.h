@@ -125,17 +125,23 @@ typedef struct rosko_packed {
  * tiles go to the workspace and a second kernel adds them in a fixed order
  * (so results do not depend on timing) and applies the FP8 row scale and
  * beta.
- * path:           ROSKO_PATH_SPARSE (row-skipping vector kernel), or
+ * path:           ROSKO_PATH_SPARSE (row-skipping vector kernel),
+ *                 ROSKO_PATH_DENSE (every panel densified from the packed form
+ *                 and multiplied on the matrix cores: BF16 MFMA when A's
+ *                 values and B are exactly BF16 -- BF16 or FP8 values with a
+ *                 BF16 B -- else FP32 MFMA; the other fields are ignored), or
  *                 ROSKO_PATH_AUTO to let the library choose everything.
  * cols_per_lane:  1, 2 or 4.  The register tile (panel height rounded up to
  *                 8/16/32/64/128, times cols_per_lane) must be one of 8x4,
  *                 16x4, 32x4, 32x2, 64x2, 128x1; other pairs return
  *                 ROSKO_EUNSUPPORTED.  Panel heights above 128 are packed but
  *                 not multiplied by this path.
- * waves_per_tile: 1, 2 or 4.
- * k_split:        1 .. ROSKO_MAX_K_SPLIT (larger values are clamped).  */
+ * waves_per_tile: 1, 2 or 4; 0 lets the library choose.
+ * k_split:        1 .. ROSKO_MAX_K_SPLIT (larger values are clamped); 0 lets
+ *                 the library choose.  */
 #define ROSKO_PATH_AUTO (-1)
 #define ROSKO_PATH_SPARSE 0
+#define ROSKO_PATH_DENSE 1
 #define ROSKO_MAX_K_SPLIT 64
 typedef struct rosko_plan {
   int32_t path;
@@ -192,7 +198,10 @@ int32_t rosko_pack_result(const void *ws, size_t ws_bytes, rosko_packed *packed,
 
 /* Device workspace bytes rosko_spmm needs for A (only its shape and mr are
  * read), N columns and `plan` (NULL = the automatic plan): 4*k_split*M*N
- * when k_split > 1, else 0. */
+ * for the sparse path when k_split > 1, else 0; for the dense path the
+ * densified A and transposed B at FP32 size,
+ * 4*(ceil(n_panels*mr / 128)*128 + ceil(N / 128)*128) * ceil(K / 32)*32
+ * (rounded to 256-byte pieces), enough for either operand type. */
 int32_t rosko_spmm_workspace_size(const rosko_packed *A, int64_t N, const rosko_plan *plan,
                                   size_t *bytes);
 
@@ -222,10 +231,73 @@ int32_t rosko_spmm_backward(const rosko_packed *A, const rosko_packed *At, const
                             int64_t lddb, float *dA_val, void *ws, size_t ws_bytes,
                             void *stream);
 
+/* ---- learned plan selection (Sec. 4.3's analytic tiling, Sec. 7's tunable
+ * choice) ------------------------------------------------------------------
+ * The choice of panel height mr, register tile and path is made per matrix
+ * from ROSKO_NFEAT statistics of A by a Linear(F,H)-ReLU-Linear(H,H)-ReLU-
+ * Linear(H,C) network that predicts, for each of the ROSKO_SCHED_CANDIDATES
+ * candidates, log(runtime / best runtime); the candidate with the smallest
+ * prediction is taken.  The analytic rule is the fallback.  All device
+ * arrays are FP32, row-major; every call is asynchronous on `stream`.
+ * Candidates (index: path, mr, cols_per_lane):
+ *   0: sparse, 8, 4     1: sparse, 16, 4    2: sparse, 32, 4
+ *   3: sparse, 32, 2    4: sparse, 64, 2    5: sparse, 128, 1
+ *   6: dense-MFMA (packed with mr 32)
+ * Feature f (0-based), with "kept" the value test of Alg. 1 and panels of
+ * r rows cut as packing cuts them:
+ *   0 log2 M, 1 log2 K, 2 log2 N, 3 d = nnz/(M K), 4 log10(d + 1e-6),
+ *   5 CV of the row counts, 6 fraction of empty rows, 7 CV of the column
+ *   counts, 8 fraction of empty columns, 9 nnz / kept panel columns (r = 32),
+ *   10 kept panel columns (r = 32) / (ceil(M/32) K), 11 nnz / kept panel
+ *   columns (r = 8), 12 CV of the 32-row panel counts, 13 max / mean of the
+ *   32-row panel counts, 14 log2(1 + nnz N), 15 log2(M N)
+ * (CV = population standard deviation / mean; a ratio with a zero
+ * denominator is 0). */
+#define ROSKO_NFEAT 16
+#define ROSKO_SCHED_CANDIDATES 7
+
+/* Device workspace bytes rosko_features needs for an M x K matrix. */
+int32_t rosko_features_workspace_size(int64_t M, int64_t K, size_t *bytes);
+/* features (device, ROSKO_NFEAT floats) of A (device, M x K, lda >= K)
+ * multiplied by N columns.  M <= 2^21.  Deterministic (integer counts). */
+int32_t rosko_features(const float *A, int64_t M, int64_t K, int64_t lda, int64_t N, void *ws,
+                       size_t ws_bytes, float *features, void *stream);
+
+/* Number of parameters of the network: F*H + H + H*H + H + H*C + C, laid
+ * out as W1 [F,H], b1 [H], W2 [H,H], b2 [H], W3 [H,C], b3 [C] (W is
+ * [in, out]; a layer computes X W + b). */
+int32_t rosko_mlp_param_count(int32_t F, int32_t H, int32_t C, int64_t *n);
+/* Xn[b][i] = (X[b][i] - mu[i]) / sigma[i] for a batch x F matrix. */
+int32_t rosko_mlp_normalize(const float *X, int64_t batch, int32_t F, const float *mu,
+                            const float *sigma, float *Xn, void *stream);
+/* Forward pass: H1 = relu(X W1 + b1), H2 = relu(H1 W2 + b2), Y = H2 W3 + b3
+ * (H1, H2: batch x H, kept for the backward; Y: batch x C). */
+int32_t rosko_mlp_forward(const float *params, int32_t F, int32_t H, int32_t C, const float *X,
+                          int64_t batch, float *H1, float *H2, float *Y, void *stream);
+/* Loss L = sum(mask (Y - T)^2) / max(1, sum mask) into *loss (device) and
+ * its gradient with respect to every parameter into grads (same layout as
+ * params).  ws: device scratch of batch * (C + 2 H) floats. */
+int32_t rosko_mlp_backward(const float *params, int32_t F, int32_t H, int32_t C, const float *X,
+                           const float *H1, const float *H2, const float *Y, const float *T,
+                           const float *mask, int64_t batch, float *grads, float *ws,
+                           float *loss, void *stream);
+/* One Adam step (t >= 1, bias-corrected) over n parameters, in place on
+ * params, m and v. */
+int32_t rosko_adam_step(float *params, const float *grads, float *m, float *v, int64_t n,
+                        float lr, float beta1, float beta2, float eps, int32_t t, void *stream);
+/* out[b] = the first index of the smallest entry of row b of Y (batch x C). */
+int32_t rosko_argmin_rows(const float *Y, int64_t batch, int32_t C, int32_t *out, void *stream);
+/* Candidate `index`: the panel height to pack with (*mr) and the plan to
+ * multiply with (waves_per_tile and k_split 0: chosen by the library). */
+int32_t rosko_sched_candidate(int32_t index, int32_t *mr, rosko_plan *plan);
+/* The analytic fallback rule on host features: the dense path from density
+ * 0.25 up, else mr 32 with 4 columns per lane (2 when N <= 128). */
+int32_t rosko_sched_analytic(const float *features_host, int32_t *index);
+
 /* ---- errors ----------------------------------------------------------- */
 const char *rosko_status_str(int32_t status);
 const char *rosko_last_error(void);   /* per host thread; "" if none */
-int32_t rosko_abi_version(void);      /* 2 */
+int32_t rosko_abi_version(void);      /* 3 */
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,9 @@ ROSKO_FP8_E4M3 = 2
 
 ROSKO_PATH_AUTO = -1
 ROSKO_PATH_SPARSE = 0
+ROSKO_PATH_DENSE = 1
+ROSKO_NFEAT = 16
+ROSKO_SCHED_CANDIDATES = 7
 ROSKO_KSTEP = 128
 
 
@@ -83,6 +86,18 @@ SIGNATURES = {
                                                   C.POINTER(_SZ)]),
     "rosko_spmm_backward": (_I32, [C.POINTER(RoskoPacked), C.POINTER(RoskoPacked), _P, _I64,
                                    _P, _I64, _I64, _P, _I64, _P, _P, _SZ, _P]),
+    "rosko_features_workspace_size": (_I32, [_I64, _I64, C.POINTER(_SZ)]),
+    "rosko_features": (_I32, [_P, _I64, _I64, _I64, _I64, _P, _SZ, _P, _P]),
+    "rosko_mlp_param_count": (_I32, [_I32, _I32, _I32, C.POINTER(_I64)]),
+    "rosko_mlp_normalize": (_I32, [_P, _I64, _I32, _P, _P, _P, _P]),
+    "rosko_mlp_forward": (_I32, [_P, _I32, _I32, _I32, _P, _I64, _P, _P, _P, _P]),
+    "rosko_mlp_backward": (_I32, [_P, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _I64, _P, _P,
+                                  _P, _P]),
+    "rosko_adam_step": (_I32, [_P, _P, _P, _P, _I64, C.c_float, C.c_float, C.c_float,
+                               C.c_float, _I32, _P]),
+    "rosko_argmin_rows": (_I32, [_P, _I64, _I32, _P, _P]),
+    "rosko_sched_candidate": (_I32, [_I32, C.POINTER(_I32), C.POINTER(RoskoPlan)]),
+    "rosko_sched_analytic": (_I32, [_P, C.POINTER(_I32)]),
     "rosko_status_str": (C.c_char_p, [_I32]),
     "rosko_last_error": (C.c_char_p, []),
     "rosko_abi_version": (_I32, []),

@@ -95,7 +95,7 @@ static int32_t check_packed_for_read(const rosko_packed* A) {
 
 extern "C" {
 
-int32_t rosko_abi_version(void) { return 2; }
+int32_t rosko_abi_version(void) { return 3; }
 
 const char* rosko_last_error(void) { return g_err; }
 
@@ -287,6 +287,9 @@ int32_t rosko_spmm(const rosko_packed* A, const void* B, int32_t b_dtype, int64_
   if ((st = normalize_plan(A, N, &p))) return st;
   if (A->M == 0 || N == 0) return ROSKO_OK;
   (void)hipGetLastError();
+  if (p.path == ROSKO_PATH_DENSE)
+    return launch_spmm_dense(A, B, b_dtype, N, ldb, C, ldc, beta, ws, ws_bytes,
+                             static_cast<hipStream_t>(stream));
   return launch_spmm_sparse(A, B, b_dtype, N, ldb, C, ldc, beta, p, static_cast<float*>(ws),
                             ws_bytes, static_cast<hipStream_t>(stream));
 }
@@ -336,6 +339,132 @@ int32_t rosko_spmm_backward(const rosko_packed* A, const rosko_packed* At, const
     (void)hipGetLastError();
     if ((st = launch_sddmm(A, dC, lddc, B, ldb, N, dA_val, s))) return st;
   }
+  return ROSKO_OK;
+}
+
+// ---------------------------------------------------------- scheduler
+
+int32_t rosko_features_workspace_size(int64_t M, int64_t K, size_t* bytes) {
+  clear_error();
+  RK_REQUIRE(bytes != nullptr, ROSKO_EINVAL, "bytes is null");
+  RK_REQUIRE(M >= 0 && K >= 0, ROSKO_EINVAL, "negative size");
+  *bytes = features_ws_bytes(M, K);
+  return ROSKO_OK;
+}
+
+int32_t rosko_features(const float* A, int64_t M, int64_t K, int64_t lda, int64_t N, void* ws,
+                       size_t ws_bytes, float* features, void* stream) {
+  clear_error();
+  int32_t st = check_dense(A, M, K, lda, "A");
+  if (st) return st;
+  RK_REQUIRE(M >= 1 && K >= 1 && N >= 1, ROSKO_EINVAL, "features need M, K, N >= 1");
+  RK_REQUIRE(M <= (int64_t(1) << 21), ROSKO_EUNSUPPORTED, "M = %lld > 2^21", (long long)M);
+  RK_REQUIRE(features != nullptr, ROSKO_EINVAL, "features is null");
+  const size_t need = features_ws_bytes(M, K);
+  RK_REQUIRE(ws != nullptr && ws_bytes >= need, ROSKO_ESMALLBUF,
+             "features workspace %zu bytes < %zu", ws_bytes, need);
+  RK_REQUIRE((uintptr_t)ws % 256 == 0, ROSKO_EINVAL, "features workspace must be 256-byte aligned");
+  (void)hipGetLastError();
+  return launch_features(A, M, K, lda, N, ws, features, static_cast<hipStream_t>(stream));
+}
+
+static int32_t check_mlp_dims(int32_t F, int32_t H, int32_t C) {
+  RK_REQUIRE(F >= 1 && H >= 1 && C >= 1 && F <= 4096 && H <= 4096 && C <= 4096, ROSKO_EINVAL,
+             "network sizes F=%d H=%d C=%d outside 1..4096", F, H, C);
+  return ROSKO_OK;
+}
+
+int32_t rosko_mlp_param_count(int32_t F, int32_t H, int32_t C, int64_t* n) {
+  clear_error();
+  int32_t st = check_mlp_dims(F, H, C);
+  if (st) return st;
+  RK_REQUIRE(n != nullptr, ROSKO_EINVAL, "n is null");
+  *n = (int64_t)F * H + H + (int64_t)H * H + H + (int64_t)H * C + C;
+  return ROSKO_OK;
+}
+
+int32_t rosko_mlp_normalize(const float* X, int64_t batch, int32_t F, const float* mu,
+                            const float* sigma, float* Xn, void* stream) {
+  clear_error();
+  RK_REQUIRE(batch >= 0 && F >= 1, ROSKO_EINVAL, "bad sizes");
+  if (batch == 0) return ROSKO_OK;
+  RK_REQUIRE(X && mu && sigma && Xn, ROSKO_EINVAL, "null argument");
+  (void)hipGetLastError();
+  return launch_normalize(X, batch, F, mu, sigma, Xn, static_cast<hipStream_t>(stream));
+}
+
+int32_t rosko_mlp_forward(const float* params, int32_t F, int32_t H, int32_t C, const float* X,
+                          int64_t batch, float* H1, float* H2, float* Y, void* stream) {
+  clear_error();
+  int32_t st = check_mlp_dims(F, H, C);
+  if (st) return st;
+  RK_REQUIRE(batch >= 0, ROSKO_EINVAL, "negative batch");
+  if (batch == 0) return ROSKO_OK;
+  RK_REQUIRE(params && X && H1 && H2 && Y, ROSKO_EINVAL, "null argument");
+  (void)hipGetLastError();
+  return launch_mlp_forward(params, F, H, C, X, batch, H1, H2, Y,
+                            static_cast<hipStream_t>(stream));
+}
+
+int32_t rosko_mlp_backward(const float* params, int32_t F, int32_t H, int32_t C, const float* X,
+                           const float* H1, const float* H2, const float* Y, const float* T,
+                           const float* mask, int64_t batch, float* grads, float* ws,
+                           float* loss, void* stream) {
+  clear_error();
+  int32_t st = check_mlp_dims(F, H, C);
+  if (st) return st;
+  RK_REQUIRE(batch >= 1, ROSKO_EINVAL, "batch must be >= 1");
+  RK_REQUIRE(params && X && H1 && H2 && Y && T && mask && grads && ws && loss, ROSKO_EINVAL,
+             "null argument");
+  (void)hipGetLastError();
+  return launch_mlp_backward(params, F, H, C, X, H1, H2, Y, T, mask, batch, grads, ws, loss,
+                             static_cast<hipStream_t>(stream));
+}
+
+int32_t rosko_adam_step(float* params, const float* grads, float* m, float* v, int64_t n,
+                        float lr, float beta1, float beta2, float eps, int32_t t, void* stream) {
+  clear_error();
+  RK_REQUIRE(n >= 0 && t >= 1, ROSKO_EINVAL, "need n >= 0 and t >= 1");
+  RK_REQUIRE(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f,
+             ROSKO_EINVAL, "bad Adam constants");
+  if (n == 0) return ROSKO_OK;
+  RK_REQUIRE(params && grads && m && v, ROSKO_EINVAL, "null argument");
+  (void)hipGetLastError();
+  return launch_adam(params, grads, m, v, n, lr, beta1, beta2, eps, t,
+                     static_cast<hipStream_t>(stream));
+}
+
+int32_t rosko_argmin_rows(const float* Y, int64_t batch, int32_t C, int32_t* out, void* stream) {
+  clear_error();
+  RK_REQUIRE(batch >= 0 && C >= 1, ROSKO_EINVAL, "bad sizes");
+  if (batch == 0) return ROSKO_OK;
+  RK_REQUIRE(Y && out, ROSKO_EINVAL, "null argument");
+  (void)hipGetLastError();
+  return launch_argmin(Y, batch, C, out, static_cast<hipStream_t>(stream));
+}
+
+int32_t rosko_sched_candidate(int32_t index, int32_t* mr, rosko_plan* plan) {
+  clear_error();
+  static const int32_t kMr[ROSKO_SCHED_CANDIDATES] = {8, 16, 32, 32, 64, 128, 32};
+  static const int32_t kV[ROSKO_SCHED_CANDIDATES] = {4, 4, 4, 2, 2, 1, 0};
+  RK_REQUIRE(index >= 0 && index < ROSKO_SCHED_CANDIDATES, ROSKO_EINVAL,
+             "candidate %d outside 0..%d", index, ROSKO_SCHED_CANDIDATES - 1);
+  RK_REQUIRE(mr && plan, ROSKO_EINVAL, "null argument");
+  *mr = kMr[index];
+  plan->path = kV[index] ? ROSKO_PATH_SPARSE : ROSKO_PATH_DENSE;
+  plan->cols_per_lane = kV[index];
+  plan->waves_per_tile = 0;
+  plan->k_split = 0;
+  return ROSKO_OK;
+}
+
+int32_t rosko_sched_analytic(const float* f, int32_t* index) {
+  clear_error();
+  RK_REQUIRE(f && index, ROSKO_EINVAL, "null argument");
+  const float density = f[3];
+  const float log2N = f[2];
+  if (density >= 0.25f) *index = 6;
+  else *index = (log2N <= 7.0f) ? 3 : 2;
   return ROSKO_OK;
 }
 

@@ -98,6 +98,29 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
                            const rosko_plan& plan, float* ws, size_t ws_bytes, hipStream_t s);
 int32_t launch_fill_zero(float* C, int64_t M, int64_t N, int64_t ldc, hipStream_t s);
 
+// Dense-MFMA path (dense.hip): workspace bytes (b_dtype ROSKO_F32 gives the
+// larger, FP32 operand size) and the launch.
+size_t dense_ws_bytes(const rosko_packed* A, int64_t N, int32_t b_dtype);
+int32_t launch_spmm_dense(const rosko_packed* A, const void* B, int32_t b_dtype, int64_t N,
+                          int64_t ldb, float* C, int64_t ldc, int32_t beta, void* ws,
+                          size_t ws_bytes, hipStream_t s);
+
+// ------------------------------------------------------ scheduler (sched.hip)
+size_t features_ws_bytes(int64_t M, int64_t K);
+int32_t launch_features(const float* A, int64_t M, int64_t K, int64_t lda, int64_t N, void* ws,
+                        float* f, hipStream_t s);
+int32_t launch_normalize(const float* X, int64_t Bn, int32_t F, const float* mu,
+                         const float* sigma, float* Xn, hipStream_t s);
+int32_t launch_mlp_forward(const float* prm, int32_t F, int32_t H, int32_t C, const float* X,
+                           int64_t Bn, float* H1, float* H2, float* Y, hipStream_t s);
+int32_t launch_mlp_backward(const float* prm, int32_t F, int32_t H, int32_t C, const float* X,
+                            const float* H1, const float* H2, const float* Y, const float* T,
+                            const float* mask, int64_t Bn, float* grads, float* ws, float* loss,
+                            hipStream_t s);
+int32_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                    float b2, float eps, int32_t t, hipStream_t s);
+int32_t launch_argmin(const float* Y, int64_t Bn, int32_t C, int32_t* out, hipStream_t s);
+
 // ---------------------------------------------------------------- SDDMM
 int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const float* B,
                      int64_t ldb, int64_t N, float* dA_val, hipStream_t s);

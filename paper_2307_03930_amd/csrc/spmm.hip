@@ -120,21 +120,16 @@ int32_t launch_fill_zero(float* C, int64_t M, int64_t N, int64_t ldc, hipStream_
   return ROSKO_OK;
 }
 
-// The analytic fallback plan.  The register tile is the widest the panel
-// height allows (128 accumulators per lane), narrowed when N is small.  The
-// grid should hold about two wavefronts per SIMD (2048 on 256 CUs): when the
-// (panel, chunk) tiles are fewer, each tile gets up to 4 wavefronts in its
-// workgroup, then up to 8 workgroups (k_split), as long as a wavefront keeps
-// at least kMinRun records (records per panel estimated from nrec, or from
-// nnz at about 8 values per record when nrec is unknown).
-rosko_plan auto_plan(const rosko_packed* A, int64_t N) {
-  rosko_plan p{};
-  p.path = ROSKO_PATH_SPARSE;
-  const int MRt = tile_height(A->mr);
-  p.cols_per_lane = (MRt <= 32) ? 4 : (MRt == 64 ? 2 : 1);
-  if (MRt == 32 && N <= 128) p.cols_per_lane = 2;
+// Parallel shape of the sparse path for V columns per lane: the grid should
+// hold about two wavefronts per SIMD (2048 on 256 CUs).  When the (panel,
+// chunk) tiles are fewer, each tile gets up to 4 wavefronts in its workgroup,
+// then up to 8 workgroups (k_split), as long as a wavefront keeps at least
+// kMinRun records (records per panel estimated from nrec, or from nnz at
+// about 8 values per record when nrec is unknown).
+static void auto_parallelism(const rosko_packed* A, int64_t N, int V, int32_t* H_out,
+                             int32_t* S_out) {
   const int64_t P = std::max<int64_t>(1, A->n_panels);
-  const int64_t chunks = std::max<int64_t>(1, ceil_div(N, 64 * p.cols_per_lane));
+  const int64_t chunks = std::max<int64_t>(1, ceil_div(N, 64 * V));
   const int64_t tiles = P * chunks;
   constexpr int64_t kTargetWaves = 2048, kMinRun = 48;
   int64_t per_panel = 1 << 30;
@@ -144,10 +139,20 @@ rosko_plan auto_plan(const rosko_packed* A, int64_t N) {
   int64_t want = std::max<int64_t>(1, kTargetWaves / tiles);
   want = std::min(want, max_parts);
   const int H = want >= 4 ? 4 : (want >= 2 ? 2 : 1);
-  int64_t S = std::max<int64_t>(1, want / H);
-  S = std::min<int64_t>(S, 8);
-  p.waves_per_tile = H;
-  p.k_split = (int32_t)S;
+  *H_out = H;
+  *S_out = (int32_t)std::min<int64_t>(8, std::max<int64_t>(1, want / H));
+}
+
+// The analytic fallback plan: the register tile is the widest the panel
+// height allows (128 accumulators per lane), narrowed when N is small; the
+// parallel shape from auto_parallelism.
+rosko_plan auto_plan(const rosko_packed* A, int64_t N) {
+  rosko_plan p{};
+  p.path = ROSKO_PATH_SPARSE;
+  const int MRt = tile_height(A->mr);
+  p.cols_per_lane = (MRt <= 32) ? 4 : (MRt == 64 ? 2 : 1);
+  if (MRt == 32 && N <= 128) p.cols_per_lane = 2;
+  auto_parallelism(A, N, p.cols_per_lane, &p.waves_per_tile, &p.k_split);
   return p;
 }
 
@@ -156,6 +161,7 @@ int32_t normalize_plan(const rosko_packed* A, int64_t N, rosko_plan* p) {
     *p = auto_plan(A, N);
     return ROSKO_OK;
   }
+  if (p->path == ROSKO_PATH_DENSE) return ROSKO_OK;   // no further parameters
   if (p->path != ROSKO_PATH_SPARSE) {
     set_error("plan path %d not supported", p->path);
     return ROSKO_EUNSUPPORTED;
@@ -165,6 +171,12 @@ int32_t normalize_plan(const rosko_packed* A, int64_t N, rosko_plan* p) {
     set_error("unsupported register tile: mr %d (height %d) with %d columns per lane", A->mr,
               MRt, p->cols_per_lane);
     return ROSKO_EUNSUPPORTED;
+  }
+  if (p->waves_per_tile == 0 || p->k_split == 0) {   // 0 fields: the library's choice
+    int32_t h, sp;
+    auto_parallelism(A, N, p->cols_per_lane, &h, &sp);
+    if (p->waves_per_tile == 0) p->waves_per_tile = h;
+    if (p->k_split == 0) p->k_split = sp;
   }
   const int H = p->waves_per_tile;
   if (H != 1 && H != 2 && H != 4) {
@@ -180,6 +192,7 @@ int32_t normalize_plan(const rosko_packed* A, int64_t N, rosko_plan* p) {
 }
 
 size_t spmm_ws_bytes(const rosko_packed* A, int64_t N, const rosko_plan& p) {
+  if (p.path == ROSKO_PATH_DENSE) return dense_ws_bytes(A, N, ROSKO_F32);
   if (p.k_split <= 1) return 0;
   return sizeof(float) * (size_t)p.k_split * (size_t)A->M * (size_t)N;
 }

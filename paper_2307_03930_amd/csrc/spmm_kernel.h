@@ -280,6 +280,7 @@ k_spmm_rows(SpmmArgs g) {
       auto rec_load = [&](int32_t i) -> uint32_t {
         return rp[16 * (int64_t)(i < n ? i : n - 1)];
       };
+      const uint32_t km1 = (uint32_t)(g.K - 1);   // as in the asm loop: B rows stay in bounds
       uint32_t RV[2 * D];
       uint32_t HD[D];
       U BV[D];
@@ -288,7 +289,7 @@ k_spmm_rows(SpmmArgs g) {
 #pragma unroll
       for (int j = 0; j < D; ++j) {
         HD[j] = __builtin_amdgcn_readfirstlane(RV[j]);
-        BV[j] = load_unit<TB, V, false>(g.B, g.ldb, HD[j] >> 8, n0, g.N);
+        BV[j] = load_unit<TB, V, false>(g.B, g.ldb, min(HD[j] >> 8, km1), n0, g.N);
         RV[D + j] = rec_load(D + j);
       }
       for (int32_t base = 0; base < n; base += 2 * D) {
@@ -301,7 +302,7 @@ k_spmm_rows(SpmmArgs g) {
           Rec<MR, V>::run(acc, RV[u], HD[u % D] & 0xFFu, b);
           const uint32_t h2 = __builtin_amdgcn_readfirstlane(RV[(u + D) % (2 * D)]);
           HD[u % D] = h2;
-          BV[u % D] = load_unit<TB, V, false>(g.B, g.ldb, h2 >> 8, n0, g.N);
+          BV[u % D] = load_unit<TB, V, false>(g.B, g.ldb, min(h2 >> 8, km1), n0, g.N);
           RV[u] = rec_load(i + 2 * D);
         }
       }

@@ -176,6 +176,14 @@ def make_plan(cols_per_lane: int | None = None, waves_per_tile: int | None = Non
     return p
 
 
+def dense_plan():
+    """The plan of the dense-MFMA path (every panel densified, matrix cores)."""
+    p = L.RoskoPlan()
+    p.path = L.ROSKO_PATH_DENSE
+    p.cols_per_lane, p.waves_per_tile, p.k_split = 0, 0, 1
+    return p
+
+
 def spmm_workspace_size(P: PackedMatrix, N: int, plan=None) -> int:
     n = C.c_size_t(0)
     st = P.struct()

@@ -1,0 +1,328 @@
+"""Learned plan selection for the Rosko SpMM (the tunable choice of Sec. 7
+in place of the analytic tiling model of Sec. 4.3).
+
+Per matrix, a Linear(16,64)-ReLU-Linear(64,64)-ReLU-Linear(64,7) network
+predicts log(runtime / best runtime) of each of the 7 candidates
+(rosko_sched_candidate: panel height mr, register tile, sparse or
+dense-MFMA path) from 16 packing statistics (rosko_features); the candidate
+with the smallest prediction is used, the analytic rule
+(rosko_sched_analytic) when no trained network is loaded.
+
+Everything numerical runs in the library's HIP kernels through the C ABI:
+statistics, normalisation, forward, the MSE gradient, backward, Adam and
+the arg-min.  This module marshals arguments, holds the device buffers and
+drives the corpus sweep (measured SpMM runtimes of every candidate on the
+2000 seeded corpus problems), the training and the held-out evaluation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import math
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import ops, synth
+
+F = L.ROSKO_NFEAT
+HID = 64
+NCAND = L.ROSKO_SCHED_CANDIDATES
+DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "sched_data")
+WEIGHTS = os.path.join(DATA_DIR, "weights.json")
+CORPUS = os.path.join(DATA_DIR, "corpus.jsonl")
+N_TRAIN = 1800
+
+
+def _p(t):
+    return ops._ptr(t)
+
+
+def _s():
+    return ops._stream_ptr()
+
+
+# ------------------------------------------------------------- statistics
+def features(A: torch.Tensor, N: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """The 16 statistics of A (M x K float32 CUDA) times N columns, on the
+    device (rosko_features)."""
+    ops._check_dense(A, "A")
+    M, K = A.shape
+    n = C.c_size_t(0)
+    L.check(L.lib().rosko_features_workspace_size(M, K, C.byref(n)))
+    ws = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=A.device)
+    if out is None:
+        out = torch.empty(F, dtype=torch.float32, device=A.device)
+    L.check(L.lib().rosko_features(_p(A), M, K, max(A.stride(0), 1), N, _p(ws), ws.numel(),
+                                   _p(out), _s()))
+    return out
+
+
+def candidate(index: int):
+    """(mr, rosko_plan) of candidate `index`."""
+    mr = C.c_int32(0)
+    plan = L.RoskoPlan()
+    L.check(L.lib().rosko_sched_candidate(int(index), C.byref(mr), C.byref(plan)))
+    return int(mr.value), plan
+
+
+def analytic(f_host: np.ndarray) -> int:
+    f = np.ascontiguousarray(f_host, np.float32)
+    idx = C.c_int32(0)
+    L.check(L.lib().rosko_sched_analytic(f.ctypes.data_as(C.c_void_p), C.byref(idx)))
+    return int(idx.value)
+
+
+# -------------------------------------------------------------------- MLP
+def param_count(Fi=F, H=HID, Cn=NCAND) -> int:
+    n = C.c_int64(0)
+    L.check(L.lib().rosko_mlp_param_count(Fi, H, Cn, C.byref(n)))
+    return int(n.value)
+
+
+def flatten(params: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(params[k], np.float32).ravel()
+                           for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def unflatten(flat: np.ndarray, Fi=F, H=HID, Cn=NCAND) -> dict:
+    shapes = [("W1", (Fi, H)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (H, Cn)),
+              ("b3", (Cn,))]
+    out, o = {}, 0
+    for k, sh in shapes:
+        n = int(np.prod(sh))
+        out[k] = np.asarray(flat[o:o + n], np.float32).reshape(sh)
+        o += n
+    return out
+
+
+class MLP:
+    """Device parameters, Adam state and the kernel calls of the network."""
+
+    def __init__(self, flat: np.ndarray, mu: np.ndarray, sigma: np.ndarray, device="cuda",
+                 Fi=F, H=HID, Cn=NCAND):
+        self.F, self.H, self.C = Fi, H, Cn
+        self.n = param_count(Fi, H, Cn)
+        assert flat.size == self.n
+        self.params = torch.from_numpy(np.asarray(flat, np.float32).copy()).to(device)
+        self.mu = torch.from_numpy(np.asarray(mu, np.float32)).to(device)
+        self.sigma = torch.from_numpy(np.asarray(sigma, np.float32)).to(device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grads = torch.zeros_like(self.params)
+        self.t = 0
+
+    def normalize(self, X: torch.Tensor) -> torch.Tensor:
+        Xn = torch.empty_like(X)
+        L.check(L.lib().rosko_mlp_normalize(_p(X), X.shape[0], self.F, _p(self.mu),
+                                            _p(self.sigma), _p(Xn), _s()))
+        return Xn
+
+    def forward(self, Xn: torch.Tensor):
+        B = Xn.shape[0]
+        dev = Xn.device
+        H1 = torch.empty((B, self.H), dtype=torch.float32, device=dev)
+        H2 = torch.empty((B, self.H), dtype=torch.float32, device=dev)
+        Y = torch.empty((B, self.C), dtype=torch.float32, device=dev)
+        L.check(L.lib().rosko_mlp_forward(_p(self.params), self.F, self.H, self.C, _p(Xn), B,
+                                          _p(H1), _p(H2), _p(Y), _s()))
+        return H1, H2, Y
+
+    def backward(self, Xn, H1, H2, Y, T, mask) -> torch.Tensor:
+        B = Xn.shape[0]
+        ws = torch.empty(B * (self.C + 2 * self.H), dtype=torch.float32, device=Xn.device)
+        loss = torch.empty(1, dtype=torch.float32, device=Xn.device)
+        L.check(L.lib().rosko_mlp_backward(_p(self.params), self.F, self.H, self.C, _p(Xn),
+                                           _p(H1), _p(H2), _p(Y), _p(T), _p(mask), B,
+                                           _p(self.grads), _p(ws), _p(loss), _s()))
+        return loss
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.t += 1
+        L.check(L.lib().rosko_adam_step(_p(self.params), _p(self.grads), _p(self.m), _p(self.v),
+                                        self.n, lr, beta1, beta2, eps, self.t, _s()))
+
+    def choose(self, X: torch.Tensor) -> torch.Tensor:
+        """Arg-min of the predicted log slowdown per row of raw features X."""
+        _, _, Y = self.forward(self.normalize(X))
+        out = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
+        L.check(L.lib().rosko_argmin_rows(_p(Y), X.shape[0], self.C, _p(out), _s()))
+        return out
+
+    def to_json(self) -> dict:
+        return {"F": self.F, "H": self.H, "C": self.C,
+                "mu": self.mu.cpu().tolist(), "sigma": self.sigma.cpu().tolist(),
+                "params": self.params.cpu().tolist()}
+
+    @staticmethod
+    def from_json(d: dict, device="cuda") -> "MLP":
+        return MLP(np.array(d["params"], np.float32), np.array(d["mu"], np.float32),
+                   np.array(d["sigma"], np.float32), device, d["F"], d["H"], d["C"])
+
+
+def load(device="cuda") -> MLP | None:
+    if not os.path.exists(WEIGHTS):
+        return None
+    with open(WEIGHTS) as f:
+        return MLP.from_json(json.load(f), device)
+
+
+def choose(A: torch.Tensor, N: int, net: MLP | None = None) -> int:
+    """Candidate index for A times N columns: the network's choice, the
+    analytic rule without one."""
+    f = features(A, N)
+    if net is None:
+        return analytic(f.cpu().numpy())
+    return int(net.choose(f.view(1, F)).item())
+
+
+# ---------------------------------------------------------------- corpus
+def time_candidate(A: torch.Tensor, B: torch.Tensor, index: int, reps: int = 5) -> float:
+    """Median SpMM time (microseconds) of candidate `index`, packing excluded."""
+    mr, plan = candidate(index)
+    P = ops.pack(A, mr, "f32")
+    N = B.shape[1]
+    Cm = torch.empty((A.shape[0], N), dtype=torch.float32, device=A.device)
+    need = ops.spmm_workspace_size(P, N, plan)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    ops.spmm(P, B, Cm, plan=plan, ws=ws)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        ops.spmm(P, B, Cm, plan=plan, ws=ws)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) * 1e3)
+    del P, Cm, ws
+    return float(np.median(ts))
+
+
+def sweep(first: int, last: int, path: str, log_every: int = 1) -> None:
+    """Measure every candidate on corpus problems [first, last) and append
+    one JSON line per problem (features, times in microseconds) to `path`."""
+    dev = torch.device("cuda")
+    done = set()
+    if os.path.exists(path):
+        with open(path) as f:
+            done = {json.loads(line)["i"] for line in f if line.strip()}
+    t0 = time.time()
+    with open(path, "a") as out:
+        for i in range(first, last):
+            if i in done:
+                continue
+            A, B, sp = synth.corpus_problem_device(i, dev)
+            f = features(A, B.shape[1]).cpu().numpy().tolist()
+            times = [time_candidate(A, B, c) for c in range(NCAND)]
+            out.write(json.dumps({"i": i, "M": sp["M"], "K": sp["K"], "N": sp["N"],
+                                  "sparsity": sp["sparsity"], "kind": sp["kind"],
+                                  "features": f, "times_us": times}) + "\n")
+            out.flush()
+            del A, B
+            if (i - first) % log_every == 0:
+                print(f"corpus {i}: {sp['M']}x{sp['K']}x{sp['N']} s={sp['sparsity']:.3f} "
+                      f"best={int(np.argmin(times))} t={min(times):.1f}us "
+                      f"({time.time() - t0:.0f}s)", flush=True)
+
+
+def read_corpus(path: str = CORPUS):
+    rows = [json.loads(line) for line in open(path) if line.strip()]
+    rows.sort(key=lambda r: r["i"])
+    X = np.array([r["features"] for r in rows], np.float32)
+    Tm = np.array([r["times_us"] for r in rows], np.float64)
+    idx = np.array([r["i"] for r in rows])
+    return idx, X, Tm
+
+
+def targets(Tm: np.ndarray) -> np.ndarray:
+    """log(t / best t) per problem and candidate."""
+    return np.log(Tm / Tm.min(axis=1, keepdims=True)).astype(np.float32)
+
+
+def train(X: np.ndarray, Tm: np.ndarray, steps: int = 4000, lr: float = 3e-3, seed: int = 17,
+          device="cuda", log_every: int = 500) -> MLP:
+    """Full-batch Adam on the GPU through the library's kernels."""
+    mu = X.mean(axis=0)
+    sigma = X.std(axis=0)
+    sigma[sigma < 1e-6] = 1.0
+    net = MLP(flatten(synth.mlp_init_params(F, HID, NCAND, seed)), mu, sigma, device)
+    Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32)).to(device)
+    Td = torch.from_numpy(targets(Tm)).to(device)
+    mask = torch.ones_like(Td)
+    Xn = net.normalize(Xd)
+    for step in range(1, steps + 1):
+        H1, H2, Y = net.forward(Xn)
+        loss = net.backward(Xn, H1, H2, Y, Td, mask)
+        net.adam(lr=lr)
+        if step % log_every == 0 or step == 1:
+            print(f"train step {step}: loss {loss.item():.5f}", flush=True)
+    return net
+
+
+def evaluate(net: MLP | None, X: np.ndarray, Tm: np.ndarray) -> dict:
+    """Slowdown t(choice) / t(best) of the network, the analytic rule and
+    the best single fixed candidate on the given problems."""
+    best = Tm.min(axis=1)
+    out = {}
+    if net is not None:
+        ch = net.choose(torch.from_numpy(np.ascontiguousarray(X, np.float32)).cuda()).cpu().numpy()
+        r = Tm[np.arange(len(ch)), ch] / best
+        out["mlp"] = {"mean": float(r.mean()), "median": float(np.median(r)),
+                      "geomean": float(np.exp(np.log(r).mean())),
+                      "within_5pct": float((r <= 1.05).mean()), "max": float(r.max())}
+    ana = np.array([analytic(x) for x in X])
+    r = Tm[np.arange(len(ana)), ana] / best
+    out["analytic"] = {"mean": float(r.mean()), "median": float(np.median(r)),
+                       "geomean": float(np.exp(np.log(r).mean())),
+                       "within_5pct": float((r <= 1.05).mean()), "max": float(r.max())}
+    fixed = [float(np.exp(np.log(Tm[:, c] / best).mean())) for c in range(NCAND)]
+    c = int(np.argmin(fixed))
+    r = Tm[:, c] / best
+    out["best_fixed"] = {"candidate": c, "mean": float(r.mean()), "geomean": fixed[c],
+                         "within_5pct": float((r <= 1.05).mean())}
+    return out
+
+
+def main(argv=None):
+    """python -m paper_2307_03930_amd.sched sweep FIRST LAST | train | eval"""
+    import argparse
+    ap = argparse.ArgumentParser(prog="python -m paper_2307_03930_amd.sched")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("sweep")
+    s.add_argument("first", type=int)
+    s.add_argument("last", type=int)
+    s.add_argument("--out", default=CORPUS)
+    t = sub.add_parser("train")
+    t.add_argument("--steps", type=int, default=4000)
+    t.add_argument("--lr", type=float, default=3e-3)
+    t.add_argument("--corpus", default=CORPUS)
+    t.add_argument("--out", default=WEIGHTS)
+    e = sub.add_parser("eval")
+    e.add_argument("--corpus", default=CORPUS)
+    a = ap.parse_args(argv)
+    if a.cmd == "sweep":
+        os.makedirs(os.path.dirname(a.out), exist_ok=True)
+        sweep(a.first, a.last, a.out)
+    elif a.cmd == "train":
+        idx, X, Tm = read_corpus(a.corpus)
+        tr = idx < N_TRAIN
+        net = train(X[tr], Tm[tr], steps=a.steps, lr=a.lr)
+        os.makedirs(os.path.dirname(a.out), exist_ok=True)
+        with open(a.out, "w") as f:
+            json.dump(net.to_json(), f)
+        print(json.dumps({"train": evaluate(net, X[tr], Tm[tr]),
+                          "held_out": evaluate(net, X[~tr], Tm[~tr])}), flush=True)
+    else:
+        idx, X, Tm = read_corpus(a.corpus)
+        net = load()
+        ho = idx >= N_TRAIN
+        print(json.dumps({"held_out": evaluate(net, X[ho], Tm[ho])}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

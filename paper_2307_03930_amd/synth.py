@@ -229,3 +229,55 @@ def mlp_init_params(F: int, H: int, Cout: int, seed: int) -> dict:
     return {"W1": lin(F, H), "b1": np.zeros(H, np.float32),
             "W2": lin(H, H), "b2": np.zeros(H, np.float32),
             "W3": lin(H, Cout), "b3": np.zeros(Cout, np.float32)}
+
+
+def corpus_problem_device(i: int, device) -> tuple:
+    """Corpus problem i generated on the GPU (torch's Philox generator seeded
+    with the problem seed): A M x K FP32 with N(0,1) values on a keep-mask of
+    the problem's kind, B K x N FP32 N(0,1).  The per-row and per-column
+    structure of the row-clustered and column-banded masks (run positions,
+    band positions) is drawn on the host with numpy exactly as in the host
+    generators; the M x K and K x N random fields are drawn on the device.
+    Used for the scheduler's timing corpus only (no oracle comparison)."""
+    import torch
+    sp = corpus_spec(i)
+    M, K, N, d, kind = sp["M"], sp["K"], sp["N"], 1.0 - sp["sparsity"], sp["kind"]
+    g = rng(sp["seed"] + 1_000_000)
+    tg = torch.Generator(device=device)
+    tg.manual_seed(sp["seed"])
+    u = torch.rand((M, K), generator=tg, device=device)
+    if kind == "iid":
+        mask = u < d
+    elif kind == "row_clustered":
+        z = g.uniform(0.0, 0.5)
+        n_zero = int(round(z * M))
+        zero_rows = np.zeros(M, dtype=bool)
+        left = n_zero
+        while left > 0:
+            run = int(min(left, max(1, g.integers(1, max(2, M // 8) + 1))))
+            start = int(g.integers(0, M))
+            for j in range(run):
+                r = (start + j) % M
+                if not zero_rows[r]:
+                    zero_rows[r] = True
+                    left -= 1
+                    if left == 0:
+                        break
+        live = max(1, M - int(zero_rows.sum()))
+        d_live = min(1.0, d * M / live)
+        mask = (u < d_live) & torch.from_numpy(~zero_rows).to(device)[:, None]
+    else:
+        nb = int(g.integers(1, 9))
+        weight = np.ones(K)
+        for _ in range(nb):
+            width = int(g.integers(max(1, K // 64), max(2, K // 8) + 1))
+            start = int(g.integers(0, K))
+            weight[(start + np.arange(width)) % K] = 10.0
+        p = np.minimum(d * K * weight / weight.sum(), 1.0)
+        mask = u < torch.from_numpy(p.astype(np.float32)).to(device)[None, :]
+    del u
+    vals = torch.randn((M, K), generator=tg, device=device)
+    A = torch.where(mask, vals, torch.zeros((), device=device))
+    del vals, mask
+    B = torch.randn((K, N), generator=tg, device=device)
+    return A, B, sp

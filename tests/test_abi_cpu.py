@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.rosko_abi_version() == 2
+    assert lib.rosko_abi_version() == 3
     assert lib.rosko_status_str(L.ROSKO_EINVAL) == b"ROSKO_EINVAL"
     assert lib.rosko_status_str(123) == b"ROSKO_UNKNOWN"
 
@@ -194,10 +194,40 @@ def test_plan_validation_and_workspace_size():
     plan.waves_per_tile, plan.cols_per_lane = 4, 1   # 32 x 1 tile not provided
     assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan),
                                          C.byref(n)) == L.ROSKO_EUNSUPPORTED
-    plan.cols_per_lane, plan.k_split = 4, 0
+    plan.cols_per_lane, plan.k_split = 4, -1
     assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan),
                                          C.byref(n)) == L.ROSKO_EINVAL
+    plan.waves_per_tile, plan.k_split = 0, 0   # the library chooses both
+    assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan), C.byref(n)) == 0
     # the automatic plan is valid for every supported panel height
     for mr in (1, 8, 13, 32, 50, 64, 100, 128):
         s2 = _packed(300, 1000, mr)
         assert lib.rosko_spmm_workspace_size(C.byref(s2), 777, None, C.byref(n)) == 0
+
+
+def test_sched_candidates_and_analytic_rule():
+    lib = L.lib()
+    mr = C.c_int32(0)
+    plan = L.RoskoPlan()
+    seen = []
+    for i in range(L.ROSKO_SCHED_CANDIDATES):
+        assert lib.rosko_sched_candidate(i, C.byref(mr), C.byref(plan)) == 0
+        seen.append((mr.value, plan.path, plan.cols_per_lane))
+        assert plan.waves_per_tile == 0 and plan.k_split == 0
+    assert seen == [(8, 0, 4), (16, 0, 4), (32, 0, 4), (32, 0, 2), (64, 0, 2), (128, 0, 1),
+                    (32, 1, 0)]
+    assert lib.rosko_sched_candidate(7, C.byref(mr), C.byref(plan)) == L.ROSKO_EINVAL
+    idx = C.c_int32(-1)
+    f = (C.c_float * 16)()
+    f[3], f[2] = 0.1, 10.0                      # 10% dense, N = 1024
+    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 2
+    f[2] = 6.0                                  # N = 64
+    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 3
+    f[3] = 0.5
+    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 6
+    n = C.c_int64(0)
+    assert lib.rosko_mlp_param_count(16, 64, 7, C.byref(n)) == 0
+    assert n.value == 16 * 64 + 64 + 64 * 64 + 64 + 64 * 7 + 7
+    sz = C.c_size_t(0)
+    assert lib.rosko_features_workspace_size(100, 50, C.byref(sz)) == 0 and sz.value > 0
+    assert lib.rosko_features(None, 0, 5, 5, 3, None, 0, None, None) == L.ROSKO_EINVAL

@@ -295,3 +295,79 @@ def test_spmm_precision_form_sampled(s, dtype):
     say(f"  err vs FP32 source {e:.3e}")
     tol = {"f32": TOL_F32, "bf16": TOL_BF16, "fp8": TOL_FP8}[dtype]
     assert e <= tol
+
+
+# --------------------------------------------------------------------------
+# dense-MFMA path: every panel densified from the packed form
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("M,K,N,mr", [(512, 512, 512, 32), (77, 131, 190, 13), (300, 40, 1, 8),
+                                      (129, 257, 129, 64), (1, 1, 1, 1)])
+def test_dense_path_f32(M, K, N, mr):
+    """FP32 values and B: FP32 MFMA on the densified panels."""
+    say(f"dense path f32 M={M} K={K} N={N} mr={mr}")
+    A = synth.sparse_matrix(M, K, 0.3, 620 + M, "iid")
+    B = synth.dense_normal(K, N, 621 + N)
+    ref = O.spmm(A, B)
+    scale = O.abs_product(A, B)
+    P = ops.pack(dev(A), mr, "f32")
+    C = ops.spmm(P, dev(B), plan=ops.dense_plan()).cpu().numpy()
+    e = err(C, ref, scale)
+    say(f"  err {e:.3e}")
+    assert e <= TOL_F32
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+@pytest.mark.parametrize("b_bf16", [False, True])
+def test_dense_path_quantised(dtype, b_bf16):
+    """BF16 / FP8 values: BF16 MFMA when B is BF16, FP32 MFMA otherwise; the
+    FP8 row scale in the epilogue."""
+    say(f"dense path values={dtype} B bf16={b_bf16}")
+    A = synth.sparse_matrix(333, 700, 0.25, 622)
+    B = synth.dense_normal(700, 260, 623)
+    if b_bf16:
+        B = synth.bf16_representable(B)
+    opk = O.pack(A, 32, DT[dtype])
+    c_deq = O.spmm_packed(opk, B)
+    scale_deq = np.abs(O.unpack(opk)) @ np.abs(B).astype(np.float64)
+    P = ops.pack(dev(A), 32, dtype)
+    Bd = dev(B).to(torch.bfloat16) if b_bf16 else dev(B)
+    C = ops.spmm(P, Bd, plan=ops.dense_plan()).cpu().numpy()
+    e = err(C, c_deq, scale_deq)
+    say(f"  err vs decoded {e:.3e}")
+    assert e <= TOL_F32
+
+
+def test_dense_path_beta_and_strides():
+    say("dense path beta=1 with padded leading dimensions")
+    A = synth.sparse_matrix(96, 200, 0.4, 624)
+    B = synth.dense_normal(200, 130, 625)
+    C0 = synth.dense_normal(96, 130, 626)
+    Bpad = np.zeros((200, 136), np.float32)
+    Bpad[:, :130] = B
+    Cpad = np.zeros((96, 140), np.float32)
+    Cpad[:, :130] = C0
+    P = ops.pack(dev(A), 32)
+    Cd = dev(Cpad)
+    ops.spmm(P, dev(Bpad)[:, :130], Cd[:, :130], beta=1, plan=ops.dense_plan())
+    got = Cd.cpu().numpy()
+    ref = O.spmm(A, B) + C0.astype(np.float64)
+    scale = O.abs_product(A, B) + np.abs(C0)
+    assert err(got[:, :130], ref, scale) <= TOL_F32
+    assert not got[:, 130:].any()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_dense_path_precision_form_sampled(dtype):
+    """4096 x 4096 at 90% times the 4096 x 2048 activations on the matrix
+    cores; 16 sampled rows against the oracle."""
+    say(f"dense path precision form values={dtype}")
+    pr = synth.precision_problem(0.90)
+    rows = np.sort(synth.rng(627).choice(4096, 16, replace=False))
+    c_src = O.spmm(pr.A[rows], pr.B)
+    scale = O.abs_product(pr.A[rows], pr.B)
+    P = ops.pack(dev(pr.A), 32, dtype)
+    Bd = dev(pr.B).to(torch.bfloat16) if dtype == "bf16" else dev(pr.B)
+    C = ops.spmm(P, Bd, plan=ops.dense_plan()).cpu().numpy()[rows]
+    e = err(C, c_src, scale)
+    say(f"  err vs FP32 source {e:.3e}")
+    assert e <= (TOL_F32 if dtype == "f32" else TOL_BF16)

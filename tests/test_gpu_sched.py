@@ -1,0 +1,133 @@
+"""Parity of the scheduler's HIP kernels (through the C ABI) with the CPU
+oracles: statistics against oracle/features.py, the network's forward,
+gradient and Adam step against oracle/mlp.py (FP64)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import features as OF
+from oracle import mlp as OM
+from paper_2307_03930_amd import sched, synth
+from tests.gpu_helpers import dev, say
+
+pytestmark = pytest.mark.gpu
+
+
+def setup_module(_m):
+    assert torch.cuda.is_available(), "GPU tests need the MI355X"
+
+
+FEAT_CASES = [(256, 2304, 0.1, "magnitude", 3136), (77, 131, 0.2, "iid", 5),
+              (1000, 300, 0.05, "row_clustered", 64), (300, 1000, 0.02, "column_banded", 999),
+              (33, 7, 0.9, "iid", 1), (8, 2049, 0.001, "iid", 4096)]
+
+
+@pytest.mark.parametrize("case", FEAT_CASES)
+def test_features_match_oracle(case):
+    M, K, d, kind, N = case
+    say(f"features {M}x{K} d={d} {kind} N={N}")
+    A = synth.sparse_matrix(M, K, d, 700 + M, kind)
+    if M > 10:
+        A[3, : min(K, 5)] = -0.0          # dropped like zeros
+        A[5, 0] = np.nan                  # kept
+    ref = OF.features(A, N)
+    got = sched.features(dev(A), N).cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got, ref, rtol=2e-6, atol=1e-6)
+
+
+def test_features_all_zero():
+    A = np.zeros((40, 50), np.float32)
+    ref = OF.features(A, 3)
+    got = sched.features(dev(A), 3).cpu().numpy()
+    np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-6)
+
+
+def _net(seed, B=37):
+    g = synth.rng(seed)
+    params = synth.mlp_init_params(sched.F, sched.HID, sched.NCAND, seed)
+    for k in ("b1", "b2", "b3"):
+        params[k] = g.normal(0, 0.1, size=params[k].shape).astype(np.float32)
+    X = g.normal(0, 1, size=(B, sched.F)).astype(np.float32)
+    T = g.normal(0, 1, size=(B, sched.NCAND)).astype(np.float32)
+    mask = (g.random((B, sched.NCAND)) < 0.8).astype(np.float32)
+    net = sched.MLP(sched.flatten(params), np.zeros(sched.F, np.float32),
+                    np.ones(sched.F, np.float32))
+    return params, X, T, mask, net
+
+
+def test_mlp_forward_matches_oracle():
+    params, X, _, _, net = _net(31)
+    Y_ref, _ = OM.forward(params, X)
+    Xd = dev(X)
+    H1, H2, Y = net.forward(net.normalize(Xd))
+    np.testing.assert_allclose(Y.cpu().numpy(), Y_ref, rtol=1e-5, atol=1e-5)
+
+
+def test_mlp_backward_matches_oracle():
+    params, X, T, mask, net = _net(32)
+    Y_ref, cache = OM.forward(params, X)
+    loss_ref, dY = OM.mse_loss(Y_ref, T, mask)
+    g_ref = OM.backward(params, cache, dY)
+    Xd = dev(X)
+    Xn = net.normalize(Xd)
+    H1, H2, Y = net.forward(Xn)
+    loss = net.backward(Xn, H1, H2, Y, dev(T), dev(mask))
+    assert loss.item() == pytest.approx(loss_ref, rel=1e-5)
+    got = sched.unflatten(net.grads.cpu().numpy())
+    for k in OM.PARAM_NAMES:
+        scale = max(1e-6, float(np.abs(g_ref[k]).max()))
+        assert float(np.abs(got[k] - g_ref[k]).max()) / scale < 1e-5, k
+
+
+def test_adam_step_matches_oracle():
+    params, X, T, mask, net = _net(33)
+    Y_ref, cache = OM.forward(params, X)
+    _, dY = OM.mse_loss(Y_ref, T, mask)
+    g_ref = OM.backward(params, cache, dY)
+    m = {k: np.zeros_like(np.asarray(params[k], np.float64)) for k in OM.PARAM_NAMES}
+    v = {k: np.zeros_like(np.asarray(params[k], np.float64)) for k in OM.PARAM_NAMES}
+    p1, m, v = OM.adam_step(params, g_ref, m, v, 1, lr=1e-2)
+    p2, m, v = OM.adam_step(p1, g_ref, m, v, 2, lr=1e-2)
+    net.grads.copy_(torch.from_numpy(sched.flatten(g_ref)).cuda())
+    net.adam(lr=1e-2)
+    net.adam(lr=1e-2)
+    got = sched.unflatten(net.params.cpu().numpy())
+    for k in OM.PARAM_NAMES:
+        np.testing.assert_allclose(got[k], p2[k], rtol=1e-5, atol=1e-6)
+
+
+def test_normalize_and_argmin():
+    g = synth.rng(34)
+    X = g.normal(3, 2, size=(50, sched.F)).astype(np.float32)
+    mu = X.mean(axis=0)
+    sigma = X.std(axis=0) + 0.5
+    net = sched.MLP(np.zeros(sched.param_count(), np.float32), mu, sigma)
+    Xn = net.normalize(dev(X)).cpu().numpy()
+    np.testing.assert_allclose(Xn, (X - mu) / sigma, rtol=1e-6, atol=1e-6)
+    Y = g.normal(size=(50, sched.NCAND)).astype(np.float32)
+    Y[7, 2] = Y[7, 5] = Y[7].min() - 1.0      # tie: the first index wins
+    out = torch.empty(50, dtype=torch.int32, device="cuda")
+    from paper_2307_03930_amd import _lib as L
+    from paper_2307_03930_amd import ops
+    L.check(L.lib().rosko_argmin_rows(ops._ptr(dev(Y)), 50, sched.NCAND, ops._ptr(out),
+                                      ops._stream_ptr()))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), Y.argmin(axis=1))
+
+
+def test_training_reduces_loss():
+    """A few hundred full-batch Adam steps on a synthetic target that is a
+    smooth function of the features lower the loss by 10x."""
+    say("mlp training on a synthetic target")
+    g = synth.rng(35)
+    X = g.normal(size=(512, sched.F)).astype(np.float32)
+    W = g.normal(size=(sched.F, sched.NCAND)).astype(np.float32) * 0.3
+    Tm = np.exp(np.tanh(X @ W) + 1.0)        # positive "times"
+    net = sched.train(X, Tm, steps=400, lr=3e-3, log_every=1000)
+    Xn = net.normalize(dev(X))
+    H1, H2, Y = net.forward(Xn)
+    T = torch.from_numpy(sched.targets(Tm)).cuda()
+    loss = net.backward(Xn, H1, H2, Y, T, torch.ones_like(T)).item()
+    base = float(((sched.targets(Tm) - sched.targets(Tm).mean(axis=0)) ** 2).mean())
+    say(f"  loss {loss:.4f} vs constant predictor {base:.4f}")
+    assert loss < 0.1 * base

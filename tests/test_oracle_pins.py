@@ -452,3 +452,58 @@ def test_records_against_independent_rebuild():
                 kbx.append(base + int(np.searchsorted(np.array(starts, int), j * 128)))
         assert np.array_equal(rec, np.array(expect, np.uint32).reshape(-1, 16))
         assert np.array_equal(kb, np.array(kbx, np.int64))
+
+
+# --------------------------------------------------------------------------
+# scheduler features: hand-derived values on small matrices
+# --------------------------------------------------------------------------
+def test_features_identity_hand_values():
+    from oracle import features as OF
+    f = OF.features(np.eye(64, dtype=np.float32), 16)
+    # 64 kept values, one per row and per column; each 32-row panel keeps 32
+    # of the 64 columns and each 8-row panel 8 of them
+    expect = {0: 6.0, 1: 6.0, 2: 4.0, 3: 1 / 64, 5: 0.0, 6: 0.0, 7: 0.0, 8: 0.0,
+              9: 1.0, 10: 0.5, 11: 1.0, 12: 0.0, 13: 1.0, 14: np.log2(1 + 64 * 16),
+              15: np.log2(64 * 16)}
+    for i, v in expect.items():
+        assert f[i] == pytest.approx(v, rel=1e-12, abs=1e-15), i
+    assert f[4] == pytest.approx(np.log10(1 / 64 + 1e-6))
+
+
+def test_features_single_value_hand_values():
+    from oracle import features as OF
+    A = np.zeros((64, 10), np.float32)
+    A[40, 3] = -2.5
+    f = OF.features(A, 7)
+    # rows: one 1 among 64 -> mean 1/64, population variance 1/64 - 1/64^2,
+    # CV = sqrt(63); columns: one 1 among 10 -> CV = 3; panels (32 rows):
+    # counts [0, 1] -> CV 1, max/mean 2; one kept panel column of 2*10
+    assert f[3] == pytest.approx(1 / 640)
+    assert f[5] == pytest.approx(np.sqrt(63.0))
+    assert f[6] == pytest.approx(63 / 64)
+    assert f[7] == pytest.approx(3.0)
+    assert f[8] == pytest.approx(0.9)
+    assert f[9] == 1.0 and f[11] == 1.0
+    assert f[10] == pytest.approx(1 / 20)
+    assert f[12] == pytest.approx(1.0) and f[13] == pytest.approx(2.0)
+    assert f[14] == pytest.approx(3.0)
+
+
+def test_features_zero_signs_and_empty():
+    from oracle import features as OF
+    A = np.full((5, 5), -0.0, np.float32)
+    f = OF.features(A, 1)
+    assert f[3] == 0.0 and f[4] == pytest.approx(-6.0)
+    assert f[6] == 1.0 and f[8] == 1.0 and f[9] == 0.0 and f[13] == 0.0
+    A[2, 2] = np.nan
+    A[0, 4] = np.float32(1e-45)            # subnormal: kept
+    f = OF.features(A, 1)
+    assert f[3] == pytest.approx(2 / 25)
+    # a 40 x 3 matrix: panels of 32 and 8 rows, last panel short
+    B = np.zeros((40, 3), np.float32)
+    B[35:40, 1] = 1.0
+    B[0, 0] = 1.0
+    f = OF.features(B, 2)
+    assert f[9] == pytest.approx(6 / 2)      # kept panel columns (32 rows): (0,0), (1,1)
+    assert f[11] == pytest.approx(6 / 2)     # (8 rows): panel 0 col 0, panel 4 col 1
+    assert f[13] == pytest.approx(5 / 3.0)   # panel counts [1, 5]
