@@ -231,8 +231,8 @@ int32_t rosko_spmm_backward(const rosko_packed *A, const rosko_packed *At, const
                             int64_t lddb, float *dA_val, void *ws, size_t ws_bytes,
                             void *stream);
 
-/* ---- learned plan selection (Sec. 4.3's analytic tiling, Sec. 7's tunable
- * choice) ------------------------------------------------------------------
+/* ---- learned plan selection (in place of Sec. 4.2's analytic tiling; the
+ * auto-tuning of the exposed parameters that Sec. 6 leaves open) ----------
  * The choice of panel height mr, register tile and path is made per matrix
  * from ROSKO_NFEAT statistics of A by a Linear(F,H)-ReLU-Linear(H,H)-ReLU-
  * Linear(H,C) network that predicts, for each of the ROSKO_SCHED_CANDIDATES

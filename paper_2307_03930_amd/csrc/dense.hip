@@ -2,8 +2,9 @@
 //
 // Row skipping pays while a column of a panel holds few nonzeros; once the
 // panels are dense enough the matrix cores win, because they run zeros at a
-// multiple of the vector rate (the method's own advice in Sec. 5.3: dense
-// multiplication below about 75% sparsity).  This path computes every panel
+// multiple of the vector rate (the method itself beats dense multiplication
+// only above about 75% sparsity, Sec. 5.3, and hands lower sparsities to a
+// dense library in Sec. 5.4).  This path computes every panel
 // densely from the packed form:
 //   1. k_densify_*:   the column records are scattered into a zero-filled
 //                     dense copy Ad (M_pad x K_pad) -- exact, since the

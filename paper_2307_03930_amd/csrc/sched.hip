@@ -1,7 +1,7 @@
 // Learned plan selection: packing statistics and a small MLP.
 //
 // The method tunes its tiling from an analytic model of the machine
-// (Sec. 4.3) and leaves the choice open as a tunable (Sec. 7).  Here the
+// (Sec. 4.2) and exposes the tiling parameters for auto-tuning (Sec. 6).  Here the
 // choice (panel height mr, register tile, sparse or dense-MFMA path) is made
 // by a 3-layer MLP on 16 statistics of A that the packing count pass can
 // see, trained on measured runtimes.  Everything the network does runs in

@@ -1,5 +1,6 @@
-"""Learned plan selection for the Rosko SpMM (the tunable choice of Sec. 7
-in place of the analytic tiling model of Sec. 4.3).
+"""Learned plan selection for the Rosko SpMM (auto-tuning the exposed tiling
+parameters, which Sec. 6 leaves to future work, in place of the analytic tiling model of
+Sec. 4.2).
 
 Per matrix, a Linear(16,64)-ReLU-Linear(64,64)-ReLU-Linear(64,7) network
 predicts log(runtime / best runtime) of each of the 7 candidates
