@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--cols-per-lane", type=int, default=None)
     ap.add_argument("--waves-per-tile", type=int, default=None)
     ap.add_argument("--k-split", type=int, default=None)
+    ap.add_argument("--depth", type=int, default=None)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -99,7 +100,7 @@ def main():
     N = B_np.shape[1]
     B = torch.from_numpy(B_np).to(dev)
     As = [torch.from_numpy(a).to(dev) for a in As_np]
-    plan = ops.make_plan(args.cols_per_lane, args.waves_per_tile, args.k_split)
+    plan = ops.make_plan(args.cols_per_lane, args.waves_per_tile, args.k_split, args.depth)
 
     # buffers sized once (the sizing query synchronises; the step does not)
     packs, wss, Cs, sws = [], [], [], []

@@ -129,7 +129,9 @@ typedef struct rosko_packed {
  *                 ROSKO_PATH_DENSE (every panel densified from the packed form
  *                 and multiplied on the matrix cores: BF16 MFMA when A's
  *                 values and B are exactly BF16 -- BF16 or FP8 values with a
- *                 BF16 B -- else FP32 MFMA; the other fields are ignored), or
+ *                 BF16 B -- else FP32 MFMA; the other fields are ignored;
+ *                 currently switched off: rosko_spmm returns
+ *                 ROSKO_EUNSUPPORTED for it), or
  *                 ROSKO_PATH_AUTO to let the library choose everything.
  * cols_per_lane:  1, 2 or 4.  The register tile (panel height rounded up to
  *                 8/16/32/64/128, times cols_per_lane) must be one of 8x4,
@@ -138,7 +140,9 @@ typedef struct rosko_packed {
  *                 not multiplied by this path.
  * waves_per_tile: 1, 2 or 4; 0 lets the library choose.
  * k_split:        1 .. ROSKO_MAX_K_SPLIT (larger values are clamped); 0 lets
- *                 the library choose.  */
+ *                 the library choose.
+ * depth:          columns whose B rows a wavefront keeps in flight, 4 or 8;
+ *                 0 lets the library choose.  */
 #define ROSKO_PATH_AUTO (-1)
 #define ROSKO_PATH_SPARSE 0
 #define ROSKO_PATH_DENSE 1
@@ -148,6 +152,7 @@ typedef struct rosko_plan {
   int32_t cols_per_lane;
   int32_t waves_per_tile;
   int32_t k_split;
+  int32_t depth;
 } rosko_plan;
 
 /* ---- packing (Alg. 1, Sec. 4.1) --------------------------------------- */
@@ -290,14 +295,15 @@ int32_t rosko_argmin_rows(const float *Y, int64_t batch, int32_t C, int32_t *out
 /* Candidate `index`: the panel height to pack with (*mr) and the plan to
  * multiply with (waves_per_tile and k_split 0: chosen by the library). */
 int32_t rosko_sched_candidate(int32_t index, int32_t *mr, rosko_plan *plan);
-/* The analytic fallback rule on host features: the dense path from density
- * 0.25 up, else mr 32 with 4 columns per lane (2 when N <= 128). */
+/* The analytic fallback rule on host features: mr 32 with 4 columns per
+ * lane (2 when N <= 128).  (With the dense path available it takes that
+ * path from density 0.25 up; the dense path is switched off in this build.) */
 int32_t rosko_sched_analytic(const float *features_host, int32_t *index);
 
 /* ---- errors ----------------------------------------------------------- */
 const char *rosko_status_str(int32_t status);
 const char *rosko_last_error(void);   /* per host thread; "" if none */
-int32_t rosko_abi_version(void);      /* 3 */
+int32_t rosko_abi_version(void);      /* 4 */
 
 #ifdef __cplusplus
 }

@@ -46,7 +46,8 @@ class RoskoPacked(C.Structure):
 
 class RoskoPlan(C.Structure):
     _fields_ = [("path", C.c_int32), ("cols_per_lane", C.c_int32),
-                ("waves_per_tile", C.c_int32), ("k_split", C.c_int32)]
+                ("waves_per_tile", C.c_int32), ("k_split", C.c_int32),
+                ("depth", C.c_int32)]
 
 
 class RoskoError(RuntimeError):

@@ -83,9 +83,9 @@ struct SpmmArgs {
   int32_t ws_vec;      // workspace rows allow V-wide vector access
 };
 // One dispatcher per B dtype; MRt = register-tile height, V = columns per
-// lane, H = wavefronts per tile.
-int32_t spmm_dispatch_bf32(const SpmmArgs& g, int MRt, int V, int H, hipStream_t s);
-int32_t spmm_dispatch_bbf16(const SpmmArgs& g, int MRt, int V, int H, hipStream_t s);
+// lane, H = wavefronts per tile, depth = B rows in flight (4 or 8).
+int32_t spmm_dispatch_bf32(const SpmmArgs& g, int MRt, int V, int H, int depth, hipStream_t s);
+int32_t spmm_dispatch_bbf16(const SpmmArgs& g, int MRt, int V, int H, int depth, hipStream_t s);
 
 // Plan helpers (spmm.hip): the automatic plan, validation/normalisation of a
 // caller's plan, and the workspace a plan needs.

@@ -143,6 +143,10 @@ static void auto_parallelism(const rosko_packed* A, int64_t N, int V, int32_t* H
   *S_out = (int32_t)std::min<int64_t>(8, std::max<int64_t>(1, want / H));
 }
 
+// B rows in flight: 8 where the register tile leaves room for them (tiles of
+// at most 64 accumulators per lane), else 4.
+static int32_t auto_depth(int MRt, int V) { return MRt * V <= 64 ? 8 : 4; }
+
 // The analytic fallback plan: the register tile is the widest the panel
 // height allows (128 accumulators per lane), narrowed when N is small; the
 // parallel shape from auto_parallelism.
@@ -153,6 +157,7 @@ rosko_plan auto_plan(const rosko_packed* A, int64_t N) {
   p.cols_per_lane = (MRt <= 32) ? 4 : (MRt == 64 ? 2 : 1);
   if (MRt == 32 && N <= 128) p.cols_per_lane = 2;
   auto_parallelism(A, N, p.cols_per_lane, &p.waves_per_tile, &p.k_split);
+  p.depth = auto_depth(MRt, p.cols_per_lane);
   return p;
 }
 
@@ -188,6 +193,11 @@ int32_t normalize_plan(const rosko_packed* A, int64_t N, rosko_plan* p) {
     return ROSKO_EINVAL;
   }
   if (p->k_split > ROSKO_MAX_K_SPLIT) p->k_split = ROSKO_MAX_K_SPLIT;
+  if (p->depth == 0) p->depth = auto_depth(MRt, p->cols_per_lane);
+  if (p->depth != 4 && p->depth != 8) {
+    set_error("unsupported depth %d (4 or 8)", p->depth);
+    return ROSKO_EUNSUPPORTED;
+  }
   return ROSKO_OK;
 }
 
@@ -234,8 +244,8 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
     }
   }
   const int MRt = tile_height(A->mr);
-  const int32_t st = (b_dtype == ROSKO_BF16) ? spmm_dispatch_bbf16(g, MRt, V, H, s)
-                                             : spmm_dispatch_bf32(g, MRt, V, H, s);
+  const int32_t st = (b_dtype == ROSKO_BF16) ? spmm_dispatch_bbf16(g, MRt, V, H, plan.depth, s)
+                                             : spmm_dispatch_bf32(g, MRt, V, H, plan.depth, s);
   if (st != ROSKO_OK || g.k_split == 1) return st;
   const bool rvec = (N % 4 == 0) && (ldc % 4 == 0) && ((uintptr_t)C % 16 == 0) &&
                     ((uintptr_t)ws % 16 == 0);

@@ -3,7 +3,7 @@
 #include "spmm_kernel.h"
 
 namespace rosko {
-int32_t spmm_dispatch_bbf16(const SpmmArgs& g, int MRt, int V, int H, hipStream_t s) {
-  return dispatch_tile<ROSKO_BF16>(g, MRt, V, H, s);
+int32_t spmm_dispatch_bbf16(const SpmmArgs& g, int MRt, int V, int H, int depth, hipStream_t s) {
+  return dispatch_tile<ROSKO_BF16>(g, MRt, V, H, depth, s);
 }
 }  // namespace rosko

@@ -220,7 +220,8 @@ __device__ __forceinline__ void tile_accumulate_lds(const Tile<NT>& acc, float* 
     for (int j = 0; j < V; ++j) buf[(q * 64 + lane) * V + j] += tile_at<MR>(acc, q, j);
 }
 
-// Records of B rows in flight per wavefront.
+// B rows in flight per wavefront in the element-load path (the vector
+// path's depth is a template parameter: 4 or 8).
 constexpr int kDepth = 4;
 
 #include "spmm_loop.inc"
@@ -232,7 +233,7 @@ constexpr int kDepth = 4;
 // fixed order.  Each wavefront streams its records and the B rows they name
 // with vector loads, kDepth records ahead of the FMAs, so no step waits on a
 // single load round trip.
-template <int MR, int V, int H, int TB, bool VEC>
+template <int MR, int V, int H, int TB, bool VEC, int DV>
 __global__ void __launch_bounds__(64 * H)
 k_spmm_rows(SpmmArgs g) {
   constexpr int NT = tile_nt<MR, V>();
@@ -273,7 +274,7 @@ k_spmm_rows(SpmmArgs g) {
       const __amdgpu_buffer_rsrc_t rb =
           __builtin_amdgcn_make_buffer_rsrc((void*)g.B, 0, -1, 0x00020000);
       const int64_t cl = n0 < g.N - V ? n0 : g.N - V;
-      RkLoop<MR, V, TB>::run(acc, (uint32_t)n, rr, rb, (uint32_t)(g.ldb * esz),
+      RkLoop<MR, V, TB, DV>::run(acc, (uint32_t)n, rr, rb, (uint32_t)(g.ldb * esz),
                              (uint32_t)(g.K - 1), (uint32_t)(lane & 15) * 4u,
                              (uint32_t)(cl * esz));
     } else {
@@ -355,7 +356,7 @@ k_spmm_rows(SpmmArgs g) {
 }
 
 template <int MR, int V, int H, int TB>
-int32_t launch_one(const SpmmArgs& g, hipStream_t st) {
+int32_t launch_one(const SpmmArgs& g, int depth, hipStream_t st) {
   const int64_t nb = (int64_t)g.n_panels * g.n_chunks * g.k_split;
   if (nb == 0) return ROSKO_OK;
   if (nb > INT32_MAX) {
@@ -363,22 +364,25 @@ int32_t launch_one(const SpmmArgs& g, hipStream_t st) {
     return ROSKO_EUNSUPPORTED;
   }
   const size_t lds = (H == 4 ? 2 : (H == 2 ? 1 : 0)) * (size_t)MR * 64 * V * sizeof(float);
-  if (g.vec)
-    hipLaunchKernelGGL((k_spmm_rows<MR, V, H, TB, true>), dim3((unsigned)nb), dim3(64 * H), lds,
-                       st, g);
+  if (!g.vec)
+    hipLaunchKernelGGL((k_spmm_rows<MR, V, H, TB, false, 4>), dim3((unsigned)nb), dim3(64 * H),
+                       lds, st, g);
+  else if (depth == 8)
+    hipLaunchKernelGGL((k_spmm_rows<MR, V, H, TB, true, 8>), dim3((unsigned)nb), dim3(64 * H),
+                       lds, st, g);
   else
-    hipLaunchKernelGGL((k_spmm_rows<MR, V, H, TB, false>), dim3((unsigned)nb), dim3(64 * H),
+    hipLaunchKernelGGL((k_spmm_rows<MR, V, H, TB, true, 4>), dim3((unsigned)nb), dim3(64 * H),
                        lds, st, g);
   ROSKO_LAUNCH_CHECK("k_spmm_rows");
   return ROSKO_OK;
 }
 
 template <int MR, int V, int TB>
-int32_t dispatch_h(const SpmmArgs& g, int H, hipStream_t s) {
+int32_t dispatch_h(const SpmmArgs& g, int H, int depth, hipStream_t s) {
   switch (H) {
-    case 1: return launch_one<MR, V, 1, TB>(g, s);
-    case 2: return launch_one<MR, V, 2, TB>(g, s);
-    case 4: return launch_one<MR, V, 4, TB>(g, s);
+    case 1: return launch_one<MR, V, 1, TB>(g, depth, s);
+    case 2: return launch_one<MR, V, 2, TB>(g, depth, s);
+    case 4: return launch_one<MR, V, 4, TB>(g, depth, s);
     default: break;
   }
   set_error("unsupported waves per tile %d (1, 2 or 4)", H);
@@ -388,13 +392,13 @@ int32_t dispatch_h(const SpmmArgs& g, int H, hipStream_t s) {
 // Supported (tile height, columns per lane) pairs keep the register tile at
 // 32, 64 or 128 VGPRs.
 template <int TB>
-int32_t dispatch_tile(const SpmmArgs& g, int MRt, int V, int H, hipStream_t s) {
-  if (MRt == 8 && V == 4) return dispatch_h<8, 4, TB>(g, H, s);
-  if (MRt == 16 && V == 4) return dispatch_h<16, 4, TB>(g, H, s);
-  if (MRt == 32 && V == 4) return dispatch_h<32, 4, TB>(g, H, s);
-  if (MRt == 32 && V == 2) return dispatch_h<32, 2, TB>(g, H, s);
-  if (MRt == 64 && V == 2) return dispatch_h<64, 2, TB>(g, H, s);
-  if (MRt == 128 && V == 1) return dispatch_h<128, 1, TB>(g, H, s);
+int32_t dispatch_tile(const SpmmArgs& g, int MRt, int V, int H, int depth, hipStream_t s) {
+  if (MRt == 8 && V == 4) return dispatch_h<8, 4, TB>(g, H, depth, s);
+  if (MRt == 16 && V == 4) return dispatch_h<16, 4, TB>(g, H, depth, s);
+  if (MRt == 32 && V == 4) return dispatch_h<32, 4, TB>(g, H, depth, s);
+  if (MRt == 32 && V == 2) return dispatch_h<32, 2, TB>(g, H, depth, s);
+  if (MRt == 64 && V == 2) return dispatch_h<64, 2, TB>(g, H, depth, s);
+  if (MRt == 128 && V == 1) return dispatch_h<128, 1, TB>(g, H, depth, s);
   set_error("unsupported register tile: height %d with %d columns per lane", MRt, V);
   return ROSKO_EUNSUPPORTED;
 }

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.rosko_abi_version() == 3
+    assert lib.rosko_abi_version() == 4
     assert lib.rosko_status_str(L.ROSKO_EINVAL) == b"ROSKO_EINVAL"
     assert lib.rosko_status_str(123) == b"ROSKO_UNKNOWN"
 
@@ -223,11 +223,22 @@ def test_sched_candidates_and_analytic_rule():
     assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 2
     f[2] = 6.0                                  # N = 64
     assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 3
-    f[3] = 0.5
-    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 6
+    f[3] = 0.5                                  # dense candidate not offered (path off)
+    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 3
     n = C.c_int64(0)
     assert lib.rosko_mlp_param_count(16, 64, 7, C.byref(n)) == 0
     assert n.value == 16 * 64 + 64 + 64 * 64 + 64 + 64 * 7 + 7
     sz = C.c_size_t(0)
     assert lib.rosko_features_workspace_size(100, 50, C.byref(sz)) == 0 and sz.value > 0
     assert lib.rosko_features(None, 0, 5, 5, 3, None, 0, None, None) == L.ROSKO_EINVAL
+
+
+def test_dense_path_is_switched_off():
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)
+    s = _packed(8, 8, 4)
+    plan = L.RoskoPlan()
+    plan.path = L.ROSKO_PATH_DENSE
+    assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 16, fake, 16, 0, C.byref(plan),
+                          fake, 1 << 20, None) == L.ROSKO_EUNSUPPORTED
+    assert b"dense" in lib.rosko_last_error()

@@ -298,8 +298,16 @@ def test_spmm_precision_form_sampled(s, dtype):
 
 
 # --------------------------------------------------------------------------
-# dense-MFMA path: every panel densified from the packed form
+# dense-MFMA path: every panel densified from the packed form.  Switched off
+# in the library (rosko_spmm returns ROSKO_EUNSUPPORTED): two GPU runs that
+# called it back to back at untested shapes faulted the GPU and the cause has
+# not been found, so these tests are skipped until it is.
 # --------------------------------------------------------------------------
+DENSE_OFF = pytest.mark.skip(reason="dense-MFMA path switched off: two GPU faults in runs "
+                             "that called it repeatedly; cause not found")
+
+
+@DENSE_OFF
 @pytest.mark.parametrize("M,K,N,mr", [(512, 512, 512, 32), (77, 131, 190, 13), (300, 40, 1, 8),
                                       (129, 257, 129, 64), (1, 1, 1, 1)])
 def test_dense_path_f32(M, K, N, mr):
@@ -316,6 +324,7 @@ def test_dense_path_f32(M, K, N, mr):
     assert e <= TOL_F32
 
 
+@DENSE_OFF
 @pytest.mark.parametrize("dtype", ["bf16", "fp8"])
 @pytest.mark.parametrize("b_bf16", [False, True])
 def test_dense_path_quantised(dtype, b_bf16):
@@ -337,6 +346,7 @@ def test_dense_path_quantised(dtype, b_bf16):
     assert e <= TOL_F32
 
 
+@DENSE_OFF
 def test_dense_path_beta_and_strides():
     say("dense path beta=1 with padded leading dimensions")
     A = synth.sparse_matrix(96, 200, 0.4, 624)
@@ -356,6 +366,7 @@ def test_dense_path_beta_and_strides():
     assert not got[:, 130:].any()
 
 
+@DENSE_OFF
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_dense_path_precision_form_sampled(dtype):
     """4096 x 4096 at 90% times the 4096 x 2048 activations on the matrix
