@@ -45,7 +45,7 @@ struct PackWs {
   size_t bytes;        // total
   int64_t P, NT;
 };
-constexpr int kPackTile = 1024;      // (panel, column) pairs per scan tile
+constexpr int kPackTile = 256;       // (panel, column) pairs per scan tile (one per thread)
 constexpr int kRecVals = 12;         // values per 16-dword column record
 constexpr int kPackThreads = 256;
 PackWs pack_ws_layout(int64_t R, int64_t S, int32_t mr, bool transpose);

@@ -54,6 +54,18 @@ __device__ __forceinline__ uint8_t enc_fp8(float y) {
 // pairs; the scans below carry all three.
 struct Tri { int64_t a, b, c; };
 
+// Rows i0 .. i0+31 of a column into registers: 32 independent loads in
+// flight at once (addresses clamped to the panel's last row; the caller
+// masks entries at or past `rows`).
+__device__ __forceinline__ void load_rows32(const float* __restrict__ col, int64_t lda, int i0,
+                                            int rows, float* x) {
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const int i = (i0 + j < rows) ? i0 + j : rows - 1;
+    x[j] = col[(int64_t)i * lda];
+  }
+}
+
 // Records a kept column of `cnt` values occupies.
 __device__ __forceinline__ int64_t n_records(int cnt) {
   return (cnt + kRecVals - 1) / kRecVals;
@@ -100,9 +112,9 @@ __device__ __forceinline__ uint32_t dec_fp8(uint8_t c) {
 }
 
 // ------------------------------------------------------------------ count
-// Tile t covers flattened indices [t*1024, t*1024+1024); thread x handles
-// f = t*1024 + x + 256*j, j = 0..3 (adjacent threads -> adjacent columns, so
-// the row loads are coalesced).
+// Tile t covers flattened indices [t*256, t*256+256); thread x handles
+// f = t*256 + x (adjacent threads -> adjacent columns, so the row loads are
+// coalesced), with all rows of its column loaded in batches of 32.
 __global__ void __launch_bounds__(kPackThreads)
 k_pack_count(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr,
              int64_t P, int32_t* __restrict__ counts, int64_t* __restrict__ tile_sums) {
@@ -118,13 +130,12 @@ k_pack_count(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
       const int rows = (int)((R - r0) < mr ? (R - r0) : mr);
       const float* col = A + r0 * lda + k;
       int c = 0;
-      int i = 0;
-      for (; i + 4 <= rows; i += 4) {
-        float x0 = col[(int64_t)(i + 0) * lda], x1 = col[(int64_t)(i + 1) * lda];
-        float x2 = col[(int64_t)(i + 2) * lda], x3 = col[(int64_t)(i + 3) * lda];
-        c += kept(x0) + kept(x1) + kept(x2) + kept(x3);
+      for (int i0 = 0; i0 < rows; i0 += 32) {
+        float x[32];
+        load_rows32(col, lda, i0, rows, x);
+#pragma unroll
+        for (int j = 0; j < 32; ++j) c += (i0 + j < rows) & kept(x[j]);
       }
-      for (; i < rows; ++i) c += kept(col[(int64_t)i * lda]);
       counts[f] = c;
       my_nnz += c;
       my_cols += (c != 0);
@@ -244,22 +255,25 @@ k_pack_write(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
     // column records: header, row bytes, FP32 values (unused slots zero)
     int in_rec = 0;
     int64_t r = rec_off;
-    uint32_t lw[3] = {0u, 0u, 0u};
+    uint32_t lw0 = 0u, lw1 = 0u, lw2 = 0u;     // row bytes of the open record
     auto flush = [&](int cnt) {
       if (r < nrec_cap) {
         uint32_t* d = rec + r * 16;
-        d[0] = ((uint32_t)k << 8) | (uint32_t)cnt;
-        d[1] = lw[0];
-        d[2] = lw[1];
-        d[3] = lw[2];
+        *reinterpret_cast<uint4*>(d) = make_uint4(((uint32_t)k << 8) | (uint32_t)cnt, lw0, lw1,
+                                                  lw2);
         for (int t = cnt; t < kRecVals; ++t) d[4 + t] = 0u;
       }
-      lw[0] = lw[1] = lw[2] = 0u;
+      lw0 = lw1 = lw2 = 0u;
       ++r;
     };
-    for (int i = 0; i < rows; ++i) {
-      const float x = col[(int64_t)i * lda];
-      if (!kept(x)) continue;
+    for (int i0 = 0; i0 < rows; i0 += 32) {
+      float xs[32];
+      load_rows32(col, lda, i0, rows, xs);
+#pragma unroll
+      for (int jj = 0; jj < 32; ++jj) {
+      const int i = i0 + jj;
+      const float x = xs[jj];
+      if (i >= rows || !kept(x)) continue;
       uint32_t vbits;
       if (DT == ROSKO_F32) {
         vbits = __float_as_uint(x);
@@ -276,10 +290,14 @@ k_pack_write(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
         loc[z] = (uint8_t)i;
         if (DT == ROSKO_F32) reinterpret_cast<float*>(val)[z] = x;
       }
-      lw[in_rec >> 2] |= (uint32_t)i << (8 * (in_rec & 3));
+      const uint32_t rb = (uint32_t)i << (8 * (in_rec & 3));
+      if (in_rec < 4) lw0 |= rb;
+      else if (in_rec < 8) lw1 |= rb;
+      else lw2 |= rb;
       if (r < nrec_cap) rec[r * 16 + 4 + in_rec] = vbits;
       ++z;
       if (++in_rec == kRecVals) { flush(kRecVals); in_rec = 0; }
+      }
     }
     if (in_rec) flush(in_rec);
   }
