@@ -18,9 +18,16 @@ depth D (4 or 8):
                        base + j*MR + r
 Per column: the header (k << 8 | count) is read with v_readfirstlane,
 min(k, K-1) * ldb * elem becomes the SGPR offset of a buffer load of the B
-row; the values are broadcast from the record register with DPP
-row_newbcast into v_fmac_f32 whose accumulator is addressed relative to the
-row byte (s_set_gpr_idx_on, SRC2 and DST).
+row.  When the column's turn comes, its three row words go to SGPRs
+(v_readlane, bytes masked to the tile height) and one computed jump
+(s_getpc / s_setpc) enters a run of twelve equal-sized value blocks at the
+block of value count-1, so the values are applied without a branch per
+value; the count is clamped to [1, 12] first, so the target is always a
+block start.  A value block extracts its row byte (s_bfe_u32) into the
+index of VGPR-relative addressing (s_set_gpr_idx_idx, SRC2 and DST turned on
+once per column) and issues V v_fmac_f32 whose A operand is the value's
+lane of the record register broadcast by DPP row_newbcast.  A CPU test
+disassembles the build and checks the block spacing the jump assumes.
 
 Run `python gen_spmm_loop.py` after changing it; a CPU test checks that the
 committed spmm_loop.inc matches.
@@ -30,6 +37,7 @@ import os
 TILES = [(8, 4), (16, 4), (32, 2), (32, 4), (64, 2), (128, 1)]
 DTYPES = ["f32", "bf16"]
 DEPTHS = [4, 8]
+PC = 88          # s[88:89]: program counter of the per-record jump (clobbered)
 
 
 def unit_dwords(dt, v):
@@ -51,6 +59,9 @@ class Plan:
         self.nclob = nxt                       # v0 .. v(nclob-1) clobbered
         self.base = (nxt + 7) // 8 * 8         # tile base
         self.nt = mr * v // 32
+        # bytes of one value block: s_bfe_u32 with literal (8), s_set_gpr_idx_idx
+        # (4), V v_fmac_f32_dpp (8 each)
+        self.blk = 12 + 8 * v
 
     def tile_ranges(self):
         return [(self.base + 32 * q, self.base + 32 * q + 31) for q in range(self.nt)]
@@ -84,7 +95,7 @@ class Plan:
 def gen_variant(mr, v, dt, D):
     pl = Plan(mr, v, dt, D)
     R = pl.R
-    mask = "0x%08x" % ((mr - 1) * 0x01010101)
+    bits = mr.bit_length() - 1               # row index width: log2 of the tile height
     cols = [pl.base + j * mr for j in range(v)]
     L = []
 
@@ -92,8 +103,7 @@ def gen_variant(mr, v, dt, D):
         L.append(x)
 
     def rload_const(j):
-        a(f"s_min_u32 %[t], {j}, %[nm1]")
-        a("s_lshl_b32 %[t], %[t], 6")
+        a(f"s_min_u32 %[t], {j * 64}, %[olast]")
         a(f"buffer_load_dword v{j}, %[vro], %[rr], %[t] offen")
 
     def bload(h, s):
@@ -107,34 +117,37 @@ def gen_variant(mr, v, dt, D):
         s = u % D
         _, bregs, conv = pl.b_slot(s)
         vr = f"v{u}"
-        end = f".Lr{u}_%="
+        # count of record i, then the header of record i+D into the same SGPR
+        # (its B row is issued after the values, when slot s is free)
         a(f"s_and_b32 %[c], %[h{s}], 0xff")
+        a(f"v_readfirstlane_b32 %[h{s}], v{(u + D) % R}")
         for c in conv:
             a(c)
-        a("s_nop 1")
-        word = 1
-        a(f"v_readlane_b32 %[w], {vr}, 1")
-        a(f"s_and_b32 %[w], %[w], {mask}")
-        for t in range(12):
-            if t > 0:
-                a(f"s_cmp_lt_u32 %[c], {t + 1}")
-                a(f"s_cbranch_scc1 {end}")
-                if t % 4 == 0:
-                    word += 1
-                    a("s_set_gpr_idx_off")
-                    a(f"v_readlane_b32 %[w], {vr}, {word}")
-                    a(f"s_and_b32 %[w], %[w], {mask}")
-                else:
-                    a("s_lshr_b32 %[w], %[w], 8")
-            a("s_set_gpr_idx_on %[w], gpr_idx(SRC2,DST)")
+        for wd in range(3):
+            a(f"v_readlane_b32 %[w{wd}], {vr}, {wd + 1}")
+        # count clamped to 12; jump to the block of value count-1 (count 0
+        # lands on .Le); the blocks run down to value 0
+        a("s_min_u32 %[c], %[c], 12")
+        a(f"s_mul_i32 %[c], %[c], {pl.blk}")
+        a(f"s_sub_u32 %[c], .Le{u}_%= - .Lp{u}_%=, %[c]")
+        a("s_set_gpr_idx_on %[c], gpr_idx(SRC2,DST)")
+        a(f"s_getpc_b64 s[{PC}:{PC + 1}]")
+        L.append(f".Lp{u}_%=:")
+        a(f"s_add_u32 s{PC}, s{PC}, %[c]")
+        a(f"s_addc_u32 s{PC + 1}, s{PC + 1}, 0")
+        a(f"s_setpc_b64 s[{PC}:{PC + 1}]")
+        for t in range(11, -1, -1):
+            # row byte t, cut to log2(MR) bits: always inside the tile
+            a(f"s_bfe_u32 %[x], %[w{t // 4}], {hex((bits << 16) | 8 * (t % 4))}")
+            a("s_set_gpr_idx_idx %[x]")
             for j in range(v):
                 a(f"v_fmac_f32_dpp v{cols[j]}, {vr}, {bregs[j]} row_newbcast:{4 + t} "
                   "row_mask:0xf bank_mask:0xf")
-        a(f"{end}:")
+        L.append(f".Le{u}_%=:")
         a("s_set_gpr_idx_off")
 
-    # ---- prologue: records 0..D-1, then for each: header, B row, record j+D
-    a("s_mov_b32 %[i], 0")
+    # ---- prologue: records 0..D-1, then for each: header, B row, record j+D.
+    # Record offsets are clamped to the run's last record.
     for j in range(D):
         rload_const(j)
     for j in range(D):
@@ -142,29 +155,28 @@ def gen_variant(mr, v, dt, D):
         a(f"v_readfirstlane_b32 %[h{j}], v{j}")
         bload(f"h{j}", j)
         rload_const(D + j)
+    a(f"s_mov_b32 %[o], {R * 64}")
     # ---- steady state, unrolled over the 2D record slots.  At the start of
     # step i the loads in flight are, oldest first, B(i) R(i+D) B(i+1) ...
-    # B(i+D-1) R(i+2D-1): vmcnt(2D-1) completes B(i), vmcnt(2D-2) R(i+D).
+    # B(i+D-1) R(i+2D-1): vmcnt(2D-2) completes B(i) and R(i+D).  o is the
+    # byte offset of record i+2D; the run ends when it reaches (n+2D)*64.
     a(".Lloop%=:")
     for u in range(R):
         s = u % D
-        a("s_cmp_ge_u32 %[i], %[n]")
+        a("s_cmp_ge_u32 %[o], %[oend]")
         a("s_cbranch_scc1 .Ldone%=")
-        a(f"s_waitcnt vmcnt({2 * D - 1})")
-        body(u)
         a(f"s_waitcnt vmcnt({2 * D - 2})")
-        a(f"v_readfirstlane_b32 %[h{s}], v{(u + D) % R}")
+        body(u)
         bload(f"h{s}", s)
-        a(f"s_add_u32 %[t], %[i], {R}")
-        a("s_min_u32 %[t], %[t], %[nm1]")
-        a("s_lshl_b32 %[t], %[t], 6")
+        a("s_min_u32 %[t], %[o], %[olast]")
         a(f"buffer_load_dword v{u}, %[vro], %[rr], %[t] offen")
-        a("s_add_u32 %[i], %[i], 1")
+        a("s_add_u32 %[o], %[o], 64")
     a("s_branch .Lloop%=")
     a(".Ldone%=:")
     a("s_waitcnt vmcnt(0)")
 
-    text = "".join(f'      "{x}\\n\\t"\n' for x in L)
+    text = "".join((f'      "{x}\\n"\n' if x.endswith(":") else f'      "{x}\\n\\t"\n')
+                   for x in L)
     outs = ", ".join(f'"+{{v[{lo}:{hi}]}}"(acc.t[{q}])'
                      for q, (lo, hi) in enumerate(pl.tile_ranges()))
     clob = ", ".join(f'"v{r}"' for r in range(pl.nclob))
@@ -174,14 +186,15 @@ def gen_variant(mr, v, dt, D):
 __device__ __forceinline__ void {pl.fn()}(Tile<{pl.nt}>& acc, uint32_t n,
                                        __amdgpu_buffer_rsrc_t rr, __amdgpu_buffer_rsrc_t rb,
                                        uint32_t ldbb, uint32_t km1, uint32_t vro, uint32_t vbo) {{
-  uint32_t i, t, k, w, c, {hdecl};
-  const uint32_t nm1 = n - 1;
+  uint32_t o, t, k, c, x, w0, w1, w2, {hdecl};
+  const uint32_t olast = (n - 1) * 64, oend = (n + {R}) * 64;
   asm volatile(
-{text}      : {outs}, [i] "=&s"(i), [t] "=&s"(t), [k] "=&s"(k), [w] "=&s"(w), [c] "=&s"(c),
+{text}      : {outs}, [o] "=&s"(o), [t] "=&s"(t), [k] "=&s"(k), [c] "=&s"(c), [x] "=&s"(x),
+        [w0] "=&s"(w0), [w1] "=&s"(w1), [w2] "=&s"(w2),
         {houts}
-      : [n] "s"(n), [nm1] "s"(nm1), [ldbb] "s"(ldbb), [km1] "s"(km1), [rr] "s"(rr), [rb] "s"(rb),
+      : [oend] "s"(oend), [olast] "s"(olast), [ldbb] "s"(ldbb), [km1] "s"(km1), [rr] "s"(rr), [rb] "s"(rb),
         [vro] "v"(vro), [vbo] "v"(vbo)
-      : {clob}, "m0", "scc", "memory");
+      : {clob}, "s{PC}", "s{PC + 1}", "m0", "scc", "memory");
 }}
 """
 
