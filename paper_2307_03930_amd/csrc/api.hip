@@ -191,8 +191,7 @@ static int32_t pack_common(const float* A, int64_t R, int64_t S, int64_t lda, in
   if (val_dtype == ROSKO_FP8_E4M3) {
     if ((st = launch_row_scale(A, R, S, lda, out->row_scale, s))) return st;
   }
-  if ((st = launch_pack_count_scan(A, R, S, lda, mr, ws, L, out, s))) return st;
-  return launch_pack_write(A, R, S, lda, mr, val_dtype, ws, L, out, s);
+  return launch_pack(A, R, S, lda, mr, val_dtype, ws, L, out, s);
 }
 
 int32_t rosko_pack(const float* A, int64_t M, int64_t K, int64_t lda, int32_t mr,

@@ -45,19 +45,24 @@ struct PackWs {
   size_t bytes;        // total
   int64_t P, NT;
 };
-constexpr int kPackTile = 256;       // (panel, column) pairs per scan tile (one per thread)
+constexpr int kPackTile = 64;        // (panel, column) pairs per tile: one wavefront, one per lane
 constexpr int kRecVals = 12;         // values per 16-dword column record
-constexpr int kPackThreads = 256;
+constexpr int kPackThreads = 64;
+// Up to this many tiles the write pass adds up the tile sums before its own
+// tile itself (no separate scan launch); beyond, a one-workgroup scan runs.
+constexpr int64_t kLocalPrefixTiles = 4096;
 PackWs pack_ws_layout(int64_t R, int64_t S, int32_t mr, bool transpose);
 
 // Enqueue count + tile scan (everything rosko_pack_query needs).
 int32_t launch_pack_count_scan(const float* A, int64_t R, int64_t S, int64_t lda, int32_t mr,
                                void* ws, const PackWs& L, const rosko_packed* out,
                                hipStream_t s);
-// Enqueue the write pass (values, loc, col arrays, panel pointers).
-int32_t launch_pack_write(const float* A, int64_t R, int64_t S, int64_t lda, int32_t mr,
-                          int32_t val_dtype, void* ws, const PackWs& L, const rosko_packed* out,
-                          hipStream_t s);
+// Enqueue the whole packing: count, then either the write pass with local
+// tile prefixes (which also closes the pointer arrays and the totals), or
+// the scan and the write pass reading its prefixes.
+int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t mr,
+                    int32_t val_dtype, void* ws, const PackWs& L, const rosko_packed* out,
+                    hipStream_t s);
 int32_t launch_row_scale(const float* A, int64_t R, int64_t S, int64_t lda, float* scale,
                          hipStream_t s);
 int32_t launch_transpose(const float* A, int64_t M, int64_t K, int64_t lda, float* At,

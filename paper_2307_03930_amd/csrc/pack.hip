@@ -1,8 +1,13 @@
-// Rosko packing on gfx950 (Alg. 1, Sec. 4.1), as three passes:
+// Rosko packing on gfx950 (Alg. 1, Sec. 4.1), as two or three passes:
 //   count  -- values per (panel, column) and per-tile sums,
-//   scan   -- exclusive prefix over tiles (one workgroup, exact integers),
+//   scan   -- exclusive prefix over tiles (one workgroup, exact integers);
+//             skipped when there are at most kLocalPrefixTiles tiles, where
+//             each write workgroup adds up the sums of the tiles before its
+//             own (and the last one closes the pointer arrays),
 //   write  -- per (panel, column): col_ind / col_nnz / col_ptr at its slot and
 //             the column's values and in-panel rows at its value offset.
+// A tile is 64 (panel, column) pairs, one per lane of a one-wavefront
+// workgroup, so even small matrices spread over many CUs.
 // The flattened index f = p*S + k walks panels, then columns, which is the
 // packed order, so the prefix of the counts at f is exactly the value offset
 // (and the prefix of "count > 0" the column slot) that Alg. 1's running
@@ -102,6 +107,34 @@ __device__ Tri block_excl_scan(Tri v, Tri* total) {
   return Tri{base.a + inc.a - v.a, base.b + inc.b - v.b, base.c + inc.c - v.c};
 }
 
+// Inclusive prefix sum over a wavefront of 32-bit integers with DPP: three
+// row shifts of the input, shifts by 4 and 8 inside each 16-lane row, then
+// the row totals broadcast forward (row_bcast:15 into rows 1 and 3,
+// row_bcast:31 into rows 2 and 3).  Lanes without a source add 0.
+__device__ __forceinline__ int wave_incl_sum(int x) {
+  int v = x;
+  v += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, x, 0x113, 0xf, 0xf, true);   // row_shr:3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xe, false);  // row_shr:4, lanes 4..15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xc, false);  // row_shr:8, lanes 8..15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
+// Exclusive prefix and total of (values, kept columns, records) over a
+// one-wavefront tile; per-tile sums fit 32 bits (64 columns of at most 256
+// rows).
+struct Tri32 { int a, b, c; };
+__device__ __forceinline__ Tri32 wave_excl_scan3(int c, Tri32* total) {
+  const int b = c != 0, r = (int)n_records(c);
+  const int ia = wave_incl_sum(c), ib = wave_incl_sum(b), ic = wave_incl_sum(r);
+  *total = Tri32{__builtin_amdgcn_readlane(ia, 63), __builtin_amdgcn_readlane(ib, 63),
+                 __builtin_amdgcn_readlane(ic, 63)};
+  return Tri32{ia - c, ib - b, ic - r};
+}
+
 // FP32 value of a packed value (FP8: the code's value, unscaled), as bits.
 __device__ __forceinline__ uint32_t dec_bf16(uint16_t h) { return (uint32_t)h << 16; }
 __device__ __forceinline__ uint32_t dec_fp8(uint8_t c) {
@@ -112,42 +145,55 @@ __device__ __forceinline__ uint32_t dec_fp8(uint8_t c) {
 }
 
 // ------------------------------------------------------------------ count
-// Tile t covers flattened indices [t*256, t*256+256); thread x handles
-// f = t*256 + x (adjacent threads -> adjacent columns, so the row loads are
+// Tile t covers flattened indices [t*64, t*64+64); lane x handles
+// f = t*64 + x (adjacent lanes -> adjacent columns, so the row loads are
 // coalesced), with all rows of its column loaded in batches of 32.
 __global__ void __launch_bounds__(kPackThreads)
 k_pack_count(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr,
              int64_t P, int32_t* __restrict__ counts, int64_t* __restrict__ tile_sums) {
+  static_assert(kPackTile == 64 && kPackThreads == 64, "one wavefront per tile");
   const int64_t total = P * S;
-  const int64_t f0 = (int64_t)blockIdx.x * kPackTile;
-  int64_t my_nnz = 0, my_cols = 0, my_recs = 0;
+  const int64_t f = (int64_t)blockIdx.x * kPackTile + threadIdx.x;
+  int c = 0;
+  if (f < total) {
+    const int64_t p = f / S, k = f - p * S;
+    const int64_t r0 = p * mr;
+    const int rows = (int)((R - r0) < mr ? (R - r0) : mr);
+    const float* col = A + r0 * lda + k;
+    for (int i0 = 0; i0 < rows; i0 += 32) {
+      float x[32];
+      load_rows32(col, lda, i0, rows, x);
 #pragma unroll
-  for (int j = 0; j < kPackTile / kPackThreads; ++j) {
-    const int64_t f = f0 + threadIdx.x + (int64_t)kPackThreads * j;
-    if (f < total) {
-      const int64_t p = f / S, k = f - p * S;
-      const int64_t r0 = p * mr;
-      const int rows = (int)((R - r0) < mr ? (R - r0) : mr);
-      const float* col = A + r0 * lda + k;
-      int c = 0;
-      for (int i0 = 0; i0 < rows; i0 += 32) {
-        float x[32];
-        load_rows32(col, lda, i0, rows, x);
-#pragma unroll
-        for (int j = 0; j < 32; ++j) c += (i0 + j < rows) & kept(x[j]);
-      }
-      counts[f] = c;
-      my_nnz += c;
-      my_cols += (c != 0);
-      my_recs += n_records(c);
+      for (int j = 0; j < 32; ++j) c += (i0 + j < rows) & kept(x[j]);
     }
+    counts[f] = c;
   }
-  Tri tot;
-  (void)block_excl_scan(Tri{my_nnz, my_cols, my_recs}, &tot);
+  Tri32 tot;
+  (void)wave_excl_scan3(c, &tot);
   if (threadIdx.x == 0) {
     tile_sums[3 * blockIdx.x] = tot.a;
     tile_sums[3 * blockIdx.x + 1] = tot.b;
     tile_sums[3 * blockIdx.x + 2] = tot.c;
+  }
+}
+
+// Totals (nnz, ncols, overflow flag, nrec) and the closing entries of the
+// pointer arrays, from the grand sums; one thread.
+__device__ void close_packing(Tri tot, int64_t* __restrict__ totals, int64_t P, int64_t S,
+                              int64_t nnz_cap, int64_t ncols_cap, int64_t nrec_cap,
+                              int64_t* __restrict__ panel_nz_ptr,
+                              int64_t* __restrict__ panel_col_ptr, int64_t* __restrict__ col_ptr,
+                              int64_t* __restrict__ kblk_ptr) {
+  const int64_t nkb = (S + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
+  totals[0] = tot.a;
+  totals[1] = tot.b;
+  totals[2] = (tot.a > nnz_cap || tot.b > ncols_cap || tot.c > nrec_cap) ? 1 : 0;
+  totals[3] = tot.c;
+  if (panel_nz_ptr) {
+    panel_nz_ptr[P] = tot.a;
+    panel_col_ptr[P] = tot.b;
+    if (tot.b <= ncols_cap) col_ptr[tot.b] = tot.a;
+    if (P > 0) kblk_ptr[(P - 1) * (nkb + 1) + nkb] = tot.c;   // end of the last panel
   }
 }
 
@@ -176,19 +222,9 @@ k_pack_scan(const int64_t* __restrict__ tile_sums, int64_t* __restrict__ tile_of
     carry.b += tot.b;
     carry.c += tot.c;
   }
-  const int64_t nkb = (S + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
-  if (threadIdx.x == 0) {
-    totals[0] = carry.a;
-    totals[1] = carry.b;
-    totals[2] = (carry.a > nnz_cap || carry.b > ncols_cap || carry.c > nrec_cap) ? 1 : 0;
-    totals[3] = carry.c;
-    if (panel_nz_ptr) {
-      panel_nz_ptr[P] = carry.a;
-      panel_col_ptr[P] = carry.b;
-      if (carry.b <= ncols_cap) col_ptr[carry.b] = carry.a;
-      if (P > 0) kblk_ptr[(P - 1) * (nkb + 1) + nkb] = carry.c;   // end of the last panel
-    }
-  }
+  if (threadIdx.x == 0)
+    close_packing(carry, totals, P, S, nnz_cap, ncols_cap, nrec_cap, panel_nz_ptr, panel_col_ptr,
+                  col_ptr, kblk_ptr);
   // With no columns at all every panel starts at 0 (the write pass, which
   // sets panel starts at k = 0, has nothing to visit).
   if (S == 0 && panel_nz_ptr) {
@@ -200,77 +236,32 @@ k_pack_scan(const int64_t* __restrict__ tile_sums, int64_t* __restrict__ tile_of
   }
 }
 
-// ------------------------------------------------------------------ write
+// The values of one kept column (rows 0..rows-1 of its panel, the first 32
+// already in xs): values and in-panel rows at their offset z, and the
+// column records (header, row bytes, FP32 values, unused slots zero) from
+// record r.  Writes stop at the capacities.
 template <int DT>
-__global__ void __launch_bounds__(kPackThreads)
-k_pack_write(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr,
-             int64_t P, const int32_t* __restrict__ counts, const int64_t* __restrict__ tile_offs,
-             int64_t nnz_cap, int64_t ncols_cap, int64_t* __restrict__ panel_nz_ptr,
-             int64_t* __restrict__ panel_col_ptr, int32_t* __restrict__ col_ind,
-             int32_t* __restrict__ col_nnz, int64_t* __restrict__ col_ptr,
-             uint8_t* __restrict__ loc, void* __restrict__ val,
-             const float* __restrict__ row_scale, int64_t* __restrict__ kblk_ptr,
-             int64_t nrec_cap, uint32_t* __restrict__ rec) {
-  const int64_t total = P * S;
-  const int64_t nkb = (S + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
-  const int64_t f0 = (int64_t)blockIdx.x * kPackTile;
-  Tri carry{tile_offs[3 * blockIdx.x], tile_offs[3 * blockIdx.x + 1],
-            tile_offs[3 * blockIdx.x + 2]};
-  // The tile is visited as four rows of 256 flattened indices; within a row
-  // thread x holds f0 + 256*j + x, so a block scan per row plus the carry of
-  // the rows before gives the exclusive prefix in flattened order.
-#pragma unroll 1
-  for (int j = 0; j < kPackTile / kPackThreads; ++j) {
-    const int64_t f = f0 + (int64_t)kPackThreads * j + threadIdx.x;
-    const int c = (f < total) ? counts[f] : 0;
-    Tri tot;
-    Tri e = block_excl_scan(Tri{c, c != 0, n_records(c)}, &tot);
-    const int64_t nz_off = carry.a + e.a;
-    const int64_t col_slot = carry.b + e.b;
-    const int64_t rec_off = carry.c + e.c;
-    carry.a += tot.a;
-    carry.b += tot.b;
-    carry.c += tot.c;
-    if (f >= total) continue;
-    const int64_t p = f / S, k = f - p * S;
-    if (k == 0) {
-      panel_nz_ptr[p] = nz_off;
-      panel_col_ptr[p] = col_slot;
+__device__ __forceinline__ void write_column(const float* __restrict__ col, int64_t lda, int rows,
+                                             float* xs, uint32_t k, int64_t r0, int64_t z,
+                                             int64_t r, int64_t nnz_cap, int64_t nrec_cap,
+                                             uint8_t* __restrict__ loc, void* __restrict__ val,
+                                             const float* __restrict__ row_scale,
+                                             uint32_t* __restrict__ rec) {
+  int in_rec = 0;
+  uint32_t lw0 = 0u, lw1 = 0u, lw2 = 0u;     // row bytes of the open record
+  auto flush = [&](int cnt) {
+    if (r < nrec_cap) {
+      uint32_t* d = rec + r * 16;
+      *reinterpret_cast<uint4*>(d) = make_uint4((k << 8) | (uint32_t)cnt, lw0, lw1, lw2);
+      for (int t = cnt; t < kRecVals; ++t) d[4 + t] = 0u;
     }
-    // the exclusive record prefix at a block start is the first record of
-    // the panel with k >= that start (or the panel's end); at k = 0 it is
-    // also the end of the previous panel
-    if (k % ROSKO_KSTEP == 0) kblk_ptr[p * (nkb + 1) + k / ROSKO_KSTEP] = rec_off;
-    if (k == 0 && p > 0) kblk_ptr[(p - 1) * (nkb + 1) + nkb] = rec_off;
-    if (c == 0) continue;
-    if (col_slot < ncols_cap) {
-      col_ind[col_slot] = (int32_t)k;
-      col_nnz[col_slot] = c;
-      col_ptr[col_slot] = nz_off;
-    }
-    const int64_t r0 = p * mr;
-    const int rows = (int)((R - r0) < mr ? (R - r0) : mr);
-    const float* col = A + r0 * lda + k;
-    int64_t z = nz_off;
-    // column records: header, row bytes, FP32 values (unused slots zero)
-    int in_rec = 0;
-    int64_t r = rec_off;
-    uint32_t lw0 = 0u, lw1 = 0u, lw2 = 0u;     // row bytes of the open record
-    auto flush = [&](int cnt) {
-      if (r < nrec_cap) {
-        uint32_t* d = rec + r * 16;
-        *reinterpret_cast<uint4*>(d) = make_uint4(((uint32_t)k << 8) | (uint32_t)cnt, lw0, lw1,
-                                                  lw2);
-        for (int t = cnt; t < kRecVals; ++t) d[4 + t] = 0u;
-      }
-      lw0 = lw1 = lw2 = 0u;
-      ++r;
-    };
-    for (int i0 = 0; i0 < rows; i0 += 32) {
-      float xs[32];
-      load_rows32(col, lda, i0, rows, xs);
+    lw0 = lw1 = lw2 = 0u;
+    ++r;
+  };
+  for (int i0 = 0; i0 < rows; i0 += 32) {
+    if (i0 > 0) load_rows32(col, lda, i0, rows, xs);
 #pragma unroll
-      for (int jj = 0; jj < 32; ++jj) {
+    for (int jj = 0; jj < 32; ++jj) {
       const int i = i0 + jj;
       const float x = xs[jj];
       if (i >= rows || !kept(x)) continue;
@@ -297,9 +288,269 @@ k_pack_write(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
       if (r < nrec_cap) rec[r * 16 + 4 + in_rec] = vbits;
       ++z;
       if (++in_rec == kRecVals) { flush(kRecVals); in_rec = 0; }
+    }
+  }
+  if (in_rec) flush(in_rec);
+}
+
+// ------------------------------------------------------------------ write
+// LOCAL: the tile's prefix is the sum of the tile sums before it, added up
+// here (lanes stride over the tiles, then a fixed-order wave reduction:
+// integers, so any order is exact); the last tile closes the arrays.
+// Otherwise the prefix comes from the scan pass (tile_offs).
+template <int DT, bool LOCAL>
+__global__ void __launch_bounds__(kPackThreads)
+k_pack_write(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr,
+             int64_t P, const int32_t* __restrict__ counts, const int64_t* __restrict__ tile_offs,
+             const int64_t* __restrict__ tile_sums, int64_t* __restrict__ totals,
+             int64_t nnz_cap, int64_t ncols_cap, int64_t* __restrict__ panel_nz_ptr,
+             int64_t* __restrict__ panel_col_ptr, int32_t* __restrict__ col_ind,
+             int32_t* __restrict__ col_nnz, int64_t* __restrict__ col_ptr,
+             uint8_t* __restrict__ loc, void* __restrict__ val,
+             const float* __restrict__ row_scale, int64_t* __restrict__ kblk_ptr,
+             int64_t nrec_cap, uint32_t* __restrict__ rec) {
+  const int64_t total = P * S;
+  const int64_t nkb = (S + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
+  static_assert(kPackTile == kPackThreads, "one (panel, column) pair per thread");
+  const int64_t f = (int64_t)blockIdx.x * kPackTile + threadIdx.x;
+  const bool valid = f < total;
+  const int c = valid ? counts[f] : 0;
+  const int64_t p = valid ? f / S : 0, k = valid ? f - p * S : 0;
+  const int64_t r0 = p * mr;
+  const int rows = valid ? (int)((R - r0) < mr ? (R - r0) : mr) : 0;
+  const float* col = A + r0 * lda + k;
+  // the column's first 32 rows, issued before the prefix loads so that the
+  // two round trips overlap
+  float xs[32];
+  if (c > 0) load_rows32(col, lda, 0, rows, xs);
+  Tri carry{0, 0, 0};
+  if constexpr (LOCAL) {
+    static_assert(kPackThreads == 64, "the local prefix is a one-wavefront reduction");
+    // lanes stride over the tiles before this one, 8 tiles in flight each
+    const int64_t nb = blockIdx.x;
+    for (int64_t i = threadIdx.x; i < nb; i += 64 * 8) {
+      int64_t va[8], vb[8], vc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t t = (i + 64 * u < nb) ? i + 64 * u : 0;
+        va[u] = tile_sums[3 * t];
+        vb[u] = tile_sums[3 * t + 1];
+        vc[u] = tile_sums[3 * t + 2];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (i + 64 * u < nb) { carry.a += va[u]; carry.b += vb[u]; carry.c += vc[u]; }
       }
     }
-    if (in_rec) flush(in_rec);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      carry.a += __shfl_xor(carry.a, d, 64);
+      carry.b += __shfl_xor(carry.b, d, 64);
+      carry.c += __shfl_xor(carry.c, d, 64);
+    }
+  } else {
+    carry = Tri{tile_offs[3 * blockIdx.x], tile_offs[3 * blockIdx.x + 1],
+                tile_offs[3 * blockIdx.x + 2]};
+  }
+  // block scan of the tile in flattened order, plus the carry of the tiles before
+  Tri tot;
+  const Tri e = block_excl_scan(Tri{c, c != 0, n_records(c)}, &tot);
+  const int64_t nz_off = carry.a + e.a;
+  const int64_t col_slot = carry.b + e.b;
+  const int64_t rec_off = carry.c + e.c;
+  if (valid) {
+    if (k == 0) {
+      panel_nz_ptr[p] = nz_off;
+      panel_col_ptr[p] = col_slot;
+    }
+    // the exclusive record prefix at a block start is the first record of
+    // the panel with k >= that start (or the panel's end); at k = 0 it is
+    // also the end of the previous panel
+    if (k % ROSKO_KSTEP == 0) kblk_ptr[p * (nkb + 1) + k / ROSKO_KSTEP] = rec_off;
+    if (k == 0 && p > 0) kblk_ptr[(p - 1) * (nkb + 1) + nkb] = rec_off;
+  }
+  if (valid && c > 0) {
+    if (col_slot < ncols_cap) {
+      col_ind[col_slot] = (int32_t)k;
+      col_nnz[col_slot] = c;
+      col_ptr[col_slot] = nz_off;
+    }
+    write_column<DT>(col, lda, rows, xs, (uint32_t)k, r0, nz_off, rec_off, nnz_cap, nrec_cap,
+                     loc, val, row_scale, rec);
+  }
+  if constexpr (LOCAL) {
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+      carry.a += tot.a;
+      carry.b += tot.b;
+      carry.c += tot.c;
+      close_packing(carry, totals, P, S, nnz_cap, ncols_cap, nrec_cap, panel_nz_ptr,
+                    panel_col_ptr, col_ptr, kblk_ptr);
+    }
+  }
+}
+
+// ------------------------------------------------------- write (mr <= 64)
+// Same output as k_pack_write, organised for the SIMD: each lane still reads
+// its own column (coalesced across the tile's 64 columns), but instead of
+// storing its values one by one it drops every entry into LDS -- a kept one
+// into its value slot and its record slot inside the tile's contiguous
+// output ranges, others into a per-lane discard slot -- so there is no
+// branch per row.  The wavefront then copies the ranges out with coalesced
+// stores (records as 16-byte vectors); the per-column arrays go last, so
+// the workgroup barriers (which wait for outstanding stores) find none.
+constexpr int kLdsMaxRows = 64;
+constexpr int kLdsVals = kPackTile * kLdsMaxRows;                 // values per tile, at most
+constexpr int kLdsRecs = kPackTile * ((kLdsMaxRows + kRecVals - 1) / kRecVals);
+
+template <int DT>
+__device__ __forceinline__ uint32_t value_code(float x, const float* __restrict__ row_scale,
+                                               int64_t row) {
+  if (DT == ROSKO_F32) return __float_as_uint(x);
+  if (DT == ROSKO_BF16) return enc_bf16(x);
+  return enc_fp8(__fdiv_rn(x, row_scale[row]));
+}
+template <int DT>
+__device__ __forceinline__ uint32_t code_bits(uint32_t code) {
+  if (DT == ROSKO_F32) return code;
+  if (DT == ROSKO_BF16) return dec_bf16((uint16_t)code);
+  return dec_fp8((uint8_t)code);
+}
+
+template <int DT, bool LOCAL>
+__global__ void __launch_bounds__(kPackThreads)
+k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr,
+                 int64_t P, const int32_t* __restrict__ counts,
+                 const int64_t* __restrict__ tile_offs, const int64_t* __restrict__ tile_sums,
+                 int64_t* __restrict__ totals, int64_t nnz_cap, int64_t ncols_cap,
+                 int64_t* __restrict__ panel_nz_ptr, int64_t* __restrict__ panel_col_ptr,
+                 int32_t* __restrict__ col_ind, int32_t* __restrict__ col_nnz,
+                 int64_t* __restrict__ col_ptr, uint8_t* __restrict__ loc,
+                 void* __restrict__ val, const float* __restrict__ row_scale,
+                 int64_t* __restrict__ kblk_ptr, int64_t nrec_cap, uint32_t* __restrict__ rec) {
+  static_assert(kPackTile == 64 && kPackThreads == 64, "one wavefront per tile");
+  // the tile's values / rows and records as they go out, plus one discard
+  // slot per lane for the entries that are not kept
+  __shared__ uint32_t s_code[kLdsVals + 64];
+  __shared__ uint8_t s_loc[kLdsVals + 64];
+  __shared__ uint4 s_rec[kLdsRecs * 4 + 128];      // discard: 8 dwords per lane
+  uint32_t* s_rw = reinterpret_cast<uint32_t*>(s_rec);
+  uint8_t* s_rb = reinterpret_cast<uint8_t*>(s_rec);
+  const int lane = threadIdx.x;
+  const int64_t total = P * S;
+  const int64_t nkb = (S + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
+  const int64_t f = (int64_t)blockIdx.x * kPackTile + lane;
+  const bool valid = f < total;
+  const int c = valid ? counts[f] : 0;
+  const int64_t p = valid ? f / S : 0, k = valid ? f - p * S : 0;
+  const int64_t r0 = p * mr;
+  const int rows = valid ? (int)((R - r0) < mr ? (R - r0) : mr) : 0;
+  const float* col = A + r0 * lda + k;
+  float xs[32];
+  if (rows > 0) load_rows32(col, lda, 0, rows, xs);   // with the count, one round trip
+  Tri carry{0, 0, 0};
+  if constexpr (LOCAL) {
+    const int64_t nb = blockIdx.x;
+    for (int64_t i = lane; i < nb; i += 64 * 8) {
+      int64_t va[8], vb[8], vc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t t = (i + 64 * u < nb) ? i + 64 * u : 0;
+        va[u] = tile_sums[3 * t];
+        vb[u] = tile_sums[3 * t + 1];
+        vc[u] = tile_sums[3 * t + 2];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (i + 64 * u < nb) { carry.a += va[u]; carry.b += vb[u]; carry.c += vc[u]; }
+      }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      carry.a += __shfl_xor(carry.a, d, 64);
+      carry.b += __shfl_xor(carry.b, d, 64);
+      carry.c += __shfl_xor(carry.c, d, 64);
+    }
+  } else {
+    carry = Tri{tile_offs[3 * blockIdx.x], tile_offs[3 * blockIdx.x + 1],
+                tile_offs[3 * blockIdx.x + 2]};
+  }
+  Tri32 tot;
+  const Tri32 e = wave_excl_scan3(c, &tot);
+  const int nv = min(tot.a, kLdsVals), nrec = min(tot.c, kLdsRecs);
+  // zero the tile's records (unused value slots and row bytes stay zero)
+  for (int t = lane; t < nrec * 4; t += 64) s_rec[t] = make_uint4(0u, 0u, 0u, 0u);
+  __syncthreads();
+  // entries -> LDS, no branch per row: a kept entry of rank r in its column
+  // goes to value slot vbase + r and to slot r % 12 of record rbase + r / 12
+  const int vbase = e.a, rbase = e.c;
+  int rank = 0;
+  for (int i0 = 0; i0 < mr; i0 += 32) {
+    if (i0 > 0 && c > 0 && i0 < rows) load_rows32(col, lda, i0, rows, xs);
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj) {
+      const int i = i0 + jj;
+      const int q = rbase + (int)((unsigned)rank / kRecVals), sl = rank - (q - rbase) * kRecVals;
+      const bool kp = (c > 0) & (i < rows) & kept(xs[jj]) & (vbase + rank < kLdsVals) &
+                      (q < kLdsRecs);
+      const uint32_t code = value_code<DT>(xs[jj], row_scale, r0 + (i < rows ? i : 0));
+      const int vp = kp ? vbase + rank : kLdsVals + lane;
+      const int rp = kp ? q * 16 : kLdsRecs * 16 + lane * 8;   // + 4 + 0 stays in the lane's 8
+      s_code[vp] = code;
+      s_loc[vp] = (uint8_t)i;
+      s_rw[rp + 4 + (kp ? sl : 0)] = code_bits<DT>(code);
+      s_rb[(rp + 1) * 4 + (kp ? sl : 0)] = (uint8_t)i;
+      rank += kp ? 1 : 0;
+    }
+  }
+  for (int j = 0; j < (kLdsMaxRows + kRecVals - 1) / kRecVals; ++j) {
+    if (j * kRecVals < c && rbase + j < kLdsRecs)
+      s_rw[(rbase + j) * 16] = ((uint32_t)k << 8) | (uint32_t)min(kRecVals, c - j * kRecVals);
+  }
+  __syncthreads();
+  // coalesced copies of the tile's values, rows and records
+  const int64_t z0 = carry.a, q0 = carry.c;
+#pragma unroll 4
+  for (int t = lane; t < nv; t += 64) {
+    const int64_t z = z0 + t;
+    const uint32_t code = s_code[t];
+    const uint8_t row = s_loc[t];
+    if (z < nnz_cap) {
+      if (DT == ROSKO_F32) reinterpret_cast<uint32_t*>(val)[z] = code;
+      else if (DT == ROSKO_BF16) reinterpret_cast<uint16_t*>(val)[z] = (uint16_t)code;
+      else reinterpret_cast<uint8_t*>(val)[z] = (uint8_t)code;
+      loc[z] = row;
+    }
+  }
+#pragma unroll 4
+  for (int t = lane; t < nrec * 4; t += 64) {
+    const uint4 w = s_rec[t];
+    if (q0 + (t >> 2) < nrec_cap) reinterpret_cast<uint4*>(rec)[q0 * 4 + t] = w;
+  }
+  // per-column arrays and pointers last: nothing above waits on them
+  const int64_t nz_off = carry.a + e.a;
+  const int64_t col_slot = carry.b + e.b;
+  const int64_t rec_off = carry.c + e.c;
+  if (valid) {
+    if (k == 0) {
+      panel_nz_ptr[p] = nz_off;
+      panel_col_ptr[p] = col_slot;
+    }
+    if (k % ROSKO_KSTEP == 0) kblk_ptr[p * (nkb + 1) + k / ROSKO_KSTEP] = rec_off;
+    if (k == 0 && p > 0) kblk_ptr[(p - 1) * (nkb + 1) + nkb] = rec_off;
+    if (c > 0 && col_slot < ncols_cap) {
+      col_ind[col_slot] = (int32_t)k;
+      col_nnz[col_slot] = c;
+      col_ptr[col_slot] = nz_off;
+    }
+  }
+  if constexpr (LOCAL) {
+    if (blockIdx.x == gridDim.x - 1 && lane == 0) {
+      carry.a += tot.a;
+      carry.b += tot.b;
+      carry.c += tot.c;
+      close_packing(carry, totals, P, S, nnz_cap, ncols_cap, nrec_cap, panel_nz_ptr,
+                    panel_col_ptr, col_ptr, kblk_ptr);
+    }
   }
 }
 
@@ -390,22 +641,41 @@ int32_t launch_pack_count_scan(const float* A, int64_t R, int64_t S, int64_t lda
   return ROSKO_OK;
 }
 
-int32_t launch_pack_write(const float* A, int64_t R, int64_t S, int64_t lda, int32_t mr,
-                          int32_t val_dtype, void* ws, const PackWs& L, const rosko_packed* out,
-                          hipStream_t s) {
-  if (L.NT == 0) return ROSKO_OK;
+int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t mr,
+                    int32_t val_dtype, void* ws, const PackWs& L, const rosko_packed* out,
+                    hipStream_t s) {
   char* w = static_cast<char*>(ws);
-  const int32_t* counts = reinterpret_cast<const int32_t*>(w + L.counts);
-  const int64_t* toff = reinterpret_cast<const int64_t*>(w + L.tile_offs);
-#define ROSKO_WRITE(DT)                                                                      \
-  hipLaunchKernelGGL(k_pack_write<DT>, dim3((unsigned)L.NT), dim3(kPackThreads), 0, s, A, R, \
-                     S, lda, mr, L.P, counts, toff, out->nnz_cap, out->ncols_cap,            \
-                     out->panel_nz_ptr, out->panel_col_ptr, out->col_ind, out->col_nnz,      \
-                     out->col_ptr, out->loc, out->val, out->row_scale, out->kblk_ptr,       \
-                     out->nrec_cap, out->rec)
-  if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_F32);
-  else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_BF16);
-  else ROSKO_WRITE(ROSKO_FP8_E4M3);
+  int32_t* counts = reinterpret_cast<int32_t*>(w + L.counts);
+  int64_t* tsum = reinterpret_cast<int64_t*>(w + L.tile_sums);
+  int64_t* toff = reinterpret_cast<int64_t*>(w + L.tile_offs);
+  int64_t* totals = reinterpret_cast<int64_t*>(w + L.totals);
+  const bool local = L.NT > 0 && L.NT <= kLocalPrefixTiles;
+  int32_t st;
+  if (local) {
+    hipLaunchKernelGGL(k_pack_count, dim3((unsigned)L.NT), dim3(kPackThreads), 0, s, A, R, S,
+                       lda, mr, L.P, counts, tsum);
+    ROSKO_LAUNCH_CHECK("k_pack_count");
+  } else if ((st = launch_pack_count_scan(A, R, S, lda, mr, ws, L, out, s))) {
+    return st;
+  }
+  if (L.NT == 0) return ROSKO_OK;
+  const bool lds = mr <= kLdsMaxRows;
+#define ROSKO_WRITE(DT, LOC)                                                                   \
+  hipLaunchKernelGGL(lds ? (k_pack_write_lds<DT, LOC>) : (k_pack_write<DT, LOC>),            \
+                     dim3((unsigned)L.NT), dim3(kPackThreads), 0, s,                         \
+                     A, R, S, lda, mr, L.P, counts, toff, tsum, totals, out->nnz_cap,         \
+                     out->ncols_cap, out->panel_nz_ptr, out->panel_col_ptr, out->col_ind,     \
+                     out->col_nnz, out->col_ptr, out->loc, out->val, out->row_scale,          \
+                     out->kblk_ptr, out->nrec_cap, out->rec)
+  if (local) {
+    if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_F32, true);
+    else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_BF16, true);
+    else ROSKO_WRITE(ROSKO_FP8_E4M3, true);
+  } else {
+    if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_F32, false);
+    else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_BF16, false);
+    else ROSKO_WRITE(ROSKO_FP8_E4M3, false);
+  }
 #undef ROSKO_WRITE
   ROSKO_LAUNCH_CHECK("k_pack_write");
   return ROSKO_OK;

@@ -51,12 +51,12 @@ def test_workspace_size_closed_form():
     n = C.c_size_t(0)
     assert lib.rosko_pack_workspace_size(256, 2304, 32, 0, C.byref(n)) == 0
     P, K = 8, 2304
-    NT = (P * K + 255) // 256
+    NT = (P * K + 63) // 64
     r = lambda x: (x + 255) // 256 * 256
     assert n.value == r(4 * P * K) + 2 * r(24 * NT) + r(32)   # tile sums: 3 x int64 per tile
     assert lib.rosko_pack_workspace_size(256, 2304, 32, 1, C.byref(n)) == 0
     P2 = (2304 + 31) // 32
-    NT2 = (P2 * 256 + 255) // 256
+    NT2 = (P2 * 256 + 63) // 64
     assert n.value == r(4 * P2 * 256) + 2 * r(24 * NT2) + r(32) + r(4 * 256 * 2304)
 
 
