@@ -35,7 +35,6 @@ HBM_PEAK_GBS = 8000.0
 # are switched off for all device code of this build.
 VALU_FP32_PEAK_TFS = 78.6
 VALU_FP32_PUBLISHED_TFS = 157.3
-MR = 32
 SPMM_SOURCES = ("spmm_kernel.h", "spmm_loop.inc", "spmm.hip", "spmm_bf32.hip", "internal.h")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_spmm_rows_cnn_256x2304x3136_pmc.txt")
 
@@ -117,6 +116,9 @@ def main():
     ap.add_argument("--waves-per-tile", type=int, default=None)
     ap.add_argument("--k-split", type=int, default=None)
     ap.add_argument("--depth", type=int, default=None)
+    ap.add_argument("--mr", type=int, default=None,
+                    help="panel height for every matrix (default: the library's analytic "
+                         "plan rule picks it per matrix)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -126,7 +128,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2307_03930_amd import ops, synth
+    from paper_2307_03930_amd import ops, sched, synth
 
     torch.backends.cuda.matmul.allow_tf32 = False
     dev = torch.device("cuda:0")
@@ -137,14 +139,24 @@ def main():
     N = B_np.shape[1]
     B = torch.from_numpy(B_np).to(dev)
     As = [torch.from_numpy(a).to(dev) for a in As_np]
-    plan = ops.make_plan(args.cols_per_lane, args.waves_per_tile, args.k_split, args.depth)
-
-    # buffers sized once (the sizing query synchronises; the step does not)
-    packs, wss, Cs, sws = [], [], [], []
+    # per matrix, set up once outside the timed region: panel height and
+    # register tile from the analytic plan rule on the matrix's statistics
+    # (unless given), the parallel shape from the library; buffers sized once
+    # (the sizing query synchronises; the step does not)
+    packs, wss, Cs, sws, plans, mrs = [], [], [], [], [], []
     for A in As:
-        P = ops.pack(A, MR, "f32")
+        cols = args.cols_per_lane
+        if args.mr is None:
+            mr, cand = sched.candidate(sched.choose(A, N))
+            cols = cols or cand.cols_per_lane
+        else:
+            mr = args.mr
+        plan = ops.make_plan(cols, args.waves_per_tile, args.k_split, args.depth)
+        P = ops.pack(A, mr, "f32")
         packs.append(P)
-        wss.append(torch.empty(max(ops.workspace_size(M, K, MR), 1), dtype=torch.uint8,
+        plans.append(plan)
+        mrs.append(mr)
+        wss.append(torch.empty(max(ops.workspace_size(M, K, mr), 1), dtype=torch.uint8,
                                device=dev))
         Cs.append(torch.empty((M, N), dtype=torch.float32, device=dev))
         sws.append(torch.empty(max(ops.spmm_workspace_size(P, N, plan), 1), dtype=torch.uint8,
@@ -154,7 +166,7 @@ def main():
     k_touched = [int((a != 0).any(axis=0).sum()) for a in As_np]
 
     def step():
-        for A, P, ws, C, sw in zip(As, packs, wss, Cs, sws):
+        for A, P, ws, C, sw, plan in zip(As, packs, wss, Cs, sws, plans):
             ops.pack_into(A, P, ws)
             ops.spmm(P, B, C, plan=plan, ws=sw)
 
@@ -172,10 +184,11 @@ def main():
     value = flops_step / (ms_step * 1e-3) / 1e9
 
     # ---- per-sparsity SpMM kernel time (back-to-back launches, warm)
-    P_panels = (M + MR - 1) // MR
     per = []
     tot_bytes, tot_ms = 0.0, 0.0
-    for s, P, C, sw, nnz, nc, kt in zip(sparsities, packs, Cs, sws, nnzs, ncolss, k_touched):
+    for s, P, C, sw, nnz, nc, kt, plan, mr in zip(sparsities, packs, Cs, sws, nnzs, ncolss,
+                                                  k_touched, plans, mrs):
+        P_panels = (M + mr - 1) // mr
         for _ in range(3):
             ops.spmm(P, B, C, plan=plan, ws=sw)
         torch.cuda.synchronize()
@@ -189,7 +202,7 @@ def main():
         by = alg_bytes(nnz, nc, P_panels, kt, N, M)
         tot_bytes += by
         tot_ms += ms
-        per.append({"sparsity": s, "nnz": nnz, "spmm_us": round(ms * 1e3, 2),
+        per.append({"sparsity": s, "nnz": nnz, "mr": mr, "spmm_us": round(ms * 1e3, 2),
                     "gflops": round(2.0 * nnz * N / (ms * 1e-3) / 1e9, 1),
                     "alu_frac": round(2.0 * nnz * N / (ms * 1e-3) / 1e12 / VALU_FP32_PEAK_TFS, 3),
                     "alg_MB": round(by / 1e6, 2),
@@ -222,7 +235,7 @@ def main():
         del src, dst
         # cold-cache SpMM: overwrite 512 MB between trials
         flush = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
-        for rec, P, C, sw in zip(per, packs, Cs, sws):
+        for rec, P, C, sw, plan in zip(per, packs, Cs, sws, plans):
             ts = []
             for _ in range(10):
                 flush.fill_(1.0)
@@ -254,7 +267,9 @@ def main():
         "config": {"workload": "pruned-CNN conv-as-GEMM FP32: A 256x2304 magnitude-pruned at "
                                "70/80/90/95/99/99.8%, B 2304x3136 im2col(ReLU(N(0,1))); "
                                "step = pack + SpMM for all six",
-                   "M": M, "K": K, "N": N, "mr": MR, "parallelism": "single-gpu"},
+                   "M": M, "K": K, "N": N,
+                   "mr": args.mr if args.mr is not None else "per matrix, analytic rule",
+                   "parallelism": "single-gpu"},
         # the SpMM call (k_spmm_rows, then k_reduce_splits when K is split),
         # one launch per sparsity, timed back to back with events on the
         # stream it runs on; FLOPs on stored nonzeros only

@@ -115,24 +115,30 @@ def gen_variant(mr, v, dt, D):
 
     def body(u):
         s = u % D
-        _, bregs, conv = pl.b_slot(s)
+        dst, bregs, conv = pl.b_slot(s)
         vr = f"v{u}"
         # count of record i, then the header of record i+D into the same SGPR
-        # (its B row is issued after the values, when slot s is free)
         a(f"s_and_b32 %[c], %[h{s}], 0xff")
         a(f"v_readfirstlane_b32 %[h{s}], v{(u + D) % R}")
         for c in conv:
             a(c)
         for wd in range(3):
             a(f"v_readlane_b32 %[w{wd}], {vr}, {wd + 1}")
-        # count clamped to 12; jump to the block of value count-1 (count 0
-        # lands on .Le); the blocks run down to value 0
+        # two independent scalar chains, interleaved: the jump of record i
+        # (count clamped to 12, block of value count-1; count 0 lands on .Le)
+        # and the B-row offset of record i+D (row clamped to K-1), whose load
+        # goes out after the values, when B slot s is free again
         a("s_min_u32 %[c], %[c], 12")
+        a(f"s_lshr_b32 %[k], %[h{s}], 8")
         a(f"s_mul_i32 %[c], %[c], {pl.blk}")
+        a("s_min_u32 %[k], %[k], %[km1]")
         a(f"s_sub_u32 %[c], .Le{u}_%= - .Lp{u}_%=, %[c]")
+        a("s_mul_i32 %[k], %[k], %[ldbb]")
+        a("s_min_u32 %[t], %[o], %[olast]")
         a("s_set_gpr_idx_on %[c], gpr_idx(SRC2,DST)")
         a(f"s_getpc_b64 s[{PC}:{PC + 1}]")
         L.append(f".Lp{u}_%=:")
+        # nothing between the add and its carry: SCC carries the high word
         a(f"s_add_u32 s{PC}, s{PC}, %[c]")
         a(f"s_addc_u32 s{PC + 1}, s{PC + 1}, 0")
         a(f"s_setpc_b64 s[{PC}:{PC + 1}]")
@@ -145,6 +151,9 @@ def gen_variant(mr, v, dt, D):
                   "row_mask:0xf bank_mask:0xf")
         L.append(f".Le{u}_%=:")
         a("s_set_gpr_idx_off")
+        a(f"{pl.b_load_op()} {dst}, %[vbo], %[rb], %[k] offen")
+        a(f"buffer_load_dword v{u}, %[vro], %[rr], %[t] offen")
+        a("s_add_u32 %[o], %[o], 64")
 
     # ---- prologue: records 0..D-1, then for each: header, B row, record j+D.
     # Record offsets are clamped to the run's last record.
@@ -167,10 +176,6 @@ def gen_variant(mr, v, dt, D):
         a("s_cbranch_scc1 .Ldone%=")
         a(f"s_waitcnt vmcnt({2 * D - 2})")
         body(u)
-        bload(f"h{s}", s)
-        a("s_min_u32 %[t], %[o], %[olast]")
-        a(f"buffer_load_dword v{u}, %[vro], %[rr], %[t] offen")
-        a("s_add_u32 %[o], %[o], 64")
     a("s_branch .Lloop%=")
     a(".Ldone%=:")
     a("s_waitcnt vmcnt(0)")

@@ -43,11 +43,15 @@ struct PackWs {
   size_t totals;       // int64 [4]          nnz, ncols, overflow flag, nrec
   size_t transposed;   // float [R*S]        dense transpose (transpose packing only)
   size_t bytes;        // total
-  int64_t P, NT;
+  int64_t P, NT;       // panels; tiles of 64 * cpl (panel, column) pairs
+  int32_t cpl;         // pairs per lane (pack_cols_per_lane)
 };
-constexpr int kPackTile = 64;        // (panel, column) pairs per tile: one wavefront, one per lane
+constexpr int kPackTile = 64;        // lanes per tile: one wavefront
 constexpr int kRecVals = 12;         // values per 16-dword column record
 constexpr int kPackThreads = 64;
+// (panel, column) pairs per lane: 4 for mr <= 8, 2 for mr <= 16, else 1, so
+// a lane sees about 32 entries and a tile 64 * cols pairs whatever mr is.
+inline int pack_cols_per_lane(int32_t mr) { return mr <= 8 ? 4 : (mr <= 16 ? 2 : 1); }
 // Up to this many tiles the write pass adds up the tile sums before its own
 // tile itself (no separate scan launch); beyond, a one-workgroup scan runs.
 constexpr int64_t kLocalPrefixTiles = 4096;

@@ -145,35 +145,55 @@ __device__ __forceinline__ uint32_t dec_fp8(uint8_t c) {
 }
 
 // ------------------------------------------------------------------ count
-// Tile t covers flattened indices [t*64, t*64+64); lane x handles
-// f = t*64 + x (adjacent lanes -> adjacent columns, so the row loads are
-// coalesced), with all rows of its column loaded in batches of 32.
+// Tile t covers flattened indices [t*T, t*T+T), T = 64 * CPL; lane x handles
+// f = t*T + 64*j + x for j < CPL (at every j adjacent lanes -> adjacent
+// columns, so the row loads are coalesced).  CPL = 1: all rows of the column
+// in batches of 32; CPL > 1 (mr <= 32 / CPL): the column's rows in one batch
+// of 32 / CPL loads.
+template <int CPL>
 __global__ void __launch_bounds__(kPackThreads)
 k_pack_count(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr,
              int64_t P, int32_t* __restrict__ counts, int64_t* __restrict__ tile_sums) {
   static_assert(kPackTile == 64 && kPackThreads == 64, "one wavefront per tile");
+  constexpr int RMAX = 32 / CPL;
   const int64_t total = P * S;
-  const int64_t f = (int64_t)blockIdx.x * kPackTile + threadIdx.x;
-  int c = 0;
-  if (f < total) {
-    const int64_t p = f / S, k = f - p * S;
-    const int64_t r0 = p * mr;
-    const int rows = (int)((R - r0) < mr ? (R - r0) : mr);
-    const float* col = A + r0 * lda + k;
-    for (int i0 = 0; i0 < rows; i0 += 32) {
-      float x[32];
-      load_rows32(col, lda, i0, rows, x);
+  const int64_t fb = (int64_t)blockIdx.x * (64 * CPL) + threadIdx.x;
+  Tri32 sum{0, 0, 0};
 #pragma unroll
-      for (int j = 0; j < 32; ++j) c += (i0 + j < rows) & kept(x[j]);
+  for (int j = 0; j < CPL; ++j) {
+    const int64_t f = fb + 64 * j;
+    int c = 0;
+    if (f < total) {
+      const int64_t p = f / S, k = f - p * S;
+      const int64_t r0 = p * mr;
+      const int rows = (int)((R - r0) < mr ? (R - r0) : mr);
+      const float* col = A + r0 * lda + k;
+      if constexpr (CPL == 1) {
+        for (int i0 = 0; i0 < rows; i0 += 32) {
+          float x[32];
+          load_rows32(col, lda, i0, rows, x);
+#pragma unroll
+          for (int i = 0; i < 32; ++i) c += (i0 + i < rows) & kept(x[i]);
+        }
+      } else {
+        float x[RMAX];
+#pragma unroll
+        for (int i = 0; i < RMAX; ++i) x[i] = col[(int64_t)(i < rows ? i : rows - 1) * lda];
+#pragma unroll
+        for (int i = 0; i < RMAX; ++i) c += (i < rows) & kept(x[i]);
+      }
+      counts[f] = c;
     }
-    counts[f] = c;
+    Tri32 t;
+    (void)wave_excl_scan3(c, &t);
+    sum.a += t.a;
+    sum.b += t.b;
+    sum.c += t.c;
   }
-  Tri32 tot;
-  (void)wave_excl_scan3(c, &tot);
   if (threadIdx.x == 0) {
-    tile_sums[3 * blockIdx.x] = tot.a;
-    tile_sums[3 * blockIdx.x + 1] = tot.b;
-    tile_sums[3 * blockIdx.x + 2] = tot.c;
+    tile_sums[3 * blockIdx.x] = sum.a;
+    tile_sums[3 * blockIdx.x + 1] = sum.b;
+    tile_sums[3 * blockIdx.x + 2] = sum.c;
   }
 }
 
@@ -416,7 +436,7 @@ __device__ __forceinline__ uint32_t code_bits(uint32_t code) {
   return dec_fp8((uint8_t)code);
 }
 
-template <int DT, bool LOCAL>
+template <int DT, bool LOCAL, int CPL>
 __global__ void __launch_bounds__(kPackThreads)
 k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr,
                  int64_t P, const int32_t* __restrict__ counts,
@@ -428,6 +448,12 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
                  void* __restrict__ val, const float* __restrict__ row_scale,
                  int64_t* __restrict__ kblk_ptr, int64_t nrec_cap, uint32_t* __restrict__ rec) {
   static_assert(kPackTile == 64 && kPackThreads == 64, "one wavefront per tile");
+  // rows held per column: 32 in batches (CPL 1, mr up to 64), else 32 / CPL
+  // (mr <= 32 / CPL); records per column at most 6 (CPL 1) or ceil(RMAX/12)
+  constexpr int RMAX = 32 / CPL;
+  constexpr int RPC = CPL == 1 ? (kLdsMaxRows + kRecVals - 1) / kRecVals
+                               : (RMAX + kRecVals - 1) / kRecVals;
+  static_assert(CPL * RPC * kPackTile <= kLdsRecs && CPL * RMAX * kPackTile <= kLdsVals, "");
   // the tile's values / rows and records as they go out, plus one discard
   // slot per lane for the entries that are not kept
   __shared__ uint32_t s_code[kLdsVals + 64];
@@ -438,15 +464,33 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   const int lane = threadIdx.x;
   const int64_t total = P * S;
   const int64_t nkb = (S + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
-  const int64_t f = (int64_t)blockIdx.x * kPackTile + lane;
-  const bool valid = f < total;
-  const int c = valid ? counts[f] : 0;
-  const int64_t p = valid ? f / S : 0, k = valid ? f - p * S : 0;
-  const int64_t r0 = p * mr;
-  const int rows = valid ? (int)((R - r0) < mr ? (R - r0) : mr) : 0;
-  const float* col = A + r0 * lda + k;
+  const int64_t fb = (int64_t)blockIdx.x * (64 * CPL) + lane;
+  bool valid[CPL];
+  int c[CPL], rows[CPL];
+  int64_t p[CPL], k[CPL], r0[CPL];
   float xs[32];
-  if (rows > 0) load_rows32(col, lda, 0, rows, xs);   // with the count, one round trip
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const int64_t f = fb + 64 * j;
+    valid[j] = f < total;
+    c[j] = valid[j] ? counts[f] : 0;
+    p[j] = valid[j] ? f / S : 0;
+    k[j] = valid[j] ? f - p[j] * S : 0;
+    r0[j] = p[j] * mr;
+    rows[j] = valid[j] ? (int)((R - r0[j]) < mr ? (R - r0[j]) : mr) : 0;
+  }
+  // rows, with the counts: one round trip (clamped reads of valid memory)
+  if constexpr (CPL == 1) {
+    if (rows[0] > 0) load_rows32(A + r0[0] * lda + k[0], lda, 0, rows[0], xs);
+  } else {
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const float* col = A + r0[j] * lda + k[j];
+      const int last = rows[j] > 0 ? rows[j] - 1 : 0;
+#pragma unroll
+      for (int i = 0; i < RMAX; ++i) xs[j * RMAX + i] = col[(int64_t)(i < last ? i : last) * lda];
+    }
+  }
   Tri carry{0, 0, 0};
   if constexpr (LOCAL) {
     const int64_t nb = blockIdx.x;
@@ -474,37 +518,54 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
     carry = Tri{tile_offs[3 * blockIdx.x], tile_offs[3 * blockIdx.x + 1],
                 tile_offs[3 * blockIdx.x + 2]};
   }
-  Tri32 tot;
-  const Tri32 e = wave_excl_scan3(c, &tot);
-  const int nv = min(tot.a, kLdsVals), nrec = min(tot.c, kLdsRecs);
+  // exclusive prefix in flattened order: the columns of j = 0 (lanes in
+  // order), then j = 1, ...
+  Tri32 e[CPL], run{0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    Tri32 t;
+    const Tri32 x = wave_excl_scan3(c[j], &t);
+    e[j] = Tri32{run.a + x.a, run.b + x.b, run.c + x.c};
+    run.a += t.a;
+    run.b += t.b;
+    run.c += t.c;
+  }
+  const int nv = min(run.a, kLdsVals), nrec = min(run.c, kLdsRecs);
   // zero the tile's records (unused value slots and row bytes stay zero)
   for (int t = lane; t < nrec * 4; t += 64) s_rec[t] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
   // entries -> LDS, no branch per row: a kept entry of rank r in its column
   // goes to value slot vbase + r and to slot r % 12 of record rbase + r / 12
-  const int vbase = e.a, rbase = e.c;
-  int rank = 0;
-  for (int i0 = 0; i0 < mr; i0 += 32) {
-    if (i0 > 0 && c > 0 && i0 < rows) load_rows32(col, lda, i0, rows, xs);
 #pragma unroll
-    for (int jj = 0; jj < 32; ++jj) {
-      const int i = i0 + jj;
-      const int q = rbase + (int)((unsigned)rank / kRecVals), sl = rank - (q - rbase) * kRecVals;
-      const bool kp = (c > 0) & (i < rows) & kept(xs[jj]) & (vbase + rank < kLdsVals) &
-                      (q < kLdsRecs);
-      const uint32_t code = value_code<DT>(xs[jj], row_scale, r0 + (i < rows ? i : 0));
-      const int vp = kp ? vbase + rank : kLdsVals + lane;
-      const int rp = kp ? q * 16 : kLdsRecs * 16 + lane * 8;   // + 4 + 0 stays in the lane's 8
-      s_code[vp] = code;
-      s_loc[vp] = (uint8_t)i;
-      s_rw[rp + 4 + (kp ? sl : 0)] = code_bits<DT>(code);
-      s_rb[(rp + 1) * 4 + (kp ? sl : 0)] = (uint8_t)i;
-      rank += kp ? 1 : 0;
+  for (int j = 0; j < CPL; ++j) {
+    const int vbase = e[j].a, rbase = e[j].c;
+    int rank = 0;
+    for (int i0 = 0; i0 < (CPL == 1 ? mr : RMAX); i0 += 32) {
+      if (CPL == 1 && i0 > 0 && c[0] > 0 && i0 < rows[0])
+        load_rows32(A + r0[0] * lda + k[0], lda, i0, rows[0], xs);
+#pragma unroll
+      for (int jj = 0; jj < (CPL == 1 ? 32 : RMAX); ++jj) {
+        const int i = i0 + jj;
+        const float x = xs[(CPL == 1 ? 0 : j * RMAX) + jj];
+        const int q = rbase + (int)((unsigned)rank / kRecVals), sl = rank - (q - rbase) * kRecVals;
+        const bool kp = (c[j] > 0) & (i < rows[j]) & kept(x) & (vbase + rank < kLdsVals) &
+                        (q < kLdsRecs);
+        const uint32_t code = value_code<DT>(x, row_scale, r0[j] + (i < rows[j] ? i : 0));
+        const int vp = kp ? vbase + rank : kLdsVals + lane;
+        const int rp = kp ? q * 16 : kLdsRecs * 16 + lane * 8;   // + 4 + 0 stays in the lane's 8
+        s_code[vp] = code;
+        s_loc[vp] = (uint8_t)i;
+        s_rw[rp + 4 + (kp ? sl : 0)] = code_bits<DT>(code);
+        s_rb[(rp + 1) * 4 + (kp ? sl : 0)] = (uint8_t)i;
+        rank += kp ? 1 : 0;
+      }
     }
-  }
-  for (int j = 0; j < (kLdsMaxRows + kRecVals - 1) / kRecVals; ++j) {
-    if (j * kRecVals < c && rbase + j < kLdsRecs)
-      s_rw[(rbase + j) * 16] = ((uint32_t)k << 8) | (uint32_t)min(kRecVals, c - j * kRecVals);
+#pragma unroll
+    for (int jr = 0; jr < RPC; ++jr) {
+      if (jr * kRecVals < c[j] && rbase + jr < kLdsRecs)
+        s_rw[(rbase + jr) * 16] =
+            ((uint32_t)k[j] << 8) | (uint32_t)min(kRecVals, c[j] - jr * kRecVals);
+    }
   }
   __syncthreads();
   // coalesced copies of the tile's values, rows and records
@@ -527,27 +588,29 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
     if (q0 + (t >> 2) < nrec_cap) reinterpret_cast<uint4*>(rec)[q0 * 4 + t] = w;
   }
   // per-column arrays and pointers last: nothing above waits on them
-  const int64_t nz_off = carry.a + e.a;
-  const int64_t col_slot = carry.b + e.b;
-  const int64_t rec_off = carry.c + e.c;
-  if (valid) {
-    if (k == 0) {
-      panel_nz_ptr[p] = nz_off;
-      panel_col_ptr[p] = col_slot;
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    if (!valid[j]) continue;
+    const int64_t nz_off = carry.a + e[j].a;
+    const int64_t col_slot = carry.b + e[j].b;
+    const int64_t rec_off = carry.c + e[j].c;
+    if (k[j] == 0) {
+      panel_nz_ptr[p[j]] = nz_off;
+      panel_col_ptr[p[j]] = col_slot;
     }
-    if (k % ROSKO_KSTEP == 0) kblk_ptr[p * (nkb + 1) + k / ROSKO_KSTEP] = rec_off;
-    if (k == 0 && p > 0) kblk_ptr[(p - 1) * (nkb + 1) + nkb] = rec_off;
-    if (c > 0 && col_slot < ncols_cap) {
-      col_ind[col_slot] = (int32_t)k;
-      col_nnz[col_slot] = c;
+    if (k[j] % ROSKO_KSTEP == 0) kblk_ptr[p[j] * (nkb + 1) + k[j] / ROSKO_KSTEP] = rec_off;
+    if (k[j] == 0 && p[j] > 0) kblk_ptr[(p[j] - 1) * (nkb + 1) + nkb] = rec_off;
+    if (c[j] > 0 && col_slot < ncols_cap) {
+      col_ind[col_slot] = (int32_t)k[j];
+      col_nnz[col_slot] = c[j];
       col_ptr[col_slot] = nz_off;
     }
   }
   if constexpr (LOCAL) {
     if (blockIdx.x == gridDim.x - 1 && lane == 0) {
-      carry.a += tot.a;
-      carry.b += tot.b;
-      carry.c += tot.c;
+      carry.a += run.a;
+      carry.b += run.b;
+      carry.c += run.c;
       close_packing(carry, totals, P, S, nnz_cap, ncols_cap, nrec_cap, panel_nz_ptr,
                     panel_col_ptr, col_ptr, kblk_ptr);
     }
@@ -600,10 +663,22 @@ k_transpose(const float* __restrict__ A, int64_t M, int64_t K, int64_t lda,
 
 }  // namespace
 
+static void launch_count(const float* A, int64_t R, int64_t S, int64_t lda, int32_t mr,
+                         const PackWs& L, int32_t* counts, int64_t* tsum, hipStream_t s) {
+  const dim3 grid((unsigned)L.NT), block(kPackThreads);
+  if (L.cpl == 4)
+    hipLaunchKernelGGL(k_pack_count<4>, grid, block, 0, s, A, R, S, lda, mr, L.P, counts, tsum);
+  else if (L.cpl == 2)
+    hipLaunchKernelGGL(k_pack_count<2>, grid, block, 0, s, A, R, S, lda, mr, L.P, counts, tsum);
+  else
+    hipLaunchKernelGGL(k_pack_count<1>, grid, block, 0, s, A, R, S, lda, mr, L.P, counts, tsum);
+}
+
 PackWs pack_ws_layout(int64_t R, int64_t S, int32_t mr, bool transpose) {
   PackWs L{};
   L.P = ceil_div(R, mr);
-  L.NT = ceil_div(L.P * S, kPackTile);
+  L.cpl = pack_cols_per_lane(mr);
+  L.NT = ceil_div(L.P * S, (int64_t)kPackTile * L.cpl);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = (size_t)round_up(off + bytes, 256); return o; };
   L.counts = take(sizeof(int32_t) * (size_t)(L.P * S));
@@ -628,8 +703,7 @@ int32_t launch_pack_count_scan(const float* A, int64_t R, int64_t S, int64_t lda
     return ROSKO_EUNSUPPORTED;
   }
   if (L.NT > 0) {
-    hipLaunchKernelGGL(k_pack_count, dim3((unsigned)L.NT), dim3(kPackThreads), 0, s, A, R, S,
-                       lda, mr, L.P, counts, tsum);
+    launch_count(A, R, S, lda, mr, L, counts, tsum, s);
     ROSKO_LAUNCH_CHECK("k_pack_count");
   }
   hipLaunchKernelGGL(k_pack_scan, dim3(1), dim3(1024), 0, s, tsum, toff, L.NT, totals, L.P, S,
@@ -652,16 +726,20 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
   const bool local = L.NT > 0 && L.NT <= kLocalPrefixTiles;
   int32_t st;
   if (local) {
-    hipLaunchKernelGGL(k_pack_count, dim3((unsigned)L.NT), dim3(kPackThreads), 0, s, A, R, S,
-                       lda, mr, L.P, counts, tsum);
+    launch_count(A, R, S, lda, mr, L, counts, tsum, s);
     ROSKO_LAUNCH_CHECK("k_pack_count");
   } else if ((st = launch_pack_count_scan(A, R, S, lda, mr, ws, L, out, s))) {
     return st;
   }
   if (L.NT == 0) return ROSKO_OK;
   const bool lds = mr <= kLdsMaxRows;
+  // mr > kLdsMaxRows only with one pair per lane (pack_cols_per_lane)
+#define ROSKO_KWRITE(DT, LOC)                                                                  \
+  (!lds ? (k_pack_write<DT, LOC>)                                                             \
+        : L.cpl == 4 ? (k_pack_write_lds<DT, LOC, 4>)                                         \
+                     : L.cpl == 2 ? (k_pack_write_lds<DT, LOC, 2>) : (k_pack_write_lds<DT, LOC, 1>))
 #define ROSKO_WRITE(DT, LOC)                                                                   \
-  hipLaunchKernelGGL(lds ? (k_pack_write_lds<DT, LOC>) : (k_pack_write<DT, LOC>),            \
+  hipLaunchKernelGGL(ROSKO_KWRITE(DT, LOC),                                                    \
                      dim3((unsigned)L.NT), dim3(kPackThreads), 0, s,                         \
                      A, R, S, lda, mr, L.P, counts, toff, tsum, totals, out->nnz_cap,         \
                      out->ncols_cap, out->panel_nz_ptr, out->panel_col_ptr, out->col_ind,     \
@@ -677,6 +755,7 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
     else ROSKO_WRITE(ROSKO_FP8_E4M3, false);
   }
 #undef ROSKO_WRITE
+#undef ROSKO_KWRITE
   ROSKO_LAUNCH_CHECK("k_pack_write");
   return ROSKO_OK;
 }

@@ -120,32 +120,47 @@ int32_t launch_fill_zero(float* C, int64_t M, int64_t N, int64_t ldc, hipStream_
   return ROSKO_OK;
 }
 
-// Parallel shape of the sparse path for V columns per lane: the grid should
-// hold about two wavefronts per SIMD (2048 on 256 CUs).  When the (panel,
-// chunk) tiles are fewer, each tile gets up to 4 wavefronts in its workgroup,
-// then up to 8 workgroups (k_split), as long as a wavefront keeps at least
-// kMinRun records (records per panel estimated from nrec, or from nnz at
-// about 8 values per record when nrec is unknown).
+// Parallel shape of the sparse path.  A wavefront's time is set by the
+// length of its run of records (each costs a few hundred cycles of scalar
+// work around its values), so the panel's records are cut into H runs per
+// workgroup (added through LDS) and, while runs stay long, into k_split
+// workgroups (added by k_reduce_splits, which costs a launch and a pass over
+// k_split copies of C):
+//   H = 4 from 64 records per panel, 2 from 32, else 1;
+//   k_split > 1 only when a run of the H-way cut exceeds kSplitRun records:
+//   then as many as keep runs of at least kMinRun records and the grid within
+//   what the SIMDs can hold at once (wavefronts per SIMD by the tile's VGPR
+//   budget), at most 8.
+// Records per panel come from nrec (or from nnz at about 8 values per record
+// when nrec is unknown).
 static void auto_parallelism(const rosko_packed* A, int64_t N, int V, int32_t* H_out,
                              int32_t* S_out) {
   const int64_t P = std::max<int64_t>(1, A->n_panels);
   const int64_t chunks = std::max<int64_t>(1, ceil_div(N, 64 * V));
   const int64_t tiles = P * chunks;
-  constexpr int64_t kTargetWaves = 2048, kMinRun = 48;
+  constexpr int64_t kMinRun = 64, kSplitRun = 100;
   int64_t per_panel = 1 << 30;
   if (A->nrec >= 0) per_panel = A->nrec / P;
   else if (A->nnz >= 0) per_panel = A->nnz / (8 * P);
-  const int64_t max_parts = std::max<int64_t>(1, per_panel / kMinRun);
-  int64_t want = std::max<int64_t>(1, kTargetWaves / tiles);
-  want = std::min(want, max_parts);
-  const int H = want >= 4 ? 4 : (want >= 2 ? 2 : 1);
+  const int H = per_panel >= 64 ? 4 : (per_panel >= 32 ? 2 : 1);
+  const int64_t run = per_panel / H;
+  // wavefronts per SIMD to aim for: 64-accumulator tiles fit 5 (about 100
+  // VGPRs), smaller ones 8; 128-accumulator tiles fit 3 (about 160 VGPRs),
+  // but 2 measured faster (fewer copies of C to add)
+  const int accs = tile_height(A->mr) * V;
+  const int64_t per_simd = accs >= 128 ? 2 : (accs >= 64 ? 5 : 8);
+  const int64_t cap = 1024 * per_simd;                     // 256 CUs x 4 SIMDs
+  int64_t S = 1;
+  if (run > kSplitRun) {
+    S = std::min<int64_t>(run / kMinRun, cap / (tiles * H));
+    S = std::max<int64_t>(1, std::min<int64_t>(S, 8));
+  }
   *H_out = H;
-  *S_out = (int32_t)std::min<int64_t>(8, std::max<int64_t>(1, want / H));
+  *S_out = (int32_t)S;
 }
 
-// B rows in flight: 8 where the register tile leaves room for them (tiles of
-// at most 64 accumulators per lane), else 4.
-static int32_t auto_depth(int MRt, int V) { return MRt * V <= 64 ? 8 : 4; }
+// B rows in flight per wavefront: 4 (8 measured no faster on any tile).
+static int32_t auto_depth(int, int) { return 4; }
 
 // The analytic fallback plan: the register tile is the widest the panel
 // height allows (128 accumulators per lane), narrowed when N is small; the

@@ -166,15 +166,15 @@ def pack_transpose(A: torch.Tensor, mr: int = 32) -> PackedMatrix:
 def make_plan(cols_per_lane: int | None = None, waves_per_tile: int | None = None,
               k_split: int | None = None, depth: int | None = None,
               path: int = L.ROSKO_PATH_SPARSE):
-    """A rosko_plan; None (automatic) when nothing is given.  depth None: the
-    library's choice."""
+    """A rosko_plan; None (automatic) when nothing is given.  A field left
+    None is the library's choice (0), columns per lane defaulting to 4."""
     if cols_per_lane is None and waves_per_tile is None and k_split is None and depth is None:
         return None
     p = L.RoskoPlan()
     p.path = path
     p.cols_per_lane = cols_per_lane or 4
-    p.waves_per_tile = waves_per_tile or 1
-    p.k_split = k_split or 1
+    p.waves_per_tile = waves_per_tile or 0
+    p.k_split = k_split or 0
     p.depth = depth or 0
     return p
 

@@ -51,12 +51,16 @@ def test_workspace_size_closed_form():
     n = C.c_size_t(0)
     assert lib.rosko_pack_workspace_size(256, 2304, 32, 0, C.byref(n)) == 0
     P, K = 8, 2304
-    NT = (P * K + 63) // 64
+    NT = (P * K + 63) // 64                 # mr 32: one pair per lane
     r = lambda x: (x + 255) // 256 * 256
     assert n.value == r(4 * P * K) + 2 * r(24 * NT) + r(32)   # tile sums: 3 x int64 per tile
-    assert lib.rosko_pack_workspace_size(256, 2304, 32, 1, C.byref(n)) == 0
     P2 = (2304 + 31) // 32
     NT2 = (P2 * 256 + 63) // 64
+    assert lib.rosko_pack_workspace_size(256, 2304, 8, 0, C.byref(n)) == 0
+    P8 = 32                                   # mr 8: four pairs per lane
+    NT8 = (P8 * 2304 + 255) // 256
+    assert n.value == r(4 * P8 * 2304) + 2 * r(24 * NT8) + r(32)
+    assert lib.rosko_pack_workspace_size(256, 2304, 32, 1, C.byref(n)) == 0
     assert n.value == r(4 * P2 * 256) + 2 * r(24 * NT2) + r(32) + r(4 * 256 * 2304)
 
 
@@ -205,6 +209,24 @@ def test_plan_validation_and_workspace_size():
         assert lib.rosko_spmm_workspace_size(C.byref(s2), 777, None, C.byref(n)) == 0
 
 
+@pytest.mark.parametrize("mr, nrec, k_split", [
+    (16, 16 * 2296, 6),      # long runs (about 2300 records per panel): split, capped by the grid
+    (32, 8 * 2550, 4),       # 128-accumulator tiles: 2 wavefronts per SIMD, fewer splits
+    (8, 32 * 777, 3),        # 777 records per panel: runs of 64+ records
+    (8, 32 * 178, 1),        # short runs: no split, no reduce pass
+    (8, 32 * 37, 1),
+])
+def test_auto_parallel_shape(mr, nrec, k_split):
+    """The automatic plan's k_split, read back through the workspace size
+    (k_split copies of C, none for 1) on the 256 x 2304 times 3136 layer."""
+    lib = L.lib()
+    s = _packed(256, 2304, mr)
+    s.nrec = nrec
+    n = C.c_size_t(0)
+    assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, None, C.byref(n)) == 0
+    assert n.value == (4 * k_split * 256 * 3136 if k_split > 1 else 0)
+
+
 def test_sched_candidates_and_analytic_rule():
     lib = L.lib()
     mr = C.c_int32(0)
@@ -219,12 +241,14 @@ def test_sched_candidates_and_analytic_rule():
     assert lib.rosko_sched_candidate(7, C.byref(mr), C.byref(plan)) == L.ROSKO_EINVAL
     idx = C.c_int32(-1)
     f = (C.c_float * 16)()
-    f[3], f[2] = 0.1, 10.0                      # 10% dense, N = 1024
-    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 2
-    f[2] = 6.0                                  # N = 64
+    f[3], f[2] = 0.1, 10.0                      # 10% dense, N = 1024: mr 16
+    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 1
+    f[3] = 0.05                                 # 5% dense: mr 8
+    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 0
+    f[3], f[2] = 0.1, 6.0                       # N = 64: mr 32, 2 columns per lane
     assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 3
-    f[3] = 0.5                                  # dense candidate not offered (path off)
-    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 3
+    f[3], f[2] = 0.5, 10.0                      # dense candidate not offered (path off)
+    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 1
     n = C.c_int64(0)
     assert lib.rosko_mlp_param_count(16, 64, 7, C.byref(n)) == 0
     assert n.value == 16 * 64 + 64 + 64 * 64 + 64 + 64 * 7 + 7

@@ -64,11 +64,17 @@ def test_record_jump_lands_on_value_blocks(tu):
     sites = [n for n, (_, op, arg) in enumerate(ins) if op == "s_setpc_b64" and "88:89" in arg]
     assert len(sites) > 0
     for n in sites:
-        # s_mul_i32 c, c, BLK ; s_sub_u32 c, END-PC, c ; s_set_gpr_idx_on ; s_getpc_b64 ;
-        # s_add_u32 ; s_addc_u32 ; s_setpc_b64
-        mul, sub, on, getpc = ins[n - 6], ins[n - 5], ins[n - 4], ins[n - 3]
-        assert mul[1] == "s_mul_i32" and sub[1] == "s_sub_u32", ins[n - 6:n + 1]
-        assert on[1] == "s_set_gpr_idx_on" and getpc[1] == "s_getpc_b64"
+        # ... s_mul_i32 c, c, BLK ... s_sub_u32 c, END-PC, c ... s_getpc_b64 pc ;
+        # s_add_u32 pc.lo, pc.lo, c ; s_addc_u32 pc.hi, pc.hi, 0 ; s_setpc_b64 pc, with the
+        # add and its carry adjacent (no SCC writer between them)
+        assert ins[n - 1][1] == "s_addc_u32" and ins[n - 2][1] == "s_add_u32", ins[n - 3:n + 1]
+        assert ins[n - 3][1] == "s_getpc_b64", ins[n - 3]
+        getpc = ins[n - 3]
+        c = ins[n - 2][2].split(",")[2].strip()
+        sub = next(x for x in reversed(ins[n - 16:n - 3])
+                   if x[1] == "s_sub_u32" and x[2].split(",")[0].strip() == c)
+        mul = next(x for x in reversed(ins[n - 16:n - 3])
+                   if x[1] == "s_mul_i32" and x[2].split(",")[0].strip() == c)
         blk = int(mul[2].split(",")[2].strip(), 0)
         end = getpc[0] + 4 + int(sub[2].split(",")[1].strip(), 0)
         starts = []
