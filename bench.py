@@ -39,14 +39,26 @@ SPMM_SOURCES = ("spmm_kernel.h", "spmm_loop.inc", "spmm.hip", "spmm_bf32.hip", "
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_spmm_rows_cnn_256x2304x3136_pmc.txt")
 
 
-def spmm_sources_digest():
-    """sha256 over the sources of the SpMM kernels (the counters below are
-    only valid for the code they were taken on)."""
+def _code_only(text):
+    """C/C++ source without comments and with whitespace runs collapsed."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def spmm_sources_digest(read=None):
+    """sha256 over the code of the SpMM kernels, comments and layout ignored
+    (the counters below are only valid for the code they were taken on)."""
     import hashlib
     h = hashlib.sha256()
     for name in SPMM_SOURCES:
-        with open(os.path.join(ROOT, "paper_2307_03930_amd", "csrc", name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+        if read is None:
+            with open(os.path.join(ROOT, "paper_2307_03930_amd", "csrc", name)) as f:
+                text = f.read()
+        else:
+            text = read(name)
+        h.update(name.encode() + b"\0" + _code_only(text).encode())
     return h.hexdigest()
 
 

@@ -15,13 +15,14 @@
 // a column never waits on a dependent load round trip.
 //
 // The C row is a run-time index, yet the tile must stay in registers.  The
-// tile is pinned to the fixed VGPR range v[64 : 64+MR*V) through inline-asm
-// register constraints, row r of column j at v[64 + j*MR + r].  For every
-// value, s_set_gpr_idx_on with the (wave-uniform) row byte turns on relative
-// addressing of the FMA's accumulator, and V v_fmac_f32 follow whose A
+// tile is pinned to a fixed VGPR range through inline-asm register
+// constraints, row r of column j at v[base + j*MR + r].  The column's values
+// are applied by a run of equal-sized value blocks entered through one
+// computed jump per column (at the block of value count-1); each block cuts
+// its row byte to log2(MR) bits, makes it the index of VGPR-relative
+// addressing (SRC2 and DST of the FMA), and issues V v_fmac_f32 whose A
 // operand is the value's lane of the record VGPR broadcast by DPP
-// row_newbcast.  Row bytes are masked to MR-1 so the relative access can
-// never leave the pinned range.
+// row_newbcast.  The cut keeps every relative access inside the pinned range.
 //
 // Small M x N outputs cannot fill the GPU with one wavefront per tile, so a
 // panel's records are cut into k_split * H equal runs: H wavefronts of one

@@ -11,10 +11,11 @@ typedef float f32x32 __attribute__((ext_vector_type(32)));
 
 // ---------------------------------------------------------------- tile
 // The C tile of one wavefront: MR rows x V columns per lane, column j of row
-// r in VGPR base + j*MR + r, pinned by the asm constraints below so that a
-// row index can select the register at run time.  The base is v40 for the
-// 128-register tiles (so the kernel fits in 168 VGPRs, three wavefronts per
-// SIMD) and v32 for the smaller ones.
+// r in VGPR base + j*MR + r, pinned by asm constraints so that a row index
+// can select the register at run time.  In the record loop (spmm_loop.inc)
+// the base is the first multiple of 8 after the loop's record and B
+// registers (v24 for the 128-register tiles at depth 4: 158 VGPRs in all);
+// the element-load path below pins it at v40 (128-register tiles) or v32.
 template <int NT>
 struct Tile { f32x32 t[NT]; };
 
