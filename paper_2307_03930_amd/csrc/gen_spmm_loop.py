@@ -37,7 +37,7 @@ import os
 TILES = [(8, 4), (16, 4), (32, 2), (32, 4), (64, 2), (128, 1)]
 DTYPES = ["f32", "bf16"]
 DEPTHS = [4, 8]
-PC = 88          # s[88:89]: program counter of the per-record jump (clobbered)
+PC = 88          # s[88:89]: jump base, s[90:91]: per-record target (both clobbered)
 
 
 def unit_dwords(dt, v):
@@ -102,9 +102,12 @@ def gen_variant(mr, v, dt, D):
     def a(x):
         L.append(x)
 
-    def rload_const(j):
-        a(f"s_min_u32 %[t], {j * 64}, %[olast]")
-        a(f"buffer_load_dword v{j}, %[vro], %[rr], %[t] offen")
+    def rload(u):
+        # record at the lane offset vro (the run's next record, clamped to its
+        # last one), then vro moves on one record (again clamped)
+        a(f"buffer_load_dword v{u}, %[vro], %[rr], 0 offen")
+        a("v_add_u32 %[vro], 64, %[vro]")
+        a("v_min_u32 %[vro], %[vro], %[vlast]")
 
     def bload(h, s):
         dst, _, _ = pl.b_slot(s)
@@ -117,31 +120,30 @@ def gen_variant(mr, v, dt, D):
         s = u % D
         dst, bregs, conv = pl.b_slot(s)
         vr = f"v{u}"
-        # count of record i, then the header of record i+D into the same SGPR
-        a(f"s_and_b32 %[c], %[h{s}], 0xff")
+        # count of record i (4 bits), then the header of record i+D into the
+        # same SGPR (its B row is issued after the values, when slot s is free)
+        a(f"s_and_b32 %[c], %[h{s}], 0xf")
         a(f"v_readfirstlane_b32 %[h{s}], v{(u + D) % R}")
         for c in conv:
             a(c)
         for wd in range(3):
             a(f"v_readlane_b32 %[w{wd}], {vr}, {wd + 1}")
-        # two independent scalar chains, interleaved: the jump of record i
-        # (count clamped to 12, block of value count-1; count 0 lands on .Le)
-        # and the B-row offset of record i+D (row clamped to K-1), whose load
-        # goes out after the values, when B slot s is free again
-        a("s_min_u32 %[c], %[c], 12")
+        # the jump of record i, interleaved with the B-row offset of record
+        # i+D (row clamped to K-1): target = .Le_u - count * block, reached
+        # from the base address taken once before the loop.  Counts 13..15
+        # (never written by packing) land in padding blocks of s_nop.
         a(f"s_lshr_b32 %[k], %[h{s}], 8")
         a(f"s_mul_i32 %[c], %[c], {pl.blk}")
         a("s_min_u32 %[k], %[k], %[km1]")
-        a(f"s_sub_u32 %[c], .Le{u}_%= - .Lp{u}_%=, %[c]")
+        a(f"s_sub_u32 %[c], .Le{u}_%= - .Lbase%=, %[c]")
         a("s_mul_i32 %[k], %[k], %[ldbb]")
-        a("s_min_u32 %[t], %[o], %[olast]")
         a("s_set_gpr_idx_on %[c], gpr_idx(SRC2,DST)")
-        a(f"s_getpc_b64 s[{PC}:{PC + 1}]")
-        L.append(f".Lp{u}_%=:")
         # nothing between the add and its carry: SCC carries the high word
-        a(f"s_add_u32 s{PC}, s{PC}, %[c]")
-        a(f"s_addc_u32 s{PC + 1}, s{PC + 1}, 0")
-        a(f"s_setpc_b64 s[{PC}:{PC + 1}]")
+        a(f"s_add_u32 s{PC + 2}, s{PC}, %[c]")
+        a(f"s_addc_u32 s{PC + 3}, s{PC + 1}, 0")
+        a(f"s_setpc_b64 s[{PC + 2}:{PC + 3}]")
+        for _ in range(3 * pl.blk // 4):      # counts 15, 14, 13: three blocks of s_nop
+            a("s_nop 0")
         for t in range(11, -1, -1):
             # row byte t, cut to log2(MR) bits: always inside the tile
             a(f"s_bfe_u32 %[x], %[w{t // 4}], {hex((bits << 16) | 8 * (t % 4))}")
@@ -152,27 +154,27 @@ def gen_variant(mr, v, dt, D):
         L.append(f".Le{u}_%=:")
         a("s_set_gpr_idx_off")
         a(f"{pl.b_load_op()} {dst}, %[vbo], %[rb], %[k] offen")
-        a(f"buffer_load_dword v{u}, %[vro], %[rr], %[t] offen")
-        a("s_add_u32 %[o], %[o], 64")
+        rload(u)
 
-    # ---- prologue: records 0..D-1, then for each: header, B row, record j+D.
-    # Record offsets are clamped to the run's last record.
+    # ---- prologue: the jump base; records 0..D-1, then for each: header,
+    # B row, record j+D
+    a(f"s_getpc_b64 s[{PC}:{PC + 1}]")
+    L.append(".Lbase%=:")
     for j in range(D):
-        rload_const(j)
+        rload(j)
     for j in range(D):
         a(f"s_waitcnt vmcnt({D - 1 + j})")
         a(f"v_readfirstlane_b32 %[h{j}], v{j}")
         bload(f"h{j}", j)
-        rload_const(D + j)
-    a(f"s_mov_b32 %[o], {R * 64}")
+        rload(D + j)
+    a("s_mov_b32 %[nl], %[n]")
     # ---- steady state, unrolled over the 2D record slots.  At the start of
     # step i the loads in flight are, oldest first, B(i) R(i+D) B(i+1) ...
-    # B(i+D-1) R(i+2D-1): vmcnt(2D-2) completes B(i) and R(i+D).  o is the
-    # byte offset of record i+2D; the run ends when it reaches (n+2D)*64.
+    # B(i+D-1) R(i+2D-1): vmcnt(2D-2) completes B(i) and R(i+D).  nl counts
+    # the records left; the borrow of its decrement ends the run.
     a(".Lloop%=:")
     for u in range(R):
-        s = u % D
-        a("s_cmp_ge_u32 %[o], %[oend]")
+        a("s_sub_u32 %[nl], %[nl], 1")
         a("s_cbranch_scc1 .Ldone%=")
         a(f"s_waitcnt vmcnt({2 * D - 2})")
         body(u)
@@ -190,16 +192,17 @@ def gen_variant(mr, v, dt, D):
     return f"""// {mr} x {v} tile, {dt.upper()} B, {D} B rows in flight; tile at v{pl.base}
 __device__ __forceinline__ void {pl.fn()}(Tile<{pl.nt}>& acc, uint32_t n,
                                        __amdgpu_buffer_rsrc_t rr, __amdgpu_buffer_rsrc_t rb,
-                                       uint32_t ldbb, uint32_t km1, uint32_t vro, uint32_t vbo) {{
-  uint32_t o, t, k, c, x, w0, w1, w2, {hdecl};
-  const uint32_t olast = (n - 1) * 64, oend = (n + {R}) * 64;
+                                       uint32_t ldbb, uint32_t km1, uint32_t vro0, uint32_t vbo) {{
+  uint32_t nl, k, c, x, w0, w1, w2, {hdecl};
+  uint32_t vro = vro0;                                // lane offset of the next record
+  const uint32_t vlast = vro0 + (n - 1) * 64;         // ... of the run's last record
   asm volatile(
-{text}      : {outs}, [o] "=&s"(o), [t] "=&s"(t), [k] "=&s"(k), [c] "=&s"(c), [x] "=&s"(x),
+{text}      : {outs}, [vro] "+v"(vro), [nl] "=&s"(nl), [k] "=&s"(k), [c] "=&s"(c), [x] "=&s"(x),
         [w0] "=&s"(w0), [w1] "=&s"(w1), [w2] "=&s"(w2),
         {houts}
-      : [oend] "s"(oend), [olast] "s"(olast), [ldbb] "s"(ldbb), [km1] "s"(km1), [rr] "s"(rr), [rb] "s"(rb),
-        [vro] "v"(vro), [vbo] "v"(vbo)
-      : {clob}, "s{PC}", "s{PC + 1}", "m0", "scc", "memory");
+      : [n] "s"(n), [ldbb] "s"(ldbb), [km1] "s"(km1), [rr] "s"(rr), [rb] "s"(rb),
+        [vlast] "v"(vlast), [vbo] "v"(vbo)
+      : {clob}, "s{PC}", "s{PC + 1}", "s{PC + 2}", "s{PC + 3}", "m0", "scc", "memory");
 }}
 """
 

@@ -49,7 +49,9 @@ k_fill_zero(float* __restrict__ C, int64_t M, int64_t N, int64_t ldc) {
 // Split-K epilogue: C[m][n] = (beta ? C[m][n] : 0) + s_m * sum_s ws[s][m][n],
 // the partials added in split order (fixed, so the result is reproducible).
 // blockIdx.y strides over rows; a thread handles 4 consecutive columns with
-// float4 accesses when VEC (N, ldc and the pointers allow it).
+// float4 accesses when VEC (N, ldc and the pointers allow it), and issues the
+// loads of up to 8 splits before it adds any, so a call costs about one
+// memory round trip per 8 splits.
 template <bool VEC>
 __global__ void __launch_bounds__(256)
 k_reduce_splits(const float* __restrict__ ws, int32_t S, int64_t M, int64_t N,
@@ -63,20 +65,25 @@ k_reduce_splits(const float* __restrict__ ws, int32_t S, int64_t M, int64_t N,
     float* c = C + m * ldc + n;
     const float sc = row_scale ? row_scale[m] : 1.0f;
     if (VEC) {
-      float4 acc = *reinterpret_cast<const float4*>(src);
-      int32_t s = 1;
-      for (; s + 4 <= S; s += 4) {
-        float4 x[4];
+      float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      for (int32_t s0 = 0; s0 < S; s0 += 8) {
+        float4 x[8];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) x[t] = *reinterpret_cast<const float4*>(src + (s + t) * MN);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          acc.x += x[t].x; acc.y += x[t].y; acc.z += x[t].z; acc.w += x[t].w;
+        for (int t = 0; t < 8; ++t) {
+          // splits past S re-read the last one (in bounds) and are not added
+          const int32_t sl = s0 + t < S ? s0 + t : S - 1;
+          x[t] = *reinterpret_cast<const float4*>(src + sl * MN);
         }
-      }
-      for (; s < S; ++s) {
-        const float4 x = *reinterpret_cast<const float4*>(src + s * MN);
-        acc.x += x.x; acc.y += x.y; acc.z += x.z; acc.w += x.w;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          if (s0 + t < S) {
+            if (s0 + t == 0) {
+              acc = x[0];
+            } else {
+              acc.x += x[t].x; acc.y += x[t].y; acc.z += x[t].z; acc.w += x[t].w;
+            }
+          }
+        }
       }
       if (row_scale) { acc.x *= sc; acc.y *= sc; acc.z *= sc; acc.w *= sc; }
       if (beta) {

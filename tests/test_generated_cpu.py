@@ -60,32 +60,42 @@ def _device_disassembly(tu):
 @pytest.mark.skipif(not os.path.exists(f"{LLVM}/llvm-objdump"), reason="ROCm LLVM tools missing")
 @pytest.mark.parametrize("tu", ["spmm_bf32.hip", "spmm_bbf16.hip"])
 def test_record_jump_lands_on_value_blocks(tu):
+    """Each loop takes its jump base once (s_getpc_b64 s[88:89] before the
+    loop); each column then jumps to base + (END_u - base) - count * BLK with
+    the count masked to 4 bits.  Checked at every jump site: the 15 blocks
+    (3 of s_nop padding, then values 11..0) are exactly BLK bytes apart and
+    start right after the jump, END_u follows the last one, and the add that
+    forms the target sits right before its carry and the jump."""
     ins = _device_disassembly(tu)
-    sites = [n for n, (_, op, arg) in enumerate(ins) if op == "s_setpc_b64" and "88:89" in arg]
+    sites = [n for n, (_, op, arg) in enumerate(ins) if op == "s_setpc_b64" and "90:91" in arg]
     assert len(sites) > 0
+    bases = [n for n, (_, op, arg) in enumerate(ins) if op == "s_getpc_b64" and "88:89" in arg]
     for n in sites:
-        # ... s_mul_i32 c, c, BLK ... s_sub_u32 c, END-PC, c ... s_getpc_b64 pc ;
-        # s_add_u32 pc.lo, pc.lo, c ; s_addc_u32 pc.hi, pc.hi, 0 ; s_setpc_b64 pc, with the
-        # add and its carry adjacent (no SCC writer between them)
         assert ins[n - 1][1] == "s_addc_u32" and ins[n - 2][1] == "s_add_u32", ins[n - 3:n + 1]
-        assert ins[n - 3][1] == "s_getpc_b64", ins[n - 3]
-        getpc = ins[n - 3]
+        base = ins[max(b for b in bases if b < n)][0] + 4        # address after s_getpc_b64
         c = ins[n - 2][2].split(",")[2].strip()
-        sub = next(x for x in reversed(ins[n - 16:n - 3])
+        window = ins[n - 28:n - 2]
+        sub = next(x for x in reversed(window)
                    if x[1] == "s_sub_u32" and x[2].split(",")[0].strip() == c)
-        mul = next(x for x in reversed(ins[n - 16:n - 3])
+        mul = next(x for x in reversed(window)
                    if x[1] == "s_mul_i32" and x[2].split(",")[0].strip() == c)
+        mask = next(x for x in reversed(window)
+                    if x[1] == "s_and_b32" and x[2].split(",")[0].strip() == c)
+        assert int(mask[2].split(",")[2].strip(), 0) == 0xF
         blk = int(mul[2].split(",")[2].strip(), 0)
-        end = getpc[0] + 4 + int(sub[2].split(",")[1].strip(), 0)
-        starts = []
+        end = base + int(sub[2].split(",")[1].strip(), 0)
+        starts, pad = [], 0
         m = n + 1
         while ins[m][1] != "s_set_gpr_idx_off":
             if ins[m][1] == "s_bfe_u32":
                 starts.append(ins[m][0])
+            elif ins[m][1] == "s_nop":
+                pad += 1
             else:
                 assert ins[m][1] in ("s_set_gpr_idx_idx", "v_fmac_f32_dpp"), ins[m]
             m += 1
-        assert len(starts) == 12
-        assert starts[0] == ins[n][0] + 4                      # right after s_setpc_b64
+        assert len(starts) == 12 and pad * 4 == 3 * blk
+        assert starts[0] == ins[n][0] + 4 + 3 * blk              # after the jump and padding
         assert all(b - a == blk for a, b in zip(starts, starts[1:]))
-        assert end == starts[-1] + blk == ins[m][0]            # s_set_gpr_idx_off at END
+        assert end == starts[-1] + blk == ins[m][0]             # s_set_gpr_idx_off at END
+        assert end - 15 * blk == ins[n][0] + 4                  # count 15: first padding block
