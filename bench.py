@@ -116,6 +116,112 @@ def cpu_baseline(As, B, budget_s: float = 20.0):
                       f"FP64 CSR loop, {threads} threads"}
 
 
+def _time_us(fn, reps, warm=3):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps * 1e3
+
+
+def run_precision(args):
+    """The precision forms: A 4096 x 4096 at 90% and 98% (i.i.d. mask, N(0,1)
+    values) with values in FP32, BF16 or FP8 E4M3 + row scales, times B
+    4096 x 2048 (BF16 for the BF16/FP8 forms, its FP32 copy for the FP32
+    form); FP32 accumulation.  SpMM and packing timed separately."""
+    import numpy as np
+    import torch
+    from paper_2307_03930_amd import ops, sched, synth
+    torch.backends.cuda.matmul.allow_tf32 = False
+    dev = torch.device("cuda:0")
+    out = []
+    dense_us = None
+    for sp in (0.90, 0.98):
+        pr = synth.precision_problem(sp)
+        A = torch.from_numpy(pr.A).to(dev)
+        B32 = torch.from_numpy(pr.B).to(dev)
+        B16 = B32.to(torch.bfloat16)
+        M, K = pr.A.shape
+        N = pr.B.shape[1]
+        if dense_us is None:
+            dense_us = _time_us(lambda: torch.matmul(A, B32), 10)
+        mr, cand = sched.candidate(sched.choose(A, N))
+        plan = ops.make_plan(cand.cols_per_lane)
+        kt = int((pr.A != 0).any(axis=0).sum())
+        for vals in ("f32", "bf16", "fp8"):
+            P = ops.pack(A, mr, vals)
+            Bd = B32 if vals == "f32" else B16
+            C = torch.empty((M, N), dtype=torch.float32, device=dev)
+            ws = torch.empty(max(ops.spmm_workspace_size(P, N, plan), 1), dtype=torch.uint8,
+                             device=dev)
+            t = _time_us(lambda: ops.spmm(P, Bd, C, plan=plan, ws=ws), args.reps)
+            pws = torch.empty(max(ops.workspace_size(M, K, mr), 1), dtype=torch.uint8, device=dev)
+            tp = _time_us(lambda: ops.pack_into(A, P, pws), args.reps)
+            s_val = {"f32": 4, "bf16": 2, "fp8": 1}[vals]
+            s_b = 4 if vals == "f32" else 2
+            by = alg_bytes(P.nnz, P.ncols, (M + mr - 1) // mr, kt, N, M, s_val=s_val, s_b=s_b) + \
+                (4 * M if vals == "fp8" else 0)
+            fl = 2.0 * P.nnz * N
+            out.append({"sparsity": sp, "values": vals, "B": "f32" if vals == "f32" else "bf16",
+                        "mr": mr, "nnz": P.nnz, "spmm_us": round(t, 2), "pack_us": round(tp, 2),
+                        "gflops": round(fl / (t * 1e-6) / 1e9, 1),
+                        "alu_frac": round(fl / (t * 1e-6) / 1e12 / VALU_FP32_PEAK_TFS, 3),
+                        "hbm_frac": round(by / (t * 1e-6) / 1e9 / HBM_PEAK_GBS, 3),
+                        "speedup_vs_dense_fp32": round(dense_us / t, 2)})
+        del A, B32, B16
+    print(json.dumps({"workload": "precision forms: A 4096x4096 at 90/98% (i.i.d.), values "
+                                  "FP32/BF16/FP8+row scales, B 4096x2048, FP32 accumulate",
+                      "unit": "us", "dense_fp32_gemm_us": round(dense_us, 2), "data": "synthetic",
+                      "forms": out}), flush=True)
+
+
+def run_backward(args):
+    """Forward and backward of C = A B: A 1024 x 4096 at 95% (i.i.d.), B
+    4096 x 1024, dC 1024 x 1024, FP32.  dB = A^T dC through the packed
+    transpose, dA = (dC B^T) on A's mask (SDDMM)."""
+    import torch
+    from paper_2307_03930_amd import ops, sched, synth
+    torch.backends.cuda.matmul.allow_tf32 = False
+    dev = torch.device("cuda:0")
+    pr = synth.grad_problem()
+    A = torch.from_numpy(pr.A).to(dev)
+    B = torch.from_numpy(pr.B).to(dev)
+    dC = torch.from_numpy(pr.dC).to(dev)
+    M, K = pr.A.shape
+    N = pr.B.shape[1]
+    mr, cand = sched.candidate(sched.choose(A, N))
+    P = ops.pack(A, mr, "f32")
+    Pt = ops.pack_transpose(A, mr)
+    plan = ops.make_plan(cand.cols_per_lane)
+    C = torch.empty((M, N), dtype=torch.float32, device=dev)
+    ws = torch.empty(max(ops.spmm_workspace_size(P, N, plan), 1), dtype=torch.uint8, device=dev)
+    n = P.nnz
+    parts = {
+        "pack_us": _time_us(lambda: ops.pack_into(A, P, P._ws), args.reps),
+        "forward_spmm_us": _time_us(lambda: ops.spmm(P, B, C, plan=plan, ws=ws), args.reps),
+        "dB_spmm_us": _time_us(lambda: ops.spmm_backward(P, Pt, B, dC, True, False), args.reps),
+        "dA_sddmm_us": _time_us(lambda: ops.spmm_backward(P, Pt, B, dC, False, True), args.reps),
+        "backward_us": _time_us(lambda: ops.spmm_backward(P, Pt, B, dC, True, True), args.reps),
+    }
+    dense_us = _time_us(lambda: torch.matmul(A, B), 10)
+    fl = 2.0 * n * N
+    res = {k: round(v, 2) for k, v in parts.items()}
+    for k in ("forward_spmm_us", "dB_spmm_us", "dA_sddmm_us"):
+        res[k.replace("_us", "_gflops")] = round(fl / (parts[k] * 1e-6) / 1e9, 1)
+        res[k.replace("_us", "_alu_frac")] = round(fl / (parts[k] * 1e-6) / 1e12 /
+                                                  VALU_FP32_PEAK_TFS, 3)
+    print(json.dumps({"workload": "forward + backward: A 1024x4096 at 95% (i.i.d.), B 4096x1024, "
+                                  "dC 1024x1024, FP32", "mr": mr, "nnz": n, "unit": "us",
+                      "dense_fp32_gemm_us": round(dense_us, 2), "data": "synthetic", **res}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,12 +237,21 @@ def main():
     ap.add_argument("--mr", type=int, default=None,
                     help="panel height for every matrix (default: the library's analytic "
                          "plan rule picks it per matrix)")
+    ap.add_argument("--workload", choices=("cnn", "precision", "backward"), default="cnn",
+                    help="cnn: the pruned-CNN sweep (the headline line); precision: the "
+                         "BF16 / FP8 value forms at 4096x4096; backward: forward + backward "
+                         "at 1024x4096")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "precision":
+        return run_precision(args)
+    if args.workload == "backward":
+        return run_backward(args)
 
     import numpy as np
     import torch

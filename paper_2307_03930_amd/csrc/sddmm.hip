@@ -3,8 +3,8 @@
 // mask), and the result is written in A's packed order so it lines up with
 // the packed values.
 //
-// A workgroup takes one panel; its wavefronts stride over the panel's kept
-// columns.  For a column the wave keeps the selected B row in registers
+// General kernel (any mr, N): a workgroup takes one panel; its wavefronts
+// stride over the panel's kept columns.  For a column the wave keeps the selected B row in registers
 // (lanes over N) and reuses it for every value of the column, which is the
 // column-wise reuse the packed format exposes; each value's dot product is
 // finished with a wave reduction.
@@ -60,12 +60,120 @@ k_sddmm(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict__ c
   }
 }
 
+// Sum of a float over the wavefront, in a fixed order, into lane 63: DPP
+// row shifts by 1, 2, 4 and 8 inside each 16-lane row, then the row totals
+// broadcast forward (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2
+// and 3).
+#define RK_DPPF(V, CTRL, RM, BM, BC) \
+  __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(V), CTRL, RM, BM, BC))
+__device__ __forceinline__ float wave_sum_f32(float x) {
+  float v = x + RK_DPPF(x, 0x111, 0xf, 0xf, true);   // row_shr:1
+  v += RK_DPPF(v, 0x112, 0xf, 0xf, true);            // row_shr:2: sums of 4
+  v += RK_DPPF(v, 0x114, 0xf, 0xe, false);           // row_shr:4, lanes 4..15: sums of 8
+  v += RK_DPPF(v, 0x118, 0xf, 0xc, false);           // row_shr:8, lanes 8..15: sums of 16
+  v += RK_DPPF(v, 0x142, 0xa, 0xf, false);           // row_bcast:15
+  v += RK_DPPF(v, 0x143, 0xc, 0xf, false);           // row_bcast:31
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+#undef RK_DPPF
+
+// Panels of at most 8 rows and N <= 64 * VB <= 1024.  The workgroup puts its
+// panel's dC rows in LDS once; each of its wavefronts takes a contiguous
+// range of the panel's kept columns (the panel's columns are also split over
+// G workgroups).  The column metadata and in-panel rows (packed as bytes)
+// come in 64 columns at a time, one column per lane; per column the wave
+// holds the B row in registers (VB values per lane, the next column's row
+// already in flight) and, for each of the column's values, forms the dot
+// product with the LDS row and reduces it across the wavefront.
+constexpr int kSdLdsRows = 8;
+constexpr int kSdLdsG = 4;       // workgroups per panel
+
+template <int VB>
+__global__ void __launch_bounds__(64 * kSdW)
+k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict__ col_ind,
+            const int32_t* __restrict__ col_nnz, const int64_t* __restrict__ col_ptr,
+            const uint8_t* __restrict__ loc, int64_t M, int32_t mr, const float* __restrict__ dC,
+            int64_t lddc, const float* __restrict__ B, int64_t ldb, int64_t N,
+            float* __restrict__ dA) {
+  __shared__ float sdc[kSdLdsRows * 64 * VB];
+  const int64_t p = blockIdx.x / kSdLdsG;
+  const int g = blockIdx.x % kSdLdsG;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r0 = p * mr;
+  const int rows = (int)min((int64_t)mr, M - r0);
+  for (int idx = threadIdx.x; idx < rows * 64 * VB; idx += 64 * kSdW) {
+    const int r = idx / (64 * VB), n = idx - r * (64 * VB);
+    sdc[idx] = n < N ? dC[(r0 + r) * lddc + n] : 0.0f;
+  }
+  __syncthreads();
+  const int64_t c_lo = panel_col_ptr[p], c_hi = panel_col_ptr[p + 1];
+  const int64_t parts = (int64_t)kSdLdsG * kSdW, part = (int64_t)g * kSdW + w;
+  const int64_t a = c_lo + (c_hi - c_lo) * part / parts;
+  const int64_t e = c_lo + (c_hi - c_lo) * (part + 1) / parts;
+  auto load_b = [&](int64_t k, float* b) {
+#pragma unroll
+    for (int v = 0; v < VB; ++v) {
+      const int64_t col = lane + 64 * v;
+      b[v] = col < N ? B[k * ldb + col] : 0.0f;
+    }
+  };
+  for (int64_t cb = a; cb < e; cb += 64) {
+    const int64_t c = cb + lane;
+    const bool valid = c < e;
+    const int kk = valid ? col_ind[c] : 0;
+    const int nn = valid ? min(col_nnz[c], kSdLdsRows) : 0;
+    const int64_t zz = valid ? col_ptr[c] : 0;
+    uint32_t rlo = 0, rhi = 0;                  // in-panel rows of the column, bytes
+#pragma unroll
+    for (int t = 0; t < kSdLdsRows; ++t) {
+      const uint32_t r = t < nn ? loc[zz + t] : 0u;
+      if (t < 4) rlo |= r << (8 * t);
+      else rhi |= r << (8 * (t - 4));
+    }
+    const int cnt = (int)min<int64_t>(64, e - cb);
+    float b[VB], bn[VB];
+    load_b(__builtin_amdgcn_readfirstlane(kk), bn);
+    for (int j = 0; j < cnt; ++j) {
+#pragma unroll
+      for (int v = 0; v < VB; ++v) b[v] = bn[v];
+      if (j + 1 < cnt) load_b(__builtin_amdgcn_readlane(kk, j + 1), bn);
+      const int n = __builtin_amdgcn_readlane(nn, j);
+      const int64_t z = ((int64_t)__builtin_amdgcn_readlane((int)(zz >> 32), j) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)zz, j);
+      const uint32_t lo = __builtin_amdgcn_readlane(rlo, j), hi = __builtin_amdgcn_readlane(rhi, j);
+      for (int t = 0; t < n; ++t) {
+        const int r = (int)(((t < 4 ? lo : hi) >> (8 * (t & 3))) & 7u);   // rows < 8
+        const float* row = sdc + r * 64 * VB;
+        float acc = 0.0f;
+#pragma unroll
+        for (int v = 0; v < VB; ++v) acc = fmaf(row[lane + 64 * v], b[v], acc);
+        const float sum = wave_sum_f32(acc);
+        if (lane == 0) dA[z + t] = sum;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const float* B,
                      int64_t ldb, int64_t N, float* dA_val, hipStream_t s) {
   if (A->n_panels == 0) return ROSKO_OK;
   const int64_t vb = ceil_div(N, 64);
+  if (A->mr <= kSdLdsRows && vb <= 16 && (int64_t)A->n_panels * kSdLdsG <= INT32_MAX) {
+    const dim3 grid((unsigned)(A->n_panels * kSdLdsG));
+#define RK_SDL(VB_)                                                                          \
+  hipLaunchKernelGGL(k_sddmm_lds<VB_>, grid, dim3(64 * kSdW), 0, s, A->panel_col_ptr,        \
+                     A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M, A->mr, dC, lddc, B,   \
+                     ldb, N, dA_val)
+    if (vb <= 4) RK_SDL(4);
+    else if (vb <= 8) RK_SDL(8);
+    else RK_SDL(16);
+#undef RK_SDL
+    ROSKO_LAUNCH_CHECK("k_sddmm_lds");
+    return ROSKO_OK;
+  }
 #define RK_SD(VB_)                                                                          \
   hipLaunchKernelGGL(k_sddmm<VB_>, dim3((unsigned)A->n_panels), dim3(64 * kSdW), 0, s,       \
                      A->panel_col_ptr, A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M,     \

@@ -24,7 +24,10 @@ def _dA_scale(pk, dC, B):
 
 
 @pytest.mark.parametrize("M,K,N,mr", [(32, 64, 16, 8), (100, 257, 190, 32), (96, 130, 1, 16),
-                                      (64, 200, 700, 64), (70, 90, 2100, 32)])
+                                      (64, 200, 700, 64), (70, 90, 2100, 32),
+                                      # panels of <= 8 rows and N <= 1024: the LDS kernel
+                                      (37, 300, 65, 8), (90, 128, 1024, 8), (50, 77, 1, 4),
+                                      (16, 40, 300, 1), (201, 513, 257, 8), (9, 1000, 511, 5)])
 def test_backward_small(M, K, N, mr):
     say(f"backward {M}x{K}x{N} mr={mr}")
     A = synth.sparse_matrix(M, K, 0.1, 700 + M)
@@ -41,21 +44,23 @@ def test_backward_small(M, K, N, mr):
     assert err(dA.cpu().numpy(), dA_ref, _dA_scale(pk, dC, B)) <= TOL
 
 
-def test_backward_grad_config_sampled():
+@pytest.mark.parametrize("mr", [32, 8])
+def test_backward_grad_config_sampled(mr):
     """1024 x 4096 at 95% with B 4096 x 1024 and dC 1024 x 1024, full size on
-    the GPU; sampled rows of dB and every 97th dA entry checked."""
-    say("backward 1024x4096x1024 s=0.95")
+    the GPU (mr 8: the panel height the analytic rule picks, and the LDS
+    SDDMM); sampled rows of dB and every 97th dA entry checked."""
+    say(f"backward 1024x4096x1024 s=0.95 mr={mr}")
     pr = synth.grad_problem()
     A, B, dC = pr.A, pr.B, pr.dC
-    P = ops.pack(dev(A), 32)
-    Pt = ops.pack_transpose(dev(A), 32)
+    P = ops.pack(dev(A), mr)
+    Pt = ops.pack_transpose(dev(A), mr)
     dA, dB = ops.spmm_backward(P, Pt, dev(B), dev(dC))
     ks = np.sort(synth.rng(703).choice(4096, 24, replace=False))
     Acols = np.ascontiguousarray(A[:, ks])
     dB_ref = O.grad_dB(Acols, dC)
     dB_scale = np.abs(Acols).T.astype(np.float64) @ np.abs(dC).astype(np.float64)
     e_dB = err(dB.cpu().numpy()[ks], dB_ref, dB_scale)
-    pk = O.pack(A, 32)
+    pk = O.pack(A, mr)                  # dA is in the packed order of this panel height
     dA_ref = O.grad_dA_packed(pk, dC, B)
     sel = np.arange(0, pk.nnz, 97)
     e_dA = err(dA.cpu().numpy()[sel], dA_ref[sel], _dA_scale(pk, dC, B)[sel])
