@@ -77,33 +77,37 @@ __device__ __forceinline__ float wave_sum_f32(float x) {
 }
 #undef RK_DPPF
 
-// Panels of at most 8 rows and N <= 64 * VB <= 1024.  The workgroup puts its
+// Panels of at most 8 rows and N <= 256 * VQ <= 1024.  The workgroup puts its
 // panel's dC rows in LDS once; each of its wavefronts takes a contiguous
 // range of the panel's kept columns (the panel's columns are also split over
-// G workgroups).  The column metadata and in-panel rows (packed as bytes)
-// come in 64 columns at a time, one column per lane; per column the wave
-// holds the B row in registers (VB values per lane, the next column's row
-// already in flight) and, for each of the column's values, forms the dot
-// product with the LDS row and reduces it across the wavefront.
+// kSdLdsG workgroups).  The column metadata and in-panel rows (packed as
+// bytes) come in 64 columns at a time, one column per lane.  Lane l holds
+// B columns 4l..4l+3 (+256 v) of a row as float4s; the B rows of the next
+// kSdDepth columns are in flight while a column is computed.  For each of a
+// column's values the wave forms the dot product with the LDS row and
+// reduces it across the wavefront.
 constexpr int kSdLdsRows = 8;
 constexpr int kSdLdsG = 4;       // workgroups per panel
+constexpr int kSdDepth = 4;      // B rows in flight per wavefront
 
-template <int VB>
+template <int VQ>
 __global__ void __launch_bounds__(64 * kSdW)
 k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict__ col_ind,
             const int32_t* __restrict__ col_nnz, const int64_t* __restrict__ col_ptr,
             const uint8_t* __restrict__ loc, int64_t M, int32_t mr, const float* __restrict__ dC,
-            int64_t lddc, const float* __restrict__ B, int64_t ldb, int64_t N,
+            int64_t lddc, const float* __restrict__ B, int64_t ldb, int64_t N, bool vec,
             float* __restrict__ dA) {
-  __shared__ float sdc[kSdLdsRows * 64 * VB];
+  constexpr int RW = 256 * VQ;                    // LDS row width (floats)
+  __shared__ float4 sdc4[kSdLdsRows * RW / 4];
+  float* sdc = reinterpret_cast<float*>(sdc4);
   const int64_t p = blockIdx.x / kSdLdsG;
   const int g = blockIdx.x % kSdLdsG;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t r0 = p * mr;
   const int rows = (int)min((int64_t)mr, M - r0);
-  for (int idx = threadIdx.x; idx < rows * 64 * VB; idx += 64 * kSdW) {
-    const int r = idx / (64 * VB), n = idx - r * (64 * VB);
+  for (int idx = threadIdx.x; idx < rows * RW; idx += 64 * kSdW) {
+    const int r = idx / RW, n = idx - r * RW;
     sdc[idx] = n < N ? dC[(r0 + r) * lddc + n] : 0.0f;
   }
   __syncthreads();
@@ -111,11 +115,19 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
   const int64_t parts = (int64_t)kSdLdsG * kSdW, part = (int64_t)g * kSdW + w;
   const int64_t a = c_lo + (c_hi - c_lo) * part / parts;
   const int64_t e = c_lo + (c_hi - c_lo) * (part + 1) / parts;
-  auto load_b = [&](int64_t k, float* b) {
+  // B row k at this lane's columns; vec: aligned float4 loads, else element
+  // loads (columns past N read as 0 and meet zero LDS entries)
+  auto load_b = [&](int64_t k, float4* b) {
+    const float* row = B + k * ldb;
 #pragma unroll
-    for (int v = 0; v < VB; ++v) {
-      const int64_t col = lane + 64 * v;
-      b[v] = col < N ? B[k * ldb + col] : 0.0f;
+    for (int v = 0; v < VQ; ++v) {
+      const int64_t col = 4 * lane + 256 * v;
+      if (vec && col < N) {
+        b[v] = *reinterpret_cast<const float4*>(row + col);
+      } else {
+        b[v] = make_float4(col < N ? row[col] : 0.0f, col + 1 < N ? row[col + 1] : 0.0f,
+                           col + 2 < N ? row[col + 2] : 0.0f, col + 3 < N ? row[col + 3] : 0.0f);
+      }
     }
   };
   for (int64_t cb = a; cb < e; cb += 64) {
@@ -132,24 +144,39 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
       else rhi |= r << (8 * (t - 4));
     }
     const int cnt = (int)min<int64_t>(64, e - cb);
-    float b[VB], bn[VB];
-    load_b(__builtin_amdgcn_readfirstlane(kk), bn);
-    for (int j = 0; j < cnt; ++j) {
+    float4 bq[kSdDepth][VQ];
 #pragma unroll
-      for (int v = 0; v < VB; ++v) b[v] = bn[v];
-      if (j + 1 < cnt) load_b(__builtin_amdgcn_readlane(kk, j + 1), bn);
-      const int n = __builtin_amdgcn_readlane(nn, j);
-      const int64_t z = ((int64_t)__builtin_amdgcn_readlane((int)(zz >> 32), j) << 32) |
-                        (uint32_t)__builtin_amdgcn_readlane((int)zz, j);
-      const uint32_t lo = __builtin_amdgcn_readlane(rlo, j), hi = __builtin_amdgcn_readlane(rhi, j);
-      for (int t = 0; t < n; ++t) {
-        const int r = (int)(((t < 4 ? lo : hi) >> (8 * (t & 3))) & 7u);   // rows < 8
-        const float* row = sdc + r * 64 * VB;
-        float acc = 0.0f;
+    for (int d = 0; d < kSdDepth; ++d)
+      load_b(__builtin_amdgcn_readlane(kk, d < cnt ? d : 0), bq[d]);
+    for (int j0 = 0; j0 < cnt; j0 += kSdDepth) {
 #pragma unroll
-        for (int v = 0; v < VB; ++v) acc = fmaf(row[lane + 64 * v], b[v], acc);
-        const float sum = wave_sum_f32(acc);
-        if (lane == 0) dA[z + t] = sum;
+      for (int d = 0; d < kSdDepth; ++d) {
+        const int j = j0 + d;
+        if (j < cnt) {
+          const int n = __builtin_amdgcn_readlane(nn, j);
+          const int64_t z = ((int64_t)__builtin_amdgcn_readlane((int)(zz >> 32), j) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane((int)zz, j);
+          const uint32_t lo = __builtin_amdgcn_readlane(rlo, j);
+          const uint32_t hi = __builtin_amdgcn_readlane(rhi, j);
+          for (int t = 0; t < n; ++t) {
+            const int r = (int)(((t < 4 ? lo : hi) >> (8 * (t & 3))) & 7u);   // rows < 8
+            const float4* row = sdc4 + (r * RW) / 4 + lane;
+            float acc = 0.0f;
+#pragma unroll
+            for (int v = 0; v < VQ; ++v) {
+              const float4 x = row[64 * v], y = bq[d][v];
+              acc = fmaf(x.x, y.x, acc);
+              acc = fmaf(x.y, y.y, acc);
+              acc = fmaf(x.z, y.z, acc);
+              acc = fmaf(x.w, y.w, acc);
+            }
+            const float sum = wave_sum_f32(acc);
+            if (lane == 0) dA[z + t] = sum;
+          }
+          // this slot's next column, kSdDepth ahead
+          const int jn = j + kSdDepth;
+          if (jn < cnt) load_b(__builtin_amdgcn_readlane(kk, jn), bq[d]);
+        }
       }
     }
   }
@@ -161,15 +188,16 @@ int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const
                      int64_t ldb, int64_t N, float* dA_val, hipStream_t s) {
   if (A->n_panels == 0) return ROSKO_OK;
   const int64_t vb = ceil_div(N, 64);
-  if (A->mr <= kSdLdsRows && vb <= 16 && (int64_t)A->n_panels * kSdLdsG <= INT32_MAX) {
+  if (A->mr <= kSdLdsRows && N <= 1024 && (int64_t)A->n_panels * kSdLdsG <= INT32_MAX) {
     const dim3 grid((unsigned)(A->n_panels * kSdLdsG));
-#define RK_SDL(VB_)                                                                          \
-  hipLaunchKernelGGL(k_sddmm_lds<VB_>, grid, dim3(64 * kSdW), 0, s, A->panel_col_ptr,        \
+    const bool vec = (N % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)B % 16 == 0);
+#define RK_SDL(VQ_)                                                                          \
+  hipLaunchKernelGGL(k_sddmm_lds<VQ_>, grid, dim3(64 * kSdW), 0, s, A->panel_col_ptr,        \
                      A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M, A->mr, dC, lddc, B,   \
-                     ldb, N, dA_val)
-    if (vb <= 4) RK_SDL(4);
-    else if (vb <= 8) RK_SDL(8);
-    else RK_SDL(16);
+                     ldb, N, vec, dA_val)
+    if (N <= 256) RK_SDL(1);
+    else if (N <= 512) RK_SDL(2);
+    else RK_SDL(4);
 #undef RK_SDL
     ROSKO_LAUNCH_CHECK("k_sddmm_lds");
     return ROSKO_OK;
