@@ -226,21 +226,28 @@ k_pack_scan(const int64_t* __restrict__ tile_sums, int64_t* __restrict__ tile_of
             int64_t ncols_cap, int64_t nrec_cap, int64_t* __restrict__ panel_nz_ptr,
             int64_t* __restrict__ panel_col_ptr, int64_t* __restrict__ col_ptr,
             int64_t* __restrict__ kblk_ptr) {
-  Tri carry{0, 0, 0};
-  for (int64_t base = 0; base < NT; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    Tri v{0, 0, 0};
-    if (i < NT) v = Tri{tile_sums[3 * i], tile_sums[3 * i + 1], tile_sums[3 * i + 2]};
-    Tri tot;
-    Tri e = block_excl_scan(v, &tot);
-    if (i < NT) {
-      tile_offs[3 * i] = carry.a + e.a;
-      tile_offs[3 * i + 1] = carry.b + e.b;
-      tile_offs[3 * i + 2] = carry.c + e.c;
-    }
-    carry.a += tot.a;
-    carry.b += tot.b;
-    carry.c += tot.c;
+  // each thread takes a contiguous run of tiles: their sums, one block scan
+  // of the run totals, then the run's exclusive offsets
+  const int64_t per = (NT + blockDim.x - 1) / blockDim.x;
+  const int64_t t0 = (int64_t)threadIdx.x * per;
+  const int64_t t1 = min(NT, t0 + per);
+  Tri run{0, 0, 0};
+#pragma unroll 8
+  for (int64_t t = t0; t < t1; ++t) {
+    run.a += tile_sums[3 * t];
+    run.b += tile_sums[3 * t + 1];
+    run.c += tile_sums[3 * t + 2];
+  }
+  Tri carry;
+  Tri e = block_excl_scan(run, &carry);
+#pragma unroll 8
+  for (int64_t t = t0; t < t1; ++t) {
+    tile_offs[3 * t] = e.a;
+    tile_offs[3 * t + 1] = e.b;
+    tile_offs[3 * t + 2] = e.c;
+    e.a += tile_sums[3 * t];
+    e.b += tile_sums[3 * t + 1];
+    e.c += tile_sums[3 * t + 2];
   }
   if (threadIdx.x == 0)
     close_packing(carry, totals, P, S, nnz_cap, ncols_cap, nrec_cap, panel_nz_ptr, panel_col_ptr,
