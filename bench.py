@@ -195,7 +195,10 @@ def run_backward(args):
     dC = torch.from_numpy(pr.dC).to(dev)
     M, K = pr.A.shape
     N = pr.B.shape[1]
-    mr, cand = sched.candidate(sched.choose(A, N))
+    # One panel height serves the forward, the transposed pack and the
+    # SDDMM; the SDDMM's LDS path covers panels of at most 8 rows, which the
+    # analytic rule gives at this density.
+    mr, cand = sched.candidate(sched.choose(A, N, rule="analytic"))
     P = ops.pack(A, mr, "f32")
     Pt = ops.pack_transpose(A, mr)
     plan = ops.make_plan(cand.cols_per_lane)
@@ -267,8 +270,8 @@ def main():
     B = torch.from_numpy(B_np).to(dev)
     As = [torch.from_numpy(a).to(dev) for a in As_np]
     # per matrix, set up once outside the timed region: panel height and
-    # register tile from the analytic plan rule on the matrix's statistics
-    # (unless given), the parallel shape from the library; buffers sized once
+    # panel height and register tile from the plan scheduler on the matrix's
+    # statistics (unless given), the parallel shape from the library; buffers sized once
     # (the sizing query synchronises; the step does not)
     packs, wss, Cs, sws, plans, mrs = [], [], [], [], [], []
     for A in As:
@@ -395,7 +398,8 @@ def main():
                                "70/80/90/95/99/99.8%, B 2304x3136 im2col(ReLU(N(0,1))); "
                                "step = pack + SpMM for all six",
                    "M": M, "K": K, "N": N,
-                   "mr": args.mr if args.mr is not None else "per matrix, analytic rule",
+                   "mr": args.mr if args.mr is not None else
+                   f"per matrix, {sched.chooser_name()} scheduler",
                    "parallelism": "single-gpu"},
         # the SpMM call (k_spmm_rows, then k_reduce_splits when K is split),
         # one launch per sparsity, timed back to back with events on the

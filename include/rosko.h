@@ -295,8 +295,7 @@ int32_t rosko_argmin_rows(const float *Y, int64_t batch, int32_t C, int32_t *out
 /* Candidate `index`: the panel height to pack with (*mr) and the plan to
  * multiply with (waves_per_tile and k_split 0: chosen by the library). */
 int32_t rosko_sched_candidate(int32_t index, int32_t *mr, rosko_plan *plan);
-/* The analytic fallback rule on host features: for N <= 128 mr 32 with 2
- * columns per lane (candidate 3); otherwise 4 columns per lane with mr 16
+/* The analytic fallback rule on host features: 4 columns per lane, mr 16
  * from density 0.08 up (candidate 1) and mr 8 below (candidate 0).  (With
  * the dense path available it takes that path from density 0.25 up; the
  * dense path is switched off in this build.) */

@@ -2,18 +2,27 @@
 parameters, which Sec. 6 leaves to future work, in place of the analytic tiling model of
 Sec. 4.2).
 
-Per matrix, a Linear(16,64)-ReLU-Linear(64,64)-ReLU-Linear(64,7) network
-predicts log(runtime / best runtime) of each of the 7 candidates
+Per matrix, a Linear(16,64)-ReLU-Linear(64,64)-ReLU-Linear(64,C) network
+predicts log(runtime / best runtime) of each candidate plan
 (rosko_sched_candidate: panel height mr, register tile, sparse or
 dense-MFMA path) from 16 packing statistics (rosko_features); the candidate
-with the smallest prediction is used, the analytic rule
-(rosko_sched_analytic) when no trained network is loaded.
+with the smallest prediction is used.  The committed network
+(sched_data/weights.json) scores the six sparse candidates (C = 6); the
+analytic rule (rosko_sched_analytic) is used when no network is loaded.
 
 Everything numerical runs in the library's HIP kernels through the C ABI:
 statistics, normalisation, forward, the MSE gradient, backward, Adam and
 the arg-min.  This module marshals arguments, holds the device buffers and
-drives the corpus sweep (measured SpMM runtimes of every candidate on the
-2000 seeded corpus problems), the training and the held-out evaluation.
+drives the timing sweeps and the training:
+
+- `measure`: measured SpMM runtimes of every sparse candidate on the
+  matrices of synth.sweep_specs() at every N of synth.SWEEP_N
+  (sched_data/measured.jsonl);
+- `fit`: full-batch Adam on the training matrices of that sweep, then the
+  slowdown t(choice) / t(fastest) of the network, the analytic rule and the
+  best fixed candidate on the held-out matrices;
+- `sweep` / `train` / `eval`: the same over the seeded random-shape corpus
+  (synth.corpus_spec).
 """
 from __future__ import annotations
 
@@ -35,6 +44,7 @@ NCAND = L.ROSKO_SCHED_CANDIDATES
 DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "sched_data")
 WEIGHTS = os.path.join(DATA_DIR, "weights.json")
 CORPUS = os.path.join(DATA_DIR, "corpus.jsonl")
+MEASURED = os.path.join(DATA_DIR, "measured.jsonl")
 N_TRAIN = 1800
 
 
@@ -164,31 +174,59 @@ class MLP:
                    np.array(d["sigma"], np.float32), device, d["F"], d["H"], d["C"])
 
 
-def load(device="cuda") -> MLP | None:
-    if not os.path.exists(WEIGHTS):
+def load(device="cuda", path: str = WEIGHTS) -> MLP | None:
+    if not os.path.exists(path):
         return None
-    with open(WEIGHTS) as f:
+    with open(path) as f:
         return MLP.from_json(json.load(f), device)
 
 
-def choose(A: torch.Tensor, N: int, net: MLP | None = None) -> int:
-    """Candidate index for A times N columns: the network's choice, the
-    analytic rule without one."""
+_NETS: dict = {}
+
+
+def default_net(device=None) -> MLP | None:
+    """The committed network on `device` (the current CUDA device if None),
+    loaded once per device; None when no weights file is present."""
+    dev = torch.device(device) if device is not None else torch.device(
+        "cuda", torch.cuda.current_device())
+    key = str(dev)
+    if key not in _NETS:
+        _NETS[key] = load(dev)
+    return _NETS[key]
+
+
+def choose(A: torch.Tensor, N: int, net: MLP | None = None, rule: str = "auto") -> int:
+    """Candidate index for A times N columns.  rule "auto": the network
+    `net`, else the committed network, else the analytic rule; rule
+    "analytic": the analytic rule."""
+    if rule not in ("auto", "analytic"):
+        raise ValueError(f"unknown rule {rule!r}")
     f = features(A, N)
-    if net is None:
+    if rule == "auto" and net is None:
+        net = default_net(A.device)
+    if rule == "analytic" or net is None:
         return analytic(f.cpu().numpy())
     return int(net.choose(f.view(1, F)).item())
 
 
+def chooser_name(device=None) -> str:
+    """Which rule choose(..., rule="auto") applies on `device`."""
+    return "mlp" if default_net(device) is not None else "analytic"
+
+
 # ---------------------------------------------------------------- corpus
-def time_candidate(A: torch.Tensor, B: torch.Tensor, index: int, reps: int = 5) -> float:
-    """Median SpMM time (microseconds) of candidate `index`, packing excluded."""
-    mr, plan = candidate(index)
-    P = ops.pack(A, mr, "f32")
+def sparse_candidates() -> list:
+    """Indices of the candidates whose plan takes the sparse path."""
+    return [c for c in range(NCAND) if candidate(c)[1].path == L.ROSKO_PATH_SPARSE]
+
+
+def time_packed(P, B: torch.Tensor, plan, reps: int = 5) -> float:
+    """Median time (microseconds) of rosko_spmm of packed P times B under
+    `plan`, one warm-up call first."""
     N = B.shape[1]
-    Cm = torch.empty((A.shape[0], N), dtype=torch.float32, device=A.device)
+    Cm = torch.empty((P.M, N), dtype=torch.float32, device=B.device)
     need = ops.spmm_workspace_size(P, N, plan)
-    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=B.device)
     ops.spmm(P, B, Cm, plan=plan, ws=ws)
     torch.cuda.synchronize()
     ts = []
@@ -200,8 +238,17 @@ def time_candidate(A: torch.Tensor, B: torch.Tensor, index: int, reps: int = 5) 
         b.record()
         b.synchronize()
         ts.append(a.elapsed_time(b) * 1e3)
-    del P, Cm, ws
+    del Cm, ws
     return float(np.median(ts))
+
+
+def time_candidate(A: torch.Tensor, B: torch.Tensor, index: int, reps: int = 5) -> float:
+    """Median SpMM time (microseconds) of candidate `index`, packing excluded."""
+    mr, plan = candidate(index)
+    P = ops.pack(A, mr, "f32")
+    t = time_packed(P, B, plan, reps)
+    del P
+    return t
 
 
 def sweep(first: int, last: int, path: str, log_every: int = 1) -> None:
@@ -219,7 +266,7 @@ def sweep(first: int, last: int, path: str, log_every: int = 1) -> None:
                 continue
             A, B, sp = synth.corpus_problem_device(i, dev)
             f = features(A, B.shape[1]).cpu().numpy().tolist()
-            times = [time_candidate(A, B, c) for c in range(NCAND)]
+            times = [time_candidate(A, B, c) for c in sparse_candidates()]
             out.write(json.dumps({"i": i, "M": sp["M"], "K": sp["K"], "N": sp["N"],
                                   "sparsity": sp["sparsity"], "kind": sp["kind"],
                                   "features": f, "times_us": times}) + "\n")
@@ -240,6 +287,56 @@ def read_corpus(path: str = CORPUS):
     return idx, X, Tm
 
 
+def measured_sweep(path: str = MEASURED, reps: int = 7) -> None:
+    """Time every sparse candidate on every matrix of synth.sweep_specs() at
+    every N of synth.SWEEP_N (packing excluded) and write one JSON line per
+    (matrix, N): the spec, the 16 statistics and the times in microseconds,
+    in candidate order.  Inputs are generated on the host, as in the parity
+    tests, and copied to the device."""
+    dev = torch.device("cuda")
+    cands = sparse_candidates()
+    # The network's output j scores candidate j: the sparse candidates are
+    # the leading indices of the table.
+    assert cands == list(range(len(cands))), cands
+    plans = [candidate(c) for c in cands]
+    Bs = {}
+    t0 = time.time()
+    with open(path, "w") as out:
+        for sp in synth.sweep_specs():
+            M, K = sp["M"], sp["K"]
+            print(f"sweep {sp['j']}: {M}x{K} s={sp['sparsity']} {sp['kind']}", flush=True)
+            A = torch.from_numpy(synth.sparse_matrix(M, K, 1.0 - sp["sparsity"], sp["seed"],
+                                                     sp["kind"])).to(dev)
+            for N in synth.SWEEP_N:
+                if (K, N) not in Bs:
+                    Bs[(K, N)] = torch.from_numpy(synth.dense_normal(K, N, 30000 + K + N)).to(dev)
+            times = {N: [] for N in synth.SWEEP_N}
+            for mr, plan in plans:
+                P = ops.pack(A, mr, "f32")
+                for N in synth.SWEEP_N:
+                    times[N].append(time_packed(P, Bs[(K, N)], plan, reps))
+                del P
+            for N in synth.SWEEP_N:
+                f = features(A, N).cpu().numpy().tolist()
+                out.write(json.dumps(dict(sp, N=N, candidates=cands, features=f,
+                                          times_us=times[N])) + "\n")
+            out.flush()
+            del A
+            best = {N: int(np.argmin(times[N])) for N in synth.SWEEP_N}
+            print(f"  best {best} ({time.time() - t0:.0f}s)", flush=True)
+
+
+def read_measured(path: str = MEASURED):
+    """Statistics X, times Tm (problems x candidates) and the held-out flag
+    of the measured sweep."""
+    rows = [json.loads(line) for line in open(path) if line.strip()]
+    rows.sort(key=lambda r: (r["j"], r["N"]))
+    X = np.array([r["features"] for r in rows], np.float32)
+    Tm = np.array([r["times_us"] for r in rows], np.float64)
+    held = np.array([bool(r["held_out"]) for r in rows])
+    return X, Tm, held
+
+
 def targets(Tm: np.ndarray) -> np.ndarray:
     """log(t / best t) per problem and candidate."""
     return np.log(Tm / Tm.min(axis=1, keepdims=True)).astype(np.float32)
@@ -251,7 +348,8 @@ def train(X: np.ndarray, Tm: np.ndarray, steps: int = 4000, lr: float = 3e-3, se
     mu = X.mean(axis=0)
     sigma = X.std(axis=0)
     sigma[sigma < 1e-6] = 1.0
-    net = MLP(flatten(synth.mlp_init_params(F, HID, NCAND, seed)), mu, sigma, device)
+    Cn = Tm.shape[1]
+    net = MLP(flatten(synth.mlp_init_params(F, HID, Cn, seed)), mu, sigma, device, F, HID, Cn)
     Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32)).to(device)
     Td = torch.from_numpy(targets(Tm)).to(device)
     mask = torch.ones_like(Td)
@@ -278,10 +376,13 @@ def evaluate(net: MLP | None, X: np.ndarray, Tm: np.ndarray) -> dict:
                       "within_5pct": float((r <= 1.05).mean()), "max": float(r.max())}
     ana = np.array([analytic(x) for x in X])
     r = Tm[np.arange(len(ana)), ana] / best
+    if net is not None:
+        out["mlp"]["vs_analytic_geomean"] = float(
+            np.exp(np.log(Tm[np.arange(len(ch)), ch] / Tm[np.arange(len(ana)), ana]).mean()))
     out["analytic"] = {"mean": float(r.mean()), "median": float(np.median(r)),
                        "geomean": float(np.exp(np.log(r).mean())),
                        "within_5pct": float((r <= 1.05).mean()), "max": float(r.max())}
-    fixed = [float(np.exp(np.log(Tm[:, c] / best).mean())) for c in range(NCAND)]
+    fixed = [float(np.exp(np.log(Tm[:, c] / best).mean())) for c in range(Tm.shape[1])]
     c = int(np.argmin(fixed))
     r = Tm[:, c] / best
     out["best_fixed"] = {"candidate": c, "mean": float(r.mean()), "geomean": fixed[c],
@@ -290,10 +391,18 @@ def evaluate(net: MLP | None, X: np.ndarray, Tm: np.ndarray) -> dict:
 
 
 def main(argv=None):
-    """python -m paper_2307_03930_amd.sched sweep FIRST LAST | train | eval"""
+    """python -m paper_2307_03930_amd.sched measure | fit | sweep FIRST LAST | train | eval"""
     import argparse
     ap = argparse.ArgumentParser(prog="python -m paper_2307_03930_amd.sched")
     sub = ap.add_subparsers(dest="cmd", required=True)
+    m = sub.add_parser("measure")
+    m.add_argument("--out", default=MEASURED)
+    m.add_argument("--reps", type=int, default=7)
+    fi = sub.add_parser("fit")
+    fi.add_argument("--data", default=MEASURED)
+    fi.add_argument("--steps", type=int, default=3000)
+    fi.add_argument("--lr", type=float, default=3e-3)
+    fi.add_argument("--out", default=WEIGHTS)
     s = sub.add_parser("sweep")
     s.add_argument("first", type=int)
     s.add_argument("last", type=int)
@@ -306,7 +415,19 @@ def main(argv=None):
     e = sub.add_parser("eval")
     e.add_argument("--corpus", default=CORPUS)
     a = ap.parse_args(argv)
-    if a.cmd == "sweep":
+    if a.cmd == "measure":
+        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+        measured_sweep(a.out, a.reps)
+    elif a.cmd == "fit":
+        X, Tm, held = read_measured(a.data)
+        net = train(X[~held], Tm[~held], steps=a.steps, lr=a.lr)
+        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+        with open(a.out, "w") as f:
+            json.dump(net.to_json(), f)
+        print(json.dumps({"n_train": int((~held).sum()), "n_held_out": int(held.sum()),
+                          "train": evaluate(net, X[~held], Tm[~held]),
+                          "held_out": evaluate(net, X[held], Tm[held])}), flush=True)
+    elif a.cmd == "sweep":
         os.makedirs(os.path.dirname(a.out), exist_ok=True)
         sweep(a.first, a.last, a.out)
     elif a.cmd == "train":

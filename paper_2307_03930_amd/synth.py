@@ -281,3 +281,34 @@ def corpus_problem_device(i: int, device) -> tuple:
     del vals, mask
     B = torch.randn((K, N), generator=tg, device=device)
     return A, B, sp
+
+
+SWEEP_N = (32, 64, 128, 256, 512, 1024, 2048, 3136)
+
+
+def sweep_specs() -> list:
+    """Matrices of the scheduler's measured sweep, each timed at every N in
+    SWEEP_N: the shapes of the benchmark workloads (256 x 2304 convolution
+    weights and their transpose, 1024 x 4096 and 4096 x 1024 from the
+    gradient workload, 4096 x 4096 from the precision workload) plus 512 x 512
+    and 2048 x 2048, over a range of sparsities and the three synthetic mask
+    kinds (and magnitude pruning at the convolution shape).  Matrix j has seed
+    20000 + j; every fourth matrix (j % 4 == 3) is held out of training."""
+    wide = (0.6, 0.7, 0.8, 0.85, 0.9, 0.95, 0.97, 0.98, 0.99, 0.995, 0.998)
+    narrow = (0.7, 0.85, 0.9, 0.95, 0.98, 0.995)
+    groups = ((256, 2304, wide, MASK_KINDS + ("magnitude",)),
+              (2304, 256, narrow, MASK_KINDS),
+              (512, 512, narrow, MASK_KINDS),
+              (1024, 4096, wide, MASK_KINDS),
+              (4096, 1024, narrow, MASK_KINDS),
+              (2048, 2048, narrow, MASK_KINDS),
+              (4096, 4096, (0.6, 0.8, 0.9, 0.95, 0.98, 0.99, 0.998), ("iid",)),
+              (4096, 4096, (0.9, 0.98), ("row_clustered", "column_banded")))
+    out = []
+    for M, K, sps, kinds in groups:
+        for sp in sps:
+            for kind in kinds:
+                j = len(out)
+                out.append({"j": j, "M": M, "K": K, "sparsity": sp, "kind": kind,
+                            "seed": 20000 + j, "held_out": j % 4 == 3})
+    return out

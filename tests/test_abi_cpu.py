@@ -245,8 +245,8 @@ def test_sched_candidates_and_analytic_rule():
     assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 1
     f[3] = 0.05                                 # 5% dense: mr 8
     assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 0
-    f[3], f[2] = 0.1, 6.0                       # N = 64: mr 32, 2 columns per lane
-    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 3
+    f[3], f[2] = 0.1, 6.0                       # N = 64: still mr 16
+    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 1
     f[3], f[2] = 0.5, 10.0                      # dense candidate not offered (path off)
     assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 1
     n = C.c_int64(0)

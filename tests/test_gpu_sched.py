@@ -42,29 +42,32 @@ def test_features_all_zero():
     np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-6)
 
 
-def _net(seed, B=37):
+def _net(seed, B=37, Cn=sched.NCAND):
     g = synth.rng(seed)
-    params = synth.mlp_init_params(sched.F, sched.HID, sched.NCAND, seed)
+    params = synth.mlp_init_params(sched.F, sched.HID, Cn, seed)
     for k in ("b1", "b2", "b3"):
         params[k] = g.normal(0, 0.1, size=params[k].shape).astype(np.float32)
     X = g.normal(0, 1, size=(B, sched.F)).astype(np.float32)
-    T = g.normal(0, 1, size=(B, sched.NCAND)).astype(np.float32)
-    mask = (g.random((B, sched.NCAND)) < 0.8).astype(np.float32)
+    T = g.normal(0, 1, size=(B, Cn)).astype(np.float32)
+    mask = (g.random((B, Cn)) < 0.8).astype(np.float32)
     net = sched.MLP(sched.flatten(params), np.zeros(sched.F, np.float32),
-                    np.ones(sched.F, np.float32))
+                    np.ones(sched.F, np.float32), "cuda", sched.F, sched.HID, Cn)
     return params, X, T, mask, net
 
 
-def test_mlp_forward_matches_oracle():
-    params, X, _, _, net = _net(31)
+# 7 outputs: every candidate; 6: the sparse candidates the committed network scores
+@pytest.mark.parametrize("Cn", [7, 6])
+def test_mlp_forward_matches_oracle(Cn):
+    params, X, _, _, net = _net(31, Cn=Cn)
     Y_ref, _ = OM.forward(params, X)
     Xd = dev(X)
     H1, H2, Y = net.forward(net.normalize(Xd))
     np.testing.assert_allclose(Y.cpu().numpy(), Y_ref, rtol=1e-5, atol=1e-5)
 
 
-def test_mlp_backward_matches_oracle():
-    params, X, T, mask, net = _net(32)
+@pytest.mark.parametrize("Cn", [7, 6])
+def test_mlp_backward_matches_oracle(Cn):
+    params, X, T, mask, net = _net(32, Cn=Cn)
     Y_ref, cache = OM.forward(params, X)
     loss_ref, dY = OM.mse_loss(Y_ref, T, mask)
     g_ref = OM.backward(params, cache, dY)
@@ -73,7 +76,7 @@ def test_mlp_backward_matches_oracle():
     H1, H2, Y = net.forward(Xn)
     loss = net.backward(Xn, H1, H2, Y, dev(T), dev(mask))
     assert loss.item() == pytest.approx(loss_ref, rel=1e-5)
-    got = sched.unflatten(net.grads.cpu().numpy())
+    got = sched.unflatten(net.grads.cpu().numpy(), Cn=Cn)
     for k in OM.PARAM_NAMES:
         scale = max(1e-6, float(np.abs(g_ref[k]).max()))
         assert float(np.abs(got[k] - g_ref[k]).max()) / scale < 1e-5, k
@@ -131,3 +134,34 @@ def test_training_reduces_loss():
     base = float(((sched.targets(Tm) - sched.targets(Tm).mean(axis=0)) ** 2).mean())
     say(f"  loss {loss:.4f} vs constant predictor {base:.4f}")
     assert loss < 0.1 * base
+
+
+def test_committed_network_reproduces_its_evaluation():
+    """The committed network, run through the library's kernels on the
+    stored statistics of the measured sweep, picks candidates whose held-out
+    slowdown is the one recorded when it was trained, and beats the analytic
+    rule and every fixed candidate there."""
+    import json
+    net = sched.default_net()
+    assert net is not None and net.C == 6
+    assert sched.chooser_name() == "mlp"
+    X, Tm, held = sched.read_measured()
+    ev = sched.evaluate(net, X[held], Tm[held])
+    with open(sched.os.path.join(sched.DATA_DIR, "fit_report.json")) as f:
+        rep = json.load(f)["held_out"]
+    say(f"held-out geomean slowdown: mlp {ev['mlp']['geomean']:.4f}, "
+        f"analytic {ev['analytic']['geomean']:.4f}, best fixed {ev['best_fixed']['geomean']:.4f}")
+    assert ev["mlp"]["geomean"] == pytest.approx(rep["mlp"]["geomean"], rel=1e-9)
+    assert ev["analytic"]["geomean"] == pytest.approx(rep["analytic"]["geomean"], rel=1e-9)
+    assert ev["mlp"]["geomean"] < ev["analytic"]["geomean"]
+    assert ev["mlp"]["geomean"] < ev["best_fixed"]["geomean"]
+
+
+def test_choose_uses_the_committed_network():
+    A = synth.sparse_matrix(1024, 4096, 0.1, 41, "iid")
+    Ad = dev(A)
+    f = sched.features(Ad, 1024).view(1, sched.F)
+    want = int(sched.default_net().choose(f).item())
+    assert sched.choose(Ad, 1024) == want
+    assert want in sched.sparse_candidates()
+    assert sched.choose(Ad, 1024, rule="analytic") == sched.analytic(f.cpu().numpy()[0])
