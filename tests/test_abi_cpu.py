@@ -195,6 +195,15 @@ def test_plan_validation_and_workspace_size():
     plan.waves_per_tile = 3
     assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan),
                                          C.byref(n)) == L.ROSKO_EUNSUPPORTED
+    # 8 and 16 waves per tile are not offered (their GPU run faulted, cause
+    # not found): every tile rejects them
+    for mr, V in ((8, 4), (16, 4), (32, 2)):
+        s2 = _packed(256, 2304, mr)
+        for H in (8, 16):
+            plan.cols_per_lane, plan.waves_per_tile = V, H
+            st = lib.rosko_spmm_workspace_size(C.byref(s2), 3136, C.byref(plan), C.byref(n))
+            assert st == L.ROSKO_EUNSUPPORTED, (mr, V, H)
+    plan.cols_per_lane, plan.waves_per_tile = 4, 4
     plan.waves_per_tile, plan.cols_per_lane = 4, 1   # 32 x 1 tile not provided
     assert lib.rosko_spmm_workspace_size(C.byref(s), 3136, C.byref(plan),
                                          C.byref(n)) == L.ROSKO_EUNSUPPORTED
