@@ -84,7 +84,8 @@ struct SpmmArgs {
   float* ws;           // k_split x M x N partial tiles (k_split > 1)
   int64_t M, K, N, ldb, ldc;
   int64_t n_chunks;    // ceil(N / (64 * cols_per_lane))
-  int64_t nrec;        // records of the whole matrix (host copy), or -1
+  int64_t rec_bound;   // records the record array holds (nrec when known, never above
+                       // its capacity): every record read stays below it
   int32_t mr, n_panels;
   int32_t beta;
   int32_t k_split;

@@ -250,7 +250,7 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
   g.beta = beta;
   const int V = plan.cols_per_lane, H = plan.waves_per_tile;
   g.k_split = std::max(1, plan.k_split);
-  g.nrec = A->nrec;
+  g.rec_bound = A->nrec >= 0 ? std::min(A->nrec, A->nrec_cap) : A->nrec_cap;
   g.n_chunks = ceil_div(N, 64 * V);
   const size_t eb = (b_dtype == ROSKO_F32) ? 4 : 2;
   // vector path: aligned V-wide rows, and B and every run of records within
@@ -259,7 +259,7 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
   g.vec = (ldb % V == 0) && (ldc % V == 0) && (N % V == 0) &&
           ((uintptr_t)B % (eb * V) == 0) && ((uintptr_t)C % (4 * V) == 0) &&
           ((uint64_t)A->K * (uint64_t)ldb * eb < (1ull << 32)) &&
-          ((uint64_t)(A->nrec + 64) * 64u < (1ull << 32));
+          ((uint64_t)(g.rec_bound + 64) * 64u < (1ull << 32));
   g.ws_vec = (N % V == 0) && ((uintptr_t)ws % (4 * V) == 0);
   if (g.k_split > 1) {
     const size_t need = spmm_ws_bytes(A, N, plan);

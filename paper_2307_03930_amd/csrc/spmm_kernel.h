@@ -254,7 +254,10 @@ k_spmm_rows(SpmmArgs g) {
   // this wavefront's run of the panel's records
   const int64_t nkb = (g.K + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
   cptr<int64_t> kblk = as_const<int64_t>(g.kblk_ptr);
-  const int64_t r0 = kblk[p * (nkb + 1)], r1 = kblk[p * (nkb + 1) + nkb];
+  // the panel's record range, clamped into [0, rec_bound] so that no content of
+  // the packed arrays can move a record address outside the record array
+  const int64_t r0 = min(max(kblk[p * (nkb + 1)], (int64_t)0), g.rec_bound);
+  const int64_t r1 = min(max(kblk[p * (nkb + 1) + nkb], r0), g.rec_bound);
   const int64_t parts = (int64_t)g.k_split * H, part = s * H + w;
   const int64_t a = r0 + (r1 - r0) * part / parts;
   const int64_t e = r0 + (r1 - r0) * (part + 1) / parts;
@@ -268,12 +271,15 @@ k_spmm_rows(SpmmArgs g) {
   if (n > 0) {
     if constexpr (VEC) {
       // the record loop in one asm block (spmm_loop.inc); buffer loads with
-      // 32-bit offsets from this run's first record and from B
+      // 32-bit offsets from this run's first record and from B.  Each buffer
+      // is sized exactly (the records from this run's first to the array's
+      // end; K rows of ldb elements), so the hardware returns zero for any
+      // load outside it instead of touching other memory
       constexpr uint32_t esz = TB == ROSKO_F32 ? 4 : 2;
-      const __amdgpu_buffer_rsrc_t rr =
-          __builtin_amdgcn_make_buffer_rsrc((void*)(g.rec + a * 16), 0, -1, 0x00020000);
-      const __amdgpu_buffer_rsrc_t rb =
-          __builtin_amdgcn_make_buffer_rsrc((void*)g.B, 0, -1, 0x00020000);
+      const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(g.rec + a * 16), 0, (int)(uint32_t)((g.rec_bound - a) * 64), 0x00020000);
+      const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)g.B, 0, (int)(uint32_t)(g.K * g.ldb * esz), 0x00020000);
       const int64_t cl = n0 < g.N - V ? n0 : g.N - V;
       RkLoop<MR, V, TB, DV>::run(acc, (uint32_t)n, rr, rb, (uint32_t)(g.ldb * esz),
                              (uint32_t)(g.K - 1), (uint32_t)(lane & 15) * 4u,
