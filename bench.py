@@ -363,19 +363,36 @@ def main():
         torch.cuda.synchronize()
         extras["copy_reference_bytes"] = int(src.numel() * 4)
         del src, dst
-        # cold-cache SpMM: overwrite 512 MB between trials
+        # per-call distributions over 50 trials (median, p10, p90): warm calls
+        # back to back, each between its own pair of events; cold calls after
+        # overwriting 512 MB (twice the last-level cache) and synchronising
+        def dist(ts):
+            return {"median": round(float(np.median(ts)), 2),
+                    "p10": round(float(np.percentile(ts, 10)), 2),
+                    "p90": round(float(np.percentile(ts, 90)), 2)}
+        trials = 50
         flush = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
         for rec, P, C, sw, plan in zip(per, packs, Cs, sws, plans):
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(trials)]
+            for a, b in ev:
+                a.record()
+                ops.spmm(P, B, C, plan=plan, ws=sw)
+                b.record()
+            torch.cuda.synchronize()
+            rec["spmm_warm_us"] = dist([a.elapsed_time(b) * 1e3 for a, b in ev])
             ts = []
-            for _ in range(10):
+            for _ in range(trials):
                 flush.fill_(1.0)
+                torch.cuda.synchronize()
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record()
                 ops.spmm(P, B, C, plan=plan, ws=sw)
                 b.record()
                 torch.cuda.synchronize()
                 ts.append(a.elapsed_time(b) * 1e3)
-            rec["spmm_cold_us_median"] = round(float(np.median(ts)), 2)
+            rec["spmm_cold_us"] = dist(ts)
+            rec["spmm_cold_us_median"] = rec["spmm_cold_us"]["median"]
         del flush
 
     hbm_achieved = tot_bytes / (tot_ms * 1e-3) / 1e9

@@ -425,9 +425,12 @@ k_pack_write(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
 // branch per row.  The wavefront then copies the ranges out with coalesced
 // stores (records as 16-byte vectors); the per-column arrays go last, so
 // the workgroup barriers (which wait for outstanding stores) find none.
+// LDS is sized per instantiation from RT, the largest panel height it takes
+// (8 with 4 columns per lane, 16 with 2, 32 or 64 with 1): a tile holds at
+// most 64 * CPL * RT values in 64 * CPL * ceil(RT / 12) records, so panels of
+// up to 32 rows need 25-29 KB per workgroup instead of 47 KB for 64 rows,
+// and more workgroups share a CU.
 constexpr int kLdsMaxRows = 64;
-constexpr int kLdsVals = kPackTile * kLdsMaxRows;                 // values per tile, at most
-constexpr int kLdsRecs = kPackTile * ((kLdsMaxRows + kRecVals - 1) / kRecVals);
 
 template <int DT>
 __device__ __forceinline__ uint32_t value_code(float x, const float* __restrict__ row_scale,
@@ -443,7 +446,7 @@ __device__ __forceinline__ uint32_t code_bits(uint32_t code) {
   return dec_fp8((uint8_t)code);
 }
 
-template <int DT, bool LOCAL, int CPL>
+template <int DT, bool LOCAL, int CPL, int RT>
 __global__ void __launch_bounds__(kPackThreads)
 k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr,
                  int64_t P, const int32_t* __restrict__ counts,
@@ -455,11 +458,15 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
                  void* __restrict__ val, const float* __restrict__ row_scale,
                  int64_t* __restrict__ kblk_ptr, int64_t nrec_cap, uint32_t* __restrict__ rec) {
   static_assert(kPackTile == 64 && kPackThreads == 64, "one wavefront per tile");
-  // rows held per column: 32 in batches (CPL 1, mr up to 64), else 32 / CPL
-  // (mr <= 32 / CPL); records per column at most 6 (CPL 1) or ceil(RMAX/12)
+  static_assert((CPL == 4 && RT == 8) || (CPL == 2 && RT == 16) ||
+                    (CPL == 1 && (RT == 32 || RT == kLdsMaxRows)),
+                "panel height bound of the instantiation");
+  // rows held per column: 32 in batches (CPL 1, mr up to RT), else 32 / CPL
+  // (mr <= 32 / CPL); records per column at most ceil(RT / 12)
   constexpr int RMAX = 32 / CPL;
-  constexpr int RPC = CPL == 1 ? (kLdsMaxRows + kRecVals - 1) / kRecVals
-                               : (RMAX + kRecVals - 1) / kRecVals;
+  constexpr int RPC = (RT + kRecVals - 1) / kRecVals;
+  constexpr int kLdsVals = kPackTile * CPL * RT;     // values per tile, at most
+  constexpr int kLdsRecs = kPackTile * CPL * RPC;    // records per tile, at most
   static_assert(CPL * RPC * kPackTile <= kLdsRecs && CPL * RMAX * kPackTile <= kLdsVals, "");
   // the tile's values / rows and records as they go out, plus one discard
   // slot per lane for the entries that are not kept
@@ -547,7 +554,7 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   for (int j = 0; j < CPL; ++j) {
     const int vbase = e[j].a, rbase = e[j].c;
     int rank = 0;
-    for (int i0 = 0; i0 < (CPL == 1 ? mr : RMAX); i0 += 32) {
+    for (int i0 = 0; i0 < (CPL == 1 ? min(mr, RT) : RMAX); i0 += 32) {
       if (CPL == 1 && i0 > 0 && c[0] > 0 && i0 < rows[0])
         load_rows32(A + r0[0] * lda + k[0], lda, i0, rows[0], xs);
 #pragma unroll
@@ -741,10 +748,18 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
   if (L.NT == 0) return ROSKO_OK;
   const bool lds = mr <= kLdsMaxRows;
   // mr > kLdsMaxRows only with one pair per lane (pack_cols_per_lane)
+  // the LDS instantiation whose panel-height bound RT covers mr (cpl 4 for
+  // mr <= 8, cpl 2 for mr <= 16, cpl 1 above; see pack_cols_per_lane)
+  const int rt = L.cpl == 4 ? 8 : L.cpl == 2 ? 16 : (mr <= 32 ? 32 : kLdsMaxRows);
+  if (lds && mr > rt) {
+    set_error("internal: panel height %d above the packing tile's %d rows", mr, rt);
+    return ROSKO_EINTERNAL;
+  }
 #define ROSKO_KWRITE(DT, LOC)                                                                  \
   (!lds ? (k_pack_write<DT, LOC>)                                                             \
-        : L.cpl == 4 ? (k_pack_write_lds<DT, LOC, 4>)                                         \
-                     : L.cpl == 2 ? (k_pack_write_lds<DT, LOC, 2>) : (k_pack_write_lds<DT, LOC, 1>))
+        : rt == 8 ? (k_pack_write_lds<DT, LOC, 4, 8>)                                         \
+        : rt == 16 ? (k_pack_write_lds<DT, LOC, 2, 16>)                                       \
+        : rt == 32 ? (k_pack_write_lds<DT, LOC, 1, 32>) : (k_pack_write_lds<DT, LOC, 1, kLdsMaxRows>))
 #define ROSKO_WRITE(DT, LOC)                                                                   \
   hipLaunchKernelGGL(ROSKO_KWRITE(DT, LOC),                                                    \
                      dim3((unsigned)L.NT), dim3(kPackThreads), 0, s,                         \
