@@ -472,7 +472,10 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   // slot per lane for the entries that are not kept
   __shared__ uint32_t s_code[kLdsVals + 64];
   __shared__ uint8_t s_loc[kLdsVals + 64];
-  __shared__ uint4 s_rec[kLdsRecs * 4 + 128];      // discard: 8 dwords per lane
+  // records, then a discard area of 512 dwords: dword 64 + lane takes a
+  // lane's dropped value, dword lane (byte 0) its dropped row, so the
+  // lanes' discards fall in distinct banks
+  __shared__ uint4 s_rec[kLdsRecs * 4 + 128];
   uint32_t* s_rw = reinterpret_cast<uint32_t*>(s_rec);
   uint8_t* s_rb = reinterpret_cast<uint8_t*>(s_rec);
   const int lane = threadIdx.x;
@@ -566,11 +569,12 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
                         (q < kLdsRecs);
         const uint32_t code = value_code<DT>(x, row_scale, r0[j] + (i < rows[j] ? i : 0));
         const int vp = kp ? vbase + rank : kLdsVals + lane;
-        const int rp = kp ? q * 16 : kLdsRecs * 16 + lane * 8;   // + 4 + 0 stays in the lane's 8
+        const int rv = kp ? q * 16 + 4 + sl : kLdsRecs * 16 + 64 + lane;   // value dword
+        const int rb = kp ? (q * 16 + 1) * 4 + sl : (kLdsRecs * 16 + lane) * 4;   // row byte
         s_code[vp] = code;
         s_loc[vp] = (uint8_t)i;
-        s_rw[rp + 4 + (kp ? sl : 0)] = code_bits<DT>(code);
-        s_rb[(rp + 1) * 4 + (kp ? sl : 0)] = (uint8_t)i;
+        s_rw[rv] = code_bits<DT>(code);
+        s_rb[rb] = (uint8_t)i;
         rank += kp ? 1 : 0;
       }
     }
