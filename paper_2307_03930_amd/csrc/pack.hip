@@ -220,34 +220,73 @@ __device__ void close_packing(Tri tot, int64_t* __restrict__ totals, int64_t P, 
 // ------------------------------------------------------------------- scan
 // One workgroup: exclusive prefix over the tile sums, totals, the overflow
 // flag, and the closing entries of the pointer arrays.
-__global__ void __launch_bounds__(1024)
+constexpr int kScanThreads = 1024;   // 16 wavefronts
+constexpr int kScanJ = 8;            // tile rows per wavefront segment
+__global__ void __launch_bounds__(kScanThreads)
 k_pack_scan(const int64_t* __restrict__ tile_sums, int64_t* __restrict__ tile_offs, int64_t NT,
             int64_t* __restrict__ totals, int64_t P, int64_t S, int64_t nnz_cap,
             int64_t ncols_cap, int64_t nrec_cap, int64_t* __restrict__ panel_nz_ptr,
             int64_t* __restrict__ panel_col_ptr, int64_t* __restrict__ col_ptr,
             int64_t* __restrict__ kblk_ptr) {
-  // each thread takes a contiguous run of tiles: their sums, one block scan
-  // of the run totals, then the run's exclusive offsets
-  const int64_t per = (NT + blockDim.x - 1) / blockDim.x;
-  const int64_t t0 = (int64_t)threadIdx.x * per;
-  const int64_t t1 = min(NT, t0 + per);
-  Tri run{0, 0, 0};
-#pragma unroll 8
-  for (int64_t t = t0; t < t1; ++t) {
-    run.a += tile_sums[3 * t];
-    run.b += tile_sums[3 * t + 1];
-    run.c += tile_sums[3 * t + 2];
-  }
-  Tri carry;
-  Tri e = block_excl_scan(run, &carry);
-#pragma unroll 8
-  for (int64_t t = t0; t < t1; ++t) {
-    tile_offs[3 * t] = e.a;
-    tile_offs[3 * t + 1] = e.b;
-    tile_offs[3 * t + 2] = e.c;
-    e.a += tile_sums[3 * t];
-    e.b += tile_sums[3 * t + 1];
-    e.c += tile_sums[3 * t + 2];
+  // Tiles in chunks of 16 x 64 x kScanJ.  Wavefront w takes the contiguous
+  // segment of 64 x kScanJ tiles at w; lane l holds tiles 64 j + l of it
+  // (coalesced loads, kept in registers), and the segment is scanned row by
+  // row with the 32-bit wave sums: a tile's sums and a segment's totals fit
+  // 32 bits (at most 512 tiles of at most 64 x 256 values).  The segment
+  // totals are joined in LDS in 64 bits, with the carry of earlier chunks.
+  __shared__ int64_t seg[3][kScanThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  constexpr int NW = kScanThreads / 64;
+  constexpr int64_t CH = (int64_t)NW * 64 * kScanJ;
+  Tri carry{0, 0, 0};
+  for (int64_t base = 0; base < NT; base += CH) {
+    const int64_t s0 = base + (int64_t)wid * 64 * kScanJ + lane;
+    int va[kScanJ], vb[kScanJ], vc[kScanJ];
+#pragma unroll
+    for (int j = 0; j < kScanJ; ++j) {
+      const int64_t t = s0 + 64 * j;
+      const bool ok = t < NT;
+      va[j] = ok ? (int)tile_sums[3 * t] : 0;
+      vb[j] = ok ? (int)tile_sums[3 * t + 1] : 0;
+      vc[j] = ok ? (int)tile_sums[3 * t + 2] : 0;
+    }
+    int ea[kScanJ], eb[kScanJ], ec[kScanJ];
+    int ra = 0, rb = 0, rc = 0;
+#pragma unroll
+    for (int j = 0; j < kScanJ; ++j) {
+      const int ia = wave_incl_sum(va[j]), ib = wave_incl_sum(vb[j]), ic = wave_incl_sum(vc[j]);
+      ea[j] = ra + ia - va[j];
+      eb[j] = rb + ib - vb[j];
+      ec[j] = rc + ic - vc[j];
+      ra += __builtin_amdgcn_readlane(ia, 63);
+      rb += __builtin_amdgcn_readlane(ib, 63);
+      rc += __builtin_amdgcn_readlane(ic, 63);
+    }
+    if (lane == 0) {
+      seg[0][wid] = ra;
+      seg[1][wid] = rb;
+      seg[2][wid] = rc;
+    }
+    __syncthreads();
+    Tri pre = carry, tot = carry;
+#pragma unroll 1
+    for (int w = 0; w < NW; ++w) {
+      if (w < wid) { pre.a += seg[0][w]; pre.b += seg[1][w]; pre.c += seg[2][w]; }
+      tot.a += seg[0][w];
+      tot.b += seg[1][w];
+      tot.c += seg[2][w];
+    }
+    __syncthreads();   // seg is rewritten by the next chunk
+#pragma unroll
+    for (int j = 0; j < kScanJ; ++j) {
+      const int64_t t = s0 + 64 * j;
+      if (t < NT) {
+        tile_offs[3 * t] = pre.a + ea[j];
+        tile_offs[3 * t + 1] = pre.b + eb[j];
+        tile_offs[3 * t + 2] = pre.c + ec[j];
+      }
+    }
+    carry = tot;
   }
   if (threadIdx.x == 0)
     close_packing(carry, totals, P, S, nnz_cap, ncols_cap, nrec_cap, panel_nz_ptr, panel_col_ptr,
@@ -724,7 +763,8 @@ int32_t launch_pack_count_scan(const float* A, int64_t R, int64_t S, int64_t lda
     launch_count(A, R, S, lda, mr, L, counts, tsum, s);
     ROSKO_LAUNCH_CHECK("k_pack_count");
   }
-  hipLaunchKernelGGL(k_pack_scan, dim3(1), dim3(1024), 0, s, tsum, toff, L.NT, totals, L.P, S,
+  hipLaunchKernelGGL(k_pack_scan, dim3(1), dim3(kScanThreads), 0, s, tsum, toff, L.NT, totals,
+                     L.P, S,
                      out ? out->nnz_cap : INT64_MAX, out ? out->ncols_cap : INT64_MAX,
                      out ? out->nrec_cap : INT64_MAX,
                      out ? out->panel_nz_ptr : nullptr, out ? out->panel_col_ptr : nullptr,

@@ -44,12 +44,14 @@ def test_pack_bit_exact(case, mr, dtype):
     assert_pack_equal(P, O.pack(A, mr, DT[dtype]))
 
 
-@pytest.mark.parametrize("M, K, mr", [(512, 512, 1), (1024, 1100, 4), (2048, 2100, 4)])
+@pytest.mark.parametrize("M, K, mr", [(512, 512, 1), (1024, 1100, 4), (2048, 2100, 4),
+                                      (2048, 2100, 1)])
 def test_pack_tile_prefix_paths(M, K, mr):
-    """Up to 4096 tiles of 64 (panel, column) pairs the write pass sums the
-    tile counts before its own tile itself; beyond, a scan pass runs first.
-    Both sides of the boundary (4096 tiles exactly, 4400, 16800) bit-exact."""
-    tiles = -(-(-(-M // mr) * K) // 64)
+    """Up to 4096 tiles of 64 x 4 (panel, column) pairs (panels of up to 8
+    rows) the write pass sums the tile counts before its own tile itself;
+    beyond, a scan pass runs first, in chunks of 8192 tiles with a carry.
+    1024, 1100, 4200 and 16800 tiles, bit-exact."""
+    tiles = -(-(-(-M // mr) * K) // 256)
     say(f"pack {M}x{K} mr={mr}: {tiles} tiles")
     A = synth.sparse_matrix(M, K, 0.02, 506 + K, "iid")
     for dtype in ("f32", "fp8"):
