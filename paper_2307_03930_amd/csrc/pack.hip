@@ -459,17 +459,23 @@ k_pack_write(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
 // Same output as k_pack_write, organised for the SIMD: each lane still reads
 // its own column (coalesced across the tile's 64 columns), but instead of
 // storing its values one by one it drops every entry into LDS -- a kept one
-// into its value slot and its record slot inside the tile's contiguous
-// output ranges, others into a per-lane discard slot -- so there is no
-// branch per row.  The wavefront then copies the ranges out with coalesced
-// stores (records as 16-byte vectors); the per-column arrays go last, so
-// the workgroup barriers (which wait for outstanding stores) find none.
+// into its value slot inside the tile's contiguous output range and its row
+// into its record's row words, others into a per-lane discard slot -- so
+// there is no branch per row.  The wavefront then copies the ranges out with
+// coalesced stores (records as 16-byte vectors, copied from their staged
+// images or assembled from the record table and the staged values); the
+// per-column arrays go last, so the workgroup barriers (which wait for
+// outstanding stores) find none.
 // LDS is sized per instantiation from RT, the largest panel height it takes
 // (8 with 4 columns per lane, 16 with 2, 32 or 64 with 1): a tile holds at
-// most 64 * CPL * RT values in 64 * CPL * ceil(RT / 12) records, so panels of
-// up to 32 rows need 25-29 KB per workgroup instead of 47 KB for 64 rows,
-// and more workgroups share a CU.
+// most 64 * CPL * RT values in 64 * CPL * ceil(RT / 12) records.  Beyond
+// kImageMaxTiles tiles the records are staged only as a 5-dword table
+// (header, row words, first value slot) and their 64-byte images built
+// during the copy-out, so panels of up to 32 rows need 15-16 KB per
+// workgroup and many workgroups share a CU; for fewer tiles the images are
+// staged whole (25-29 KB), which shortens each tile's own chain.
 constexpr int kLdsMaxRows = 64;
+constexpr int64_t kImageMaxTiles = 1024;   // about 4 tiles per CU
 
 template <int DT>
 __device__ __forceinline__ uint32_t value_code(float x, const float* __restrict__ row_scale,
@@ -485,7 +491,7 @@ __device__ __forceinline__ uint32_t code_bits(uint32_t code) {
   return dec_fp8((uint8_t)code);
 }
 
-template <int DT, bool LOCAL, int CPL, int RT>
+template <int DT, bool LOCAL, int CPL, int RT, bool TABLE>
 __global__ void __launch_bounds__(kPackThreads)
 k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr,
                  int64_t P, const int32_t* __restrict__ counts,
@@ -507,16 +513,24 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   constexpr int kLdsVals = kPackTile * CPL * RT;     // values per tile, at most
   constexpr int kLdsRecs = kPackTile * CPL * RPC;    // records per tile, at most
   static_assert(CPL * RPC * kPackTile <= kLdsRecs && CPL * RMAX * kPackTile <= kLdsVals, "");
-  // the tile's values / rows and records as they go out, plus one discard
-  // slot per lane for the entries that are not kept
+  // the tile's values / rows as they go out, plus one discard slot per lane
+  // for the entries that are not kept
   __shared__ uint32_t s_code[kLdsVals + 64];
   __shared__ uint8_t s_loc[kLdsVals + 64];
-  // records, then a discard area of 512 dwords: dword 64 + lane takes a
-  // lane's dropped value, dword lane (byte 0) its dropped row, so the
-  // lanes' discards fall in distinct banks
-  __shared__ uint4 s_rec[kLdsRecs * 4 + 128];
-  uint32_t* s_rw = reinterpret_cast<uint32_t*>(s_rec);
-  uint8_t* s_rb = reinterpret_cast<uint8_t*>(s_rec);
+  // Records, in one of two forms.  TABLE: kTab dwords per record (header,
+  // the three row words, the value slot of its first value), the 64-byte
+  // images built from these and the staged values during the copy-out, then
+  // one discard dword per lane for the rows of entries that are not kept;
+  // the LDS footprint is smallest, for grids of many tiles.  Otherwise the
+  // 64-byte images themselves, then a 512-dword discard area (dword 64 +
+  // lane a dropped value, dword lane a dropped row, distinct banks); the
+  // copy-out is one 16-byte read per store, for grids of a few tiles per CU
+  // where a tile's own chain is the time.
+  constexpr int kTab = 5;
+  constexpr int kRaw = TABLE ? (kLdsRecs * kTab + 64 + 3) / 4 : kLdsRecs * 4 + 128;
+  __shared__ uint4 s_raw[kRaw];
+  uint32_t* s_tab = reinterpret_cast<uint32_t*>(s_raw);   // TABLE: the table; else dwords
+  uint8_t* s_tb = reinterpret_cast<uint8_t*>(s_raw);
   const int lane = threadIdx.x;
   const int64_t total = P * S;
   const int64_t nkb = (S + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
@@ -587,11 +601,16 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
     run.c += t.c;
   }
   const int nv = min(run.a, kLdsVals), nrec = min(run.c, kLdsRecs);
-  // zero the tile's records (unused value slots and row bytes stay zero)
-  for (int t = lane; t < nrec * 4; t += 64) s_rec[t] = make_uint4(0u, 0u, 0u, 0u);
+  // zero the tile's records (unused row bytes and value slots stay zero)
+  if constexpr (TABLE) {
+    for (int t = lane; t < nrec * kTab; t += 64) s_tab[t] = 0u;
+  } else {
+    for (int t = lane; t < nrec * 4; t += 64) s_raw[t] = make_uint4(0u, 0u, 0u, 0u);
+  }
   __syncthreads();
   // entries -> LDS, no branch per row: a kept entry of rank r in its column
-  // goes to value slot vbase + r and to slot r % 12 of record rbase + r / 12
+  // goes to value slot vbase + r, and its row to byte r % 12 of the row words
+  // of record rbase + r / 12
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
     const int vbase = e[j].a, rbase = e[j].c;
@@ -608,20 +627,31 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
                         (q < kLdsRecs);
         const uint32_t code = value_code<DT>(x, row_scale, r0[j] + (i < rows[j] ? i : 0));
         const int vp = kp ? vbase + rank : kLdsVals + lane;
-        const int rv = kp ? q * 16 + 4 + sl : kLdsRecs * 16 + 64 + lane;   // value dword
-        const int rb = kp ? (q * 16 + 1) * 4 + sl : (kLdsRecs * 16 + lane) * 4;   // row byte
         s_code[vp] = code;
         s_loc[vp] = (uint8_t)i;
-        s_rw[rv] = code_bits<DT>(code);
-        s_rb[rb] = (uint8_t)i;
+        if constexpr (TABLE) {
+          const int rb = kp ? (q * kTab + 1) * 4 + sl : (kLdsRecs * kTab + lane) * 4;
+          s_tb[rb] = (uint8_t)i;
+        } else {
+          const int rv = kp ? q * 16 + 4 + sl : kLdsRecs * 16 + 64 + lane;   // value dword
+          const int rb = kp ? (q * 16 + 1) * 4 + sl : (kLdsRecs * 16 + lane) * 4;   // row byte
+          s_tab[rv] = code_bits<DT>(code);
+          s_tb[rb] = (uint8_t)i;
+        }
         rank += kp ? 1 : 0;
       }
     }
 #pragma unroll
     for (int jr = 0; jr < RPC; ++jr) {
-      if (jr * kRecVals < c[j] && rbase + jr < kLdsRecs)
-        s_rw[(rbase + jr) * 16] =
-            ((uint32_t)k[j] << 8) | (uint32_t)min(kRecVals, c[j] - jr * kRecVals);
+      if (jr * kRecVals < c[j] && rbase + jr < kLdsRecs) {
+        const uint32_t h = ((uint32_t)k[j] << 8) | (uint32_t)min(kRecVals, c[j] - jr * kRecVals);
+        if constexpr (TABLE) {
+          s_tab[(rbase + jr) * kTab] = h;
+          s_tab[(rbase + jr) * kTab + 4] = (uint32_t)(vbase + jr * kRecVals);
+        } else {
+          s_tab[(rbase + jr) * 16] = h;
+        }
+      }
     }
   }
   __syncthreads();
@@ -639,10 +669,28 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
       loc[z] = row;
     }
   }
+  // record images, 16 bytes per lane: part 0 is the header and row words,
+  // parts 1..3 values 4(part-1) .. 4(part-1)+3 (zero past the count)
 #pragma unroll 4
   for (int t = lane; t < nrec * 4; t += 64) {
-    const uint4 w = s_rec[t];
-    if (q0 + (t >> 2) < nrec_cap) reinterpret_cast<uint4*>(rec)[q0 * 4 + t] = w;
+    const int q = t >> 2, part = t & 3;
+    const uint32_t* tb = s_tab + q * kTab;
+    uint4 w;
+    if constexpr (!TABLE) {
+      w = s_raw[t];
+    } else if (part == 0) {
+      w = make_uint4(tb[0], tb[1], tb[2], tb[3]);
+    } else {
+      const int cnt = (int)(tb[0] & 0xffu), v0 = (int)tb[4], sl = (part - 1) * 4;
+      uint32_t x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int vs = v0 + sl + u;
+        x[u] = (sl + u < cnt && vs < kLdsVals) ? code_bits<DT>(s_code[vs]) : 0u;
+      }
+      w = make_uint4(x[0], x[1], x[2], x[3]);
+    }
+    if (q0 + q < nrec_cap) reinterpret_cast<uint4*>(rec)[q0 * 4 + t] = w;
   }
   // per-column arrays and pointers last: nothing above waits on them
 #pragma unroll
@@ -799,11 +847,17 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
     set_error("internal: panel height %d above the packing tile's %d rows", mr, rt);
     return ROSKO_EINTERNAL;
   }
-#define ROSKO_KWRITE(DT, LOC)                                                                  \
+  // record images staged whole for grids of up to kImageMaxTiles tiles (a
+  // few per CU: each tile's own chain is the time), as a table above (the
+  // smaller LDS footprint lets more workgroups share a CU)
+  const bool table = L.NT > kImageMaxTiles;
+#define ROSKO_KWRITE_T(DT, LOC, TB)                                                            \
   (!lds ? (k_pack_write<DT, LOC>)                                                             \
-        : rt == 8 ? (k_pack_write_lds<DT, LOC, 4, 8>)                                         \
-        : rt == 16 ? (k_pack_write_lds<DT, LOC, 2, 16>)                                       \
-        : rt == 32 ? (k_pack_write_lds<DT, LOC, 1, 32>) : (k_pack_write_lds<DT, LOC, 1, kLdsMaxRows>))
+        : rt == 8 ? (k_pack_write_lds<DT, LOC, 4, 8, TB>)                                     \
+        : rt == 16 ? (k_pack_write_lds<DT, LOC, 2, 16, TB>)                                   \
+        : rt == 32 ? (k_pack_write_lds<DT, LOC, 1, 32, TB>)                                   \
+                   : (k_pack_write_lds<DT, LOC, 1, kLdsMaxRows, TB>))
+#define ROSKO_KWRITE(DT, LOC) (table ? ROSKO_KWRITE_T(DT, LOC, true) : ROSKO_KWRITE_T(DT, LOC, false))
 #define ROSKO_WRITE(DT, LOC)                                                                   \
   hipLaunchKernelGGL(ROSKO_KWRITE(DT, LOC),                                                    \
                      dim3((unsigned)L.NT), dim3(kPackThreads), 0, s,                         \
@@ -822,6 +876,7 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
   }
 #undef ROSKO_WRITE
 #undef ROSKO_KWRITE
+#undef ROSKO_KWRITE_T
   ROSKO_LAUNCH_CHECK("k_pack_write");
   return ROSKO_OK;
 }
