@@ -134,7 +134,8 @@ int32_t launch_fill_zero(float* C, int64_t M, int64_t N, int64_t ldc, hipStream_
 // workgroup (added through LDS) and, while runs stay long, into k_split
 // workgroups (added by k_reduce_splits, which costs a launch and a pass over
 // k_split copies of C):
-//   H = 4 from 64 records per panel, 2 from 32, else 1;
+//   H = 4 from 64 records per panel, 2 from 32, else 1 (but 1 for
+//   128-accumulator tiles on grids of 512 tiles or more, below);
 //   k_split > 1 only when a run of the H-way cut exceeds kSplitRun records:
 //   then as many as keep runs of at least kMinRun records and the grid within
 //   what the SIMDs can hold at once (wavefronts per SIMD by the tile's VGPR
@@ -165,6 +166,20 @@ static void auto_parallelism(const rosko_packed* A, int64_t N, int V, int32_t* H
   }
   *H_out = H;
   *S_out = (int32_t)S;
+  // 128-accumulator tiles on a grid of kWideGridTiles tiles or more: a
+  // 4-wavefront workgroup's LDS reduction (two 32 KB tile images) leaves
+  // room for 2 workgroups per CU, which that grid already fills, while
+  // one-wavefront workgroups need no LDS and fit 3 per SIMD by VGPRs.  So
+  // one wavefront per tile and as many splits as fill those 3 per SIMD, at
+  // most 8 (measured: 4096 x 4096 at 90%, N = 2048: 270 us against 284 us
+  // for 4 wavefronts, 1024 tiles; with 104-416 tiles 4 wavefronts stay
+  // faster).
+  constexpr int64_t kWideGridTiles = 512;
+  if (accs >= 128 && tiles >= kWideGridTiles) {
+    int64_t S1 = std::min<int64_t>(per_panel / kMinRun, 3 * 1024 / tiles);
+    *H_out = 1;
+    *S_out = (int32_t)std::max<int64_t>(1, std::min<int64_t>(S1, 8));
+  }
 }
 
 // B rows in flight per wavefront: 4 (8 measured no faster on any tile).

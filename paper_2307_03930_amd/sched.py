@@ -252,8 +252,9 @@ def time_candidate(A: torch.Tensor, B: torch.Tensor, index: int, reps: int = 5) 
 
 
 def sweep(first: int, last: int, path: str, log_every: int = 1) -> None:
-    """Measure every candidate on corpus problems [first, last) and append
-    one JSON line per problem (features, times in microseconds) to `path`."""
+    """Measure every sparse candidate on corpus problems [first, last) and
+    append one JSON line per problem (features, times in microseconds) to
+    `path`."""
     dev = torch.device("cuda")
     done = set()
     if os.path.exists(path):

@@ -236,6 +236,25 @@ def test_auto_parallel_shape(mr, nrec, k_split):
     assert n.value == (4 * k_split * 256 * 3136 if k_split > 1 else 0)
 
 
+@pytest.mark.parametrize("mr, M, N, k_split", [
+    (32, 4096, 2048, 3),     # 128 x 8 = 1024 tiles: one wavefront per tile, 3 splits
+    (64, 4096, 2048, 3),     # 64 x 16 = 1024 tiles (2 columns per lane)
+    (32, 2048, 2048, 6),     # 512 tiles: 3 x 1024 / 512 = 6 splits
+    (32, 1024, 2048, 2),     # 256 tiles: 4 wavefronts per tile as before, 2 splits
+])
+def test_auto_parallel_wide_grid(mr, M, N, k_split):
+    """128-accumulator tiles on grids of 512 tiles or more take one
+    wavefront per tile and splits filling 3 wavefronts per SIMD (at most 8);
+    smaller grids keep the 4-wavefront rule.  4096 columns, about 4000
+    records per panel (90% sparsity at mr 32)."""
+    lib = L.lib()
+    s = _packed(M, 4096, mr)
+    s.nrec = s.n_panels * 3958
+    n = C.c_size_t(0)
+    assert lib.rosko_spmm_workspace_size(C.byref(s), N, None, C.byref(n)) == 0
+    assert n.value == 4 * k_split * M * N
+
+
 def test_sched_candidates_and_analytic_rule():
     lib = L.lib()
     mr = C.c_int32(0)
