@@ -20,7 +20,9 @@ drives the timing sweeps and the training:
   (sched_data/measured.jsonl);
 - `fit`: full-batch Adam on the training matrices of that sweep, then the
   slowdown t(choice) / t(fastest) of the network, the analytic rule and the
-  best fixed candidate on the held-out matrices;
+  best fixed candidate on the held-out matrices.  The time is repack plus
+  SpMM by default (a step that packs afresh), or the SpMM alone
+  (`--objective spmm`, a matrix packed once);
 - `sweep` / `train` / `eval`: the same over the seeded random-shape corpus
   (synth.corpus_spec).
 """
@@ -242,6 +244,26 @@ def time_packed(P, B: torch.Tensor, plan, reps: int = 5) -> float:
     return float(np.median(ts))
 
 
+def time_pack(A: torch.Tensor, P, reps: int = 5) -> float:
+    """Median time (microseconds) of repacking A into P's buffers (the
+    count, offset and write passes), one warm-up call first."""
+    M, K = A.shape
+    ws = torch.empty(max(ops.workspace_size(M, K, P.mr), 1), dtype=torch.uint8, device=A.device)
+    ops.pack_into(A, P, ws)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        ops.pack_into(A, P, ws)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) * 1e3)
+    del ws
+    return float(np.median(ts))
+
+
 def time_candidate(A: torch.Tensor, B: torch.Tensor, index: int, reps: int = 5) -> float:
     """Median SpMM time (microseconds) of candidate `index`, packing excluded."""
     mr, plan = candidate(index)
@@ -290,9 +312,10 @@ def read_corpus(path: str = CORPUS):
 
 def measured_sweep(path: str = MEASURED, reps: int = 7) -> None:
     """Time every sparse candidate on every matrix of synth.sweep_specs() at
-    every N of synth.SWEEP_N (packing excluded) and write one JSON line per
-    (matrix, N): the spec, the 16 statistics and the times in microseconds,
-    in candidate order.  Inputs are generated on the host, as in the parity
+    every N of synth.SWEEP_N and write one JSON line per (matrix, N): the
+    spec, the 16 statistics, the SpMM times and the times to repack the
+    matrix at the candidate's panel height (FP32 values), in microseconds, in
+    candidate order.  Inputs are generated on the host, as in the parity
     tests, and copied to the device."""
     dev = torch.device("cuda")
     cands = sparse_candidates()
@@ -312,28 +335,39 @@ def measured_sweep(path: str = MEASURED, reps: int = 7) -> None:
                 if (K, N) not in Bs:
                     Bs[(K, N)] = torch.from_numpy(synth.dense_normal(K, N, 30000 + K + N)).to(dev)
             times = {N: [] for N in synth.SWEEP_N}
+            packs = []
             for mr, plan in plans:
                 P = ops.pack(A, mr, "f32")
+                packs.append(time_pack(A, P, reps))
                 for N in synth.SWEEP_N:
                     times[N].append(time_packed(P, Bs[(K, N)], plan, reps))
                 del P
             for N in synth.SWEEP_N:
                 f = features(A, N).cpu().numpy().tolist()
                 out.write(json.dumps(dict(sp, N=N, candidates=cands, features=f,
-                                          times_us=times[N])) + "\n")
+                                          times_us=times[N], pack_us=packs)) + "\n")
             out.flush()
             del A
             best = {N: int(np.argmin(times[N])) for N in synth.SWEEP_N}
             print(f"  best {best} ({time.time() - t0:.0f}s)", flush=True)
 
 
-def read_measured(path: str = MEASURED):
+OBJECTIVES = ("step", "spmm")
+
+
+def read_measured(path: str = MEASURED, objective: str = "step"):
     """Statistics X, times Tm (problems x candidates) and the held-out flag
-    of the measured sweep."""
+    of the measured sweep.  objective "step": repack plus SpMM, the cost of
+    a step that packs its matrix afresh (training, and the benchmark step);
+    "spmm": the SpMM alone, for a matrix packed once and reused."""
+    if objective not in OBJECTIVES:
+        raise ValueError(f"unknown objective {objective!r}")
     rows = [json.loads(line) for line in open(path) if line.strip()]
     rows.sort(key=lambda r: (r["j"], r["N"]))
     X = np.array([r["features"] for r in rows], np.float32)
     Tm = np.array([r["times_us"] for r in rows], np.float64)
+    if objective == "step":
+        Tm = Tm + np.array([r["pack_us"] for r in rows], np.float64)
     held = np.array([bool(r["held_out"]) for r in rows])
     return X, Tm, held
 
@@ -404,6 +438,7 @@ def main(argv=None):
     fi.add_argument("--steps", type=int, default=3000)
     fi.add_argument("--lr", type=float, default=3e-3)
     fi.add_argument("--out", default=WEIGHTS)
+    fi.add_argument("--objective", choices=OBJECTIVES, default="step")
     s = sub.add_parser("sweep")
     s.add_argument("first", type=int)
     s.add_argument("last", type=int)
@@ -420,12 +455,13 @@ def main(argv=None):
         os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
         measured_sweep(a.out, a.reps)
     elif a.cmd == "fit":
-        X, Tm, held = read_measured(a.data)
+        X, Tm, held = read_measured(a.data, a.objective)
         net = train(X[~held], Tm[~held], steps=a.steps, lr=a.lr)
         os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
         with open(a.out, "w") as f:
-            json.dump(net.to_json(), f)
-        print(json.dumps({"n_train": int((~held).sum()), "n_held_out": int(held.sum()),
+            json.dump(dict(net.to_json(), objective=a.objective), f)
+        print(json.dumps({"objective": a.objective,
+                          "n_train": int((~held).sum()), "n_held_out": int(held.sum()),
                           "train": evaluate(net, X[~held], Tm[~held]),
                           "held_out": evaluate(net, X[held], Tm[held])}), flush=True)
     elif a.cmd == "sweep":

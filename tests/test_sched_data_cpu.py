@@ -1,8 +1,8 @@
 """The scheduler's committed timing data and network, checked on the host.
 
 The measured sweep (sched_data/measured.jsonl) holds, per (matrix, N), the
-statistics the GPU computed and the measured times of the six sparse
-candidates.  These tests check that it covers exactly the matrices and N of
+statistics the GPU computed and the measured SpMM and repack times of the
+six sparse candidates.  These tests check that it covers exactly the matrices and N of
 the sweep's generator, that its statistics agree with the FP64 oracle on a
 sample of matrices regenerated from their seeds, that the committed network
 has the shape of the six-candidate scorer, and that the analytic rule's
@@ -39,6 +39,7 @@ def test_measured_sweep_covers_the_generator():
             assert r[k] == sp[k], (r["j"], k)
         assert r["candidates"] == [0, 1, 2, 3, 4, 5]
         assert len(r["times_us"]) == 6 and min(r["times_us"]) > 0
+        assert len(r["pack_us"]) == 6 and min(r["pack_us"]) > 0
         assert len(r["features"]) == OF.NFEAT
         assert r["features"][2] == pytest.approx(np.log2(r["N"]), abs=1e-6)
 
@@ -64,6 +65,7 @@ def test_committed_network_shape():
     assert len(w["params"]) == Fi * H + H + H * H + H + H * Cn + Cn
     assert len(w["mu"]) == Fi and len(w["sigma"]) == Fi and min(w["sigma"]) > 0
     assert np.isfinite(np.array(w["params"])).all()
+    assert w["objective"] in sched.OBJECTIVES
 
 
 def test_report_analytic_figure_matches_library_rule():
@@ -84,6 +86,8 @@ def test_report_analytic_figure_matches_library_rule():
         idx = C.c_int32(-1)
         assert lib.rosko_sched_analytic(f.ctypes.data_as(C.c_void_p), C.byref(idx)) == 0
         t = np.array(r["times_us"])
+        if rep["objective"] == "step":
+            t = t + np.array(r["pack_us"])
         ratios.append(t[idx.value] / t.min())
     assert rep["n_held_out"] == n_held
     geo = float(np.exp(np.log(ratios).mean()))
