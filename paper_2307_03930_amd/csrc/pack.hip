@@ -725,6 +725,7 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
 // -------------------------------------------------------------- row scale
 // One wave per row: s_m = max |A[m][k]| / 448 (FP32, correctly rounded),
 // 1.0 for an all-zero row; NaN entries never win the comparison.
+template <bool VEC>
 __global__ void __launch_bounds__(256)
 k_row_scale(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
             float* __restrict__ scale) {
@@ -733,7 +734,28 @@ k_row_scale(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   if (row >= R) return;
   const float* a = A + row * lda;
   float amax = 0.0f;
-  for (int64_t k = lane; k < S; k += 64) {
+  int64_t k0 = 0;
+  if constexpr (VEC) {
+    // 16-byte rows (A aligned, lda a multiple of 4): the first 4 floor(S/4)
+    // entries as float4s, the rest one by one below.  The maximum does not
+    // depend on the order the entries are visited in.
+    const float4* a4 = reinterpret_cast<const float4*>(a);
+    const int64_t n4 = S / 4;
+#pragma unroll 4
+    for (int64_t k = lane; k < n4; k += 64) {
+      const float4 x = a4[k];
+      float v = fabsf(x.x);
+      if (v > amax) amax = v;
+      v = fabsf(x.y);
+      if (v > amax) amax = v;
+      v = fabsf(x.z);
+      if (v > amax) amax = v;
+      v = fabsf(x.w);
+      if (v > amax) amax = v;
+    }
+    k0 = n4 * 4;
+  }
+  for (int64_t k = k0 + lane; k < S; k += 64) {
     const float v = fabsf(a[k]);
     if (v > amax) amax = v;
   }
@@ -884,8 +906,13 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
 int32_t launch_row_scale(const float* A, int64_t R, int64_t S, int64_t lda, float* scale,
                          hipStream_t s) {
   if (R == 0) return ROSKO_OK;
-  hipLaunchKernelGGL(k_row_scale, dim3((unsigned)ceil_div(R, 4)), dim3(256), 0, s, A, R, S, lda,
-                     scale);
+  const bool vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
+  if (vec)
+    hipLaunchKernelGGL(k_row_scale<true>, dim3((unsigned)ceil_div(R, 4)), dim3(256), 0, s, A, R,
+                       S, lda, scale);
+  else
+    hipLaunchKernelGGL(k_row_scale<false>, dim3((unsigned)ceil_div(R, 4)), dim3(256), 0, s, A, R,
+                       S, lda, scale);
   ROSKO_LAUNCH_CHECK("k_row_scale");
   return ROSKO_OK;
 }

@@ -59,6 +59,22 @@ def test_pack_tile_prefix_paths(M, K, mr):
         assert_pack_equal(P, O.pack(A, mr, DT[dtype]))
 
 
+@pytest.mark.parametrize("M, K, ld", [(64, 130, 136), (33, 4099, 4100), (5, 7, 8)])
+def test_pack_fp8_strided_rows(M, K, ld):
+    """FP8 packing of a view whose rows are 16-byte aligned (leading dimension
+    a multiple of 4) but whose width is not: the row scales take the vector
+    loads for the first 4 floor(K/4) entries and single loads for the rest."""
+    say(f"pack fp8 {M}x{K} ld={ld}")
+    A = synth.sparse_matrix(M, K, 0.2, 640 + K, "iid")
+    pad = np.full((M, ld), 1e30, np.float32)      # padding never read as data
+    pad[:, :K] = A
+    Ad = dev(pad)[:, :K]
+    assert Ad.stride(0) == ld
+    for mr in (8, 32):
+        P = ops.pack(Ad, mr, "fp8")
+        assert_pack_equal(P, O.pack(A, mr, DT["fp8"]))
+
+
 def test_pack_special_values():
     say("pack special values")
     g = synth.rng(501)
