@@ -528,6 +528,10 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   // where a tile's own chain is the time.
   constexpr int kTab = 5;
   constexpr int kRaw = TABLE ? (kLdsRecs * kTab + 64 + 3) / 4 : kLdsRecs * 4 + 128;
+  // FP8: the matrix row of each staged value (its scale is applied after
+  // staging), so the records are always assembled from the table
+  static_assert(DT != ROSKO_FP8_E4M3 || TABLE, "FP8 packs through the record table");
+  __shared__ int32_t s_grow[DT == ROSKO_FP8_E4M3 ? kLdsVals + 64 : 1];
   __shared__ uint4 s_raw[kRaw];
   uint32_t* s_tab = reinterpret_cast<uint32_t*>(s_raw);   // TABLE: the table; else dwords
   uint8_t* s_tb = reinterpret_cast<uint8_t*>(s_raw);
@@ -625,10 +629,15 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
         const int q = rbase + (int)((unsigned)rank / kRecVals), sl = rank - (q - rbase) * kRecVals;
         const bool kp = (c[j] > 0) & (i < rows[j]) & kept(x) & (vbase + rank < kLdsVals) &
                         (q < kLdsRecs);
-        const uint32_t code = value_code<DT>(x, row_scale, r0[j] + (i < rows[j] ? i : 0));
+        // FP8: the raw value and its matrix row now, the division by the row
+        // scale and the encoding later for the kept values only
+        const uint32_t code = DT == ROSKO_FP8_E4M3
+                                  ? __float_as_uint(x)
+                                  : value_code<DT>(x, row_scale, r0[j] + (i < rows[j] ? i : 0));
         const int vp = kp ? vbase + rank : kLdsVals + lane;
         s_code[vp] = code;
         s_loc[vp] = (uint8_t)i;
+        if constexpr (DT == ROSKO_FP8_E4M3) s_grow[vp] = (int32_t)(r0[j] + i);
         if constexpr (TABLE) {
           const int rb = kp ? (q * kTab + 1) * 4 + sl : (kLdsRecs * kTab + lane) * 4;
           s_tb[rb] = (uint8_t)i;
@@ -655,6 +664,12 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
     }
   }
   __syncthreads();
+  if constexpr (DT == ROSKO_FP8_E4M3) {
+    // the kept values only: x / s_row (correctly rounded), then E4M3
+    for (int t = lane; t < nv; t += 64)
+      s_code[t] = value_code<DT>(__uint_as_float(s_code[t]), row_scale, s_grow[t]);
+    __syncthreads();
+  }
   // coalesced copies of the tile's values, rows and records
   const int64_t z0 = carry.a, q0 = carry.c;
 #pragma unroll 4
@@ -880,24 +895,26 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
         : rt == 32 ? (k_pack_write_lds<DT, LOC, 1, 32, TB>)                                   \
                    : (k_pack_write_lds<DT, LOC, 1, kLdsMaxRows, TB>))
 #define ROSKO_KWRITE(DT, LOC) (table ? ROSKO_KWRITE_T(DT, LOC, true) : ROSKO_KWRITE_T(DT, LOC, false))
-#define ROSKO_WRITE(DT, LOC)                                                                   \
-  hipLaunchKernelGGL(ROSKO_KWRITE(DT, LOC),                                                    \
+#define ROSKO_KWRITE_FP8(LOC) ROSKO_KWRITE_T(ROSKO_FP8_E4M3, LOC, true)
+#define ROSKO_WRITE(KERNEL)                                                                    \
+  hipLaunchKernelGGL(KERNEL,                                                                  \
                      dim3((unsigned)L.NT), dim3(kPackThreads), 0, s,                         \
                      A, R, S, lda, mr, L.P, counts, toff, tsum, totals, out->nnz_cap,         \
                      out->ncols_cap, out->panel_nz_ptr, out->panel_col_ptr, out->col_ind,     \
                      out->col_nnz, out->col_ptr, out->loc, out->val, out->row_scale,          \
                      out->kblk_ptr, out->nrec_cap, out->rec)
   if (local) {
-    if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_F32, true);
-    else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_BF16, true);
-    else ROSKO_WRITE(ROSKO_FP8_E4M3, true);
+    if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_F32, true));
+    else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_BF16, true));
+    else ROSKO_WRITE(ROSKO_KWRITE_FP8(true));
   } else {
-    if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_F32, false);
-    else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_BF16, false);
-    else ROSKO_WRITE(ROSKO_FP8_E4M3, false);
+    if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_F32, false));
+    else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_BF16, false));
+    else ROSKO_WRITE(ROSKO_KWRITE_FP8(false));
   }
 #undef ROSKO_WRITE
 #undef ROSKO_KWRITE
+#undef ROSKO_KWRITE_FP8
 #undef ROSKO_KWRITE_T
   ROSKO_LAUNCH_CHECK("k_pack_write");
   return ROSKO_OK;
