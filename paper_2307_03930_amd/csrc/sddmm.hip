@@ -87,7 +87,7 @@ __device__ __forceinline__ float wave_sum_f32(float x) {
 // column's values the wave forms the dot product with the LDS row and
 // reduces it across the wavefront.
 constexpr int kSdLdsRows = 8;
-constexpr int kSdLdsG = 4;       // workgroups per panel
+constexpr int kSdLdsG = 8;       // workgroups per panel
 constexpr int kSdDepth = 4;      // B rows in flight per wavefront
 
 template <int VQ>
