@@ -13,7 +13,7 @@
 namespace rosko {
 namespace {
 
-constexpr int kSdW = 4;        // waves per workgroup
+constexpr int kSdW = 8;        // waves per workgroup
 constexpr int kSdMaxV = 32;    // B values held per lane (N <= 2048 in registers)
 
 template <int VB>
@@ -87,7 +87,7 @@ __device__ __forceinline__ float wave_sum_f32(float x) {
 // column's values the wave forms the dot product with the LDS row and
 // reduces it across the wavefront.
 constexpr int kSdLdsRows = 8;
-constexpr int kSdLdsG = 8;       // workgroups per panel
+constexpr int kSdLdsG = 4;       // workgroups per panel
 constexpr int kSdDepth = 4;      // B rows in flight per wavefront
 
 template <int VQ>
