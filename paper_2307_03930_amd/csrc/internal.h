@@ -45,13 +45,29 @@ struct PackWs {
   size_t bytes;        // total
   int64_t P, NT;       // panels; tiles of 64 * cpl (panel, column) pairs
   int32_t cpl;         // pairs per lane (pack_cols_per_lane)
+  int32_t rr;          // rows per lane load (pack_rows_per_lane)
 };
 constexpr int kPackTile = 64;        // lanes per tile: one wavefront
 constexpr int kRecVals = 12;         // values per 16-dword column record
 constexpr int kPackThreads = 64;
 // (panel, column) pairs per lane: 4 for mr <= 8, 2 for mr <= 16, else 1, so
 // a lane sees about 32 entries and a tile 64 * cols pairs whatever mr is.
-inline int pack_cols_per_lane(int32_t mr) { return mr <= 8 ? 4 : (mr <= 16 ? 2 : 1); }
+// (panel, column) pairs per lane in a packing tile: one for panels of more
+// than 16 rows, and for panels of up to 16 rows while the grid stays within
+// kOnePairMaxTiles tiles (more, shorter tiles spread a small matrix over more
+// SIMDs); otherwise 4 (up to 8 rows) or 2 (up to 16), about 32 entries a lane.
+constexpr int64_t kOnePairMaxTiles = 1280;
+inline int pack_cols_per_lane(int32_t mr, int64_t pairs) {
+  if (mr > 16 || pairs <= kOnePairMaxTiles * 64) return 1;
+  return mr <= 8 ? 4 : 2;
+}
+// Rows a lane loads per pair: the panel height bound of the tile shape
+// (8 or 16 with one pair per lane for small panels), 32 per batch above.
+inline int pack_rows_per_lane(int32_t mr, int cpl) {
+  if (cpl == 4 || mr <= 8) return 8;
+  if (cpl == 2 || mr <= 16) return 16;
+  return 32;
+}
 // Up to this many tiles the write pass adds up the tile sums before its own
 // tile itself (no separate scan launch); beyond, a one-workgroup scan runs.
 constexpr int64_t kLocalPrefixTiles = 4096;

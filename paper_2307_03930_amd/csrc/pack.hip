@@ -150,12 +150,15 @@ __device__ __forceinline__ uint32_t dec_fp8(uint8_t c) {
 // columns, so the row loads are coalesced).  CPL = 1: all rows of the column
 // in batches of 32; CPL > 1 (mr <= 32 / CPL): the column's rows in one batch
 // of 32 / CPL loads.
-template <int CPL>
+template <int CPL, int RR>
 __global__ void __launch_bounds__(kPackThreads)
 k_pack_count(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr,
              int64_t P, int32_t* __restrict__ counts, int64_t* __restrict__ tile_sums) {
   static_assert(kPackTile == 64 && kPackThreads == 64, "one wavefront per tile");
-  constexpr int RMAX = 32 / CPL;
+  static_assert(RR == 32 ? CPL == 1 : CPL * RR <= 32, "rows per lane load");
+  // rows per pair: RR (the panel height bound) in one load round, or for
+  // RR = 32 (one pair per lane, panels above 16 rows) batches of 32
+  constexpr int RMAX = RR;
   const int64_t total = P * S;
   const int64_t fb = (int64_t)blockIdx.x * (64 * CPL) + threadIdx.x;
   Tri32 sum{0, 0, 0};
@@ -168,7 +171,7 @@ k_pack_count(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
       const int64_t r0 = p * mr;
       const int rows = (int)((R - r0) < mr ? (R - r0) : mr);
       const float* col = A + r0 * lda + k;
-      if constexpr (CPL == 1) {
+      if constexpr (RR == 32) {
         for (int i0 = 0; i0 < rows; i0 += 32) {
           float x[32];
           load_rows32(col, lda, i0, rows, x);
@@ -504,11 +507,12 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
                  int64_t* __restrict__ kblk_ptr, int64_t nrec_cap, uint32_t* __restrict__ rec) {
   static_assert(kPackTile == 64 && kPackThreads == 64, "one wavefront per tile");
   static_assert((CPL == 4 && RT == 8) || (CPL == 2 && RT == 16) ||
-                    (CPL == 1 && (RT == 32 || RT == kLdsMaxRows)),
+                    (CPL == 1 && (RT == 8 || RT == 16 || RT == 32 || RT == kLdsMaxRows)),
                 "panel height bound of the instantiation");
-  // rows held per column: 32 in batches (CPL 1, mr up to RT), else 32 / CPL
-  // (mr <= 32 / CPL); records per column at most ceil(RT / 12)
-  constexpr int RMAX = 32 / CPL;
+  // rows held per column: RT in one load round (RT <= 16, or RT = 32 / CPL),
+  // else 32 in batches (one pair per lane, mr up to RT); records per column
+  // at most ceil(RT / 12)
+  constexpr int RMAX = RT < 32 ? RT : 32;
   constexpr int RPC = (RT + kRecVals - 1) / kRecVals;
   constexpr int kLdsVals = kPackTile * CPL * RT;     // values per tile, at most
   constexpr int kLdsRecs = kPackTile * CPL * RPC;    // records per tile, at most
@@ -554,7 +558,7 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
     rows[j] = valid[j] ? (int)((R - r0[j]) < mr ? (R - r0[j]) : mr) : 0;
   }
   // rows, with the counts: one round trip (clamped reads of valid memory)
-  if constexpr (CPL == 1) {
+  if constexpr (RT >= 32) {
     if (rows[0] > 0) load_rows32(A + r0[0] * lda + k[0], lda, 0, rows[0], xs);
   } else {
 #pragma unroll
@@ -619,13 +623,13 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   for (int j = 0; j < CPL; ++j) {
     const int vbase = e[j].a, rbase = e[j].c;
     int rank = 0;
-    for (int i0 = 0; i0 < (CPL == 1 ? min(mr, RT) : RMAX); i0 += 32) {
-      if (CPL == 1 && i0 > 0 && c[0] > 0 && i0 < rows[0])
+    for (int i0 = 0; i0 < (RT >= 32 ? min(mr, RT) : RMAX); i0 += 32) {
+      if (RT >= 32 && i0 > 0 && c[0] > 0 && i0 < rows[0])
         load_rows32(A + r0[0] * lda + k[0], lda, i0, rows[0], xs);
 #pragma unroll
-      for (int jj = 0; jj < (CPL == 1 ? 32 : RMAX); ++jj) {
+      for (int jj = 0; jj < RMAX; ++jj) {
         const int i = i0 + jj;
-        const float x = xs[(CPL == 1 ? 0 : j * RMAX) + jj];
+        const float x = xs[j * RMAX + jj];
         const int q = rbase + (int)((unsigned)rank / kRecVals), sl = rank - (q - rbase) * kRecVals;
         const bool kp = (c[j] > 0) & (i < rows[j]) & kept(x) & (vbase + rank < kLdsVals) &
                         (q < kLdsRecs);
@@ -809,17 +813,27 @@ static void launch_count(const float* A, int64_t R, int64_t S, int64_t lda, int3
                          const PackWs& L, int32_t* counts, int64_t* tsum, hipStream_t s) {
   const dim3 grid((unsigned)L.NT), block(kPackThreads);
   if (L.cpl == 4)
-    hipLaunchKernelGGL(k_pack_count<4>, grid, block, 0, s, A, R, S, lda, mr, L.P, counts, tsum);
+    hipLaunchKernelGGL((k_pack_count<4, 8>), grid, block, 0, s, A, R, S, lda, mr, L.P, counts,
+                       tsum);
   else if (L.cpl == 2)
-    hipLaunchKernelGGL(k_pack_count<2>, grid, block, 0, s, A, R, S, lda, mr, L.P, counts, tsum);
+    hipLaunchKernelGGL((k_pack_count<2, 16>), grid, block, 0, s, A, R, S, lda, mr, L.P, counts,
+                       tsum);
+  else if (L.rr == 8)
+    hipLaunchKernelGGL((k_pack_count<1, 8>), grid, block, 0, s, A, R, S, lda, mr, L.P, counts,
+                       tsum);
+  else if (L.rr == 16)
+    hipLaunchKernelGGL((k_pack_count<1, 16>), grid, block, 0, s, A, R, S, lda, mr, L.P, counts,
+                       tsum);
   else
-    hipLaunchKernelGGL(k_pack_count<1>, grid, block, 0, s, A, R, S, lda, mr, L.P, counts, tsum);
+    hipLaunchKernelGGL((k_pack_count<1, 32>), grid, block, 0, s, A, R, S, lda, mr, L.P, counts,
+                       tsum);
 }
 
 PackWs pack_ws_layout(int64_t R, int64_t S, int32_t mr, bool transpose) {
   PackWs L{};
   L.P = ceil_div(R, mr);
-  L.cpl = pack_cols_per_lane(mr);
+  L.cpl = pack_cols_per_lane(mr, L.P * S);
+  L.rr = pack_rows_per_lane(mr, L.cpl);
   L.NT = ceil_div(L.P * S, (int64_t)kPackTile * L.cpl);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = (size_t)round_up(off + bytes, 256); return o; };
@@ -877,9 +891,13 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
   if (L.NT == 0) return ROSKO_OK;
   const bool lds = mr <= kLdsMaxRows;
   // mr > kLdsMaxRows only with one pair per lane (pack_cols_per_lane)
-  // the LDS instantiation whose panel-height bound RT covers mr (cpl 4 for
-  // mr <= 8, cpl 2 for mr <= 16, cpl 1 above; see pack_cols_per_lane)
-  const int rt = L.cpl == 4 ? 8 : L.cpl == 2 ? 16 : (mr <= 32 ? 32 : kLdsMaxRows);
+  // the LDS instantiation whose panel-height bound RT covers mr: 8 with 4
+  // pairs per lane, 16 with 2, and with one pair per lane the rows per lane
+  // load (8 or 16 for small panels) or 32 / 64 (see pack_cols_per_lane)
+  const int rt = L.cpl == 4   ? 8
+                 : L.cpl == 2 ? 16
+                 : L.rr < 32  ? L.rr
+                              : (mr <= 32 ? 32 : kLdsMaxRows);
   if (lds && mr > rt) {
     set_error("internal: panel height %d above the packing tile's %d rows", mr, rt);
     return ROSKO_EINTERNAL;
@@ -890,8 +908,10 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
   const bool table = L.NT > kImageMaxTiles;
 #define ROSKO_KWRITE_T(DT, LOC, TB)                                                            \
   (!lds ? (k_pack_write<DT, LOC>)                                                             \
-        : rt == 8 ? (k_pack_write_lds<DT, LOC, 4, 8, TB>)                                     \
-        : rt == 16 ? (k_pack_write_lds<DT, LOC, 2, 16, TB>)                                   \
+        : L.cpl == 4 ? (k_pack_write_lds<DT, LOC, 4, 8, TB>)                                  \
+        : L.cpl == 2 ? (k_pack_write_lds<DT, LOC, 2, 16, TB>)                                 \
+        : rt == 8 ? (k_pack_write_lds<DT, LOC, 1, 8, TB>)                                     \
+        : rt == 16 ? (k_pack_write_lds<DT, LOC, 1, 16, TB>)                                   \
         : rt == 32 ? (k_pack_write_lds<DT, LOC, 1, 32, TB>)                                   \
                    : (k_pack_write_lds<DT, LOC, 1, kLdsMaxRows, TB>))
 #define ROSKO_KWRITE(DT, LOC) (table ? ROSKO_KWRITE_T(DT, LOC, true) : ROSKO_KWRITE_T(DT, LOC, false))

@@ -57,9 +57,17 @@ def test_workspace_size_closed_form():
     P2 = (2304 + 31) // 32
     NT2 = (P2 * 256 + 63) // 64
     assert lib.rosko_pack_workspace_size(256, 2304, 8, 0, C.byref(n)) == 0
-    P8 = 32                                   # mr 8: four pairs per lane
-    NT8 = (P8 * 2304 + 255) // 256
+    P8 = 32                     # mr 8, 73728 pairs: within 1280 one-pair tiles
+    NT8 = (P8 * 2304 + 63) // 64
     assert n.value == r(4 * P8 * 2304) + 2 * r(24 * NT8) + r(32)
+    assert lib.rosko_pack_workspace_size(1024, 4096, 8, 0, C.byref(n)) == 0
+    P8 = 128                    # mr 8, 524288 pairs: four pairs per lane
+    NT8 = (P8 * 4096 + 255) // 256
+    assert n.value == r(4 * P8 * 4096) + 2 * r(24 * NT8) + r(32)
+    assert lib.rosko_pack_workspace_size(1024, 4096, 16, 0, C.byref(n)) == 0
+    P16 = 64                    # mr 16, 262144 pairs: two pairs per lane
+    NT16 = (P16 * 4096 + 127) // 128
+    assert n.value == r(4 * P16 * 4096) + 2 * r(24 * NT16) + r(32)
     assert lib.rosko_pack_workspace_size(256, 2304, 32, 1, C.byref(n)) == 0
     assert n.value == r(4 * P2 * 256) + 2 * r(24 * NT2) + r(32) + r(4 * 256 * 2304)
 
