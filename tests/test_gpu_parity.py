@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle as O
-from paper_2307_03930_amd import ops, synth
+from paper_2307_03930_amd import ops, sched, synth
 from tests.gpu_helpers import DT, assert_pack_equal, dev, err, packed_to_np, say
 
 pytestmark = pytest.mark.gpu
@@ -324,6 +324,41 @@ def test_spmm_cnn_layer_sampled(s):
         assert e <= TOL_F32
 
 
+@pytest.mark.parametrize("s", synth.CNN_SPARSITIES)
+def test_timed_step_configuration(s):
+    """The step as the benchmark times it on the 256 x 2304 x 3136 layer: the
+    plan scheduler's candidate for the matrix, a re-pack into the buffers of
+    a first pack (bit-exact with Alg. 1 both times), then the SpMM with that
+    candidate's columns per lane and the library's parallel shape.  24
+    sampled rows of C against the oracle; a second step gives the same bits."""
+    pr = synth.cnn_layer(s)
+    Ad, Bd = dev(pr.A), dev(pr.B)
+    M, K = pr.A.shape
+    N = pr.B.shape[1]
+    mr, cand = sched.candidate(sched.choose(Ad, N))
+    plan = ops.make_plan(cand.cols_per_lane)
+    say(f"timed step s={s}: mr={mr} cols_per_lane={cand.cols_per_lane}")
+    ref_pack = O.pack(pr.A, mr, DT["f32"])
+    P = ops.pack(Ad, mr, "f32")
+    assert_pack_equal(P, ref_pack)
+    ws = torch.empty(max(ops.workspace_size(M, K, mr), 1), dtype=torch.uint8, device=Ad.device)
+    sw = torch.empty(max(ops.spmm_workspace_size(P, N, plan), 1), dtype=torch.uint8,
+                     device=Ad.device)
+    C = torch.empty((M, N), dtype=torch.float32, device=Ad.device)
+    outs = []
+    for _ in range(2):
+        ops.pack_into(Ad, P, ws)
+        ops.spmm(P, Bd, C, plan=plan, ws=sw)
+        torch.cuda.synchronize()
+        assert_pack_equal(P, ref_pack)
+        outs.append(C.cpu().numpy().copy())
+    rows = np.sort(synth.rng(611).choice(M, 24, replace=False))
+    e = err(outs[0][rows], O.spmm(pr.A[rows], pr.B), O.abs_product(pr.A[rows], pr.B))
+    say(f"  err {e:.3e}")
+    assert e <= TOL_F32
+    assert np.array_equal(outs[0], outs[1])
+
+
 # --------------------------------------------------------------------------
 # precision forms
 # --------------------------------------------------------------------------
@@ -353,20 +388,26 @@ def test_spmm_quantised_values(dtype, b_bf16):
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 def test_spmm_precision_form_sampled(s, dtype):
     """4096 x 4096 at 90/98% times 4096 x 2048 BF16 activations, full size on
-    the GPU; 16 sampled rows checked against the oracle."""
+    the GPU; 16 sampled rows checked against the oracle, with mr 32 and the
+    library's plan, then with the plan scheduler's candidate (its panel
+    height and columns per lane) as the benchmark runs it."""
     say(f"spmm precision form s={s} values={dtype}")
     pr = synth.precision_problem(s)
     rows = np.sort(synth.rng(613).choice(4096, 16, replace=False))
     Arows = pr.A[rows]
     c_src = O.spmm(Arows, pr.B)
     scale = O.abs_product(Arows, pr.B)
-    P = ops.pack(dev(pr.A), 32, dtype)
+    Ad = dev(pr.A)
     Bd = dev(pr.B).to(torch.bfloat16) if dtype != "f32" else dev(pr.B)
-    C = ops.spmm(P, Bd).cpu().numpy()[rows]
-    e = err(C, c_src, scale)
-    say(f"  err vs FP32 source {e:.3e}")
+    mr_s, cand = sched.candidate(sched.choose(Ad, pr.B.shape[1]))
     tol = {"f32": TOL_F32, "bf16": TOL_BF16, "fp8": TOL_FP8}[dtype]
-    assert e <= tol
+    for mr, plan in ((32, None), (mr_s, ops.make_plan(cand.cols_per_lane))):
+        P = ops.pack(Ad, mr, dtype)
+        C = ops.spmm(P, Bd, plan=plan).cpu().numpy()[rows]
+        e = err(C, c_src, scale)
+        say(f"  mr {mr} plan {'auto' if plan is None else cand.cols_per_lane}: "
+            f"err vs FP32 source {e:.3e}")
+        assert e <= tol
 
 
 # --------------------------------------------------------------------------
