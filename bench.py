@@ -32,7 +32,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # FP32 FMA on the vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
 # Packed-FP32 forms (which would double it to the published 157.3 TFLOP/s)
-# are switched off for all device code of this build.
+# are switched off for all of the library's device code.
 VALU_FP32_PEAK_TFS = 78.6
 VALU_FP32_PUBLISHED_TFS = 157.3
 SPMM_SOURCES = ("spmm_kernel.h", "spmm_loop.inc", "spmm.hip", "spmm_bf32.hip", "internal.h")
@@ -247,7 +247,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
 

@@ -298,7 +298,7 @@ int32_t rosko_sched_candidate(int32_t index, int32_t *mr, rosko_plan *plan);
 /* The analytic fallback rule on host features: 4 columns per lane, mr 16
  * from density 0.08 up (candidate 1) and mr 8 below (candidate 0).  (With
  * the dense path available it takes that path from density 0.25 up; the
- * dense path is switched off in this build.) */
+ * dense path is switched off in this version.) */
 int32_t rosko_sched_analytic(const float *features_host, int32_t *index);
 
 /* ---- errors ----------------------------------------------------------- */

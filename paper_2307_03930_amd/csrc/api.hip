@@ -290,7 +290,7 @@ int32_t rosko_spmm(const rosko_packed* A, const void* B, int32_t b_dtype, int64_
     // Switched off: two GPU runs that called this path back to back at
     // untested shapes faulted the GPU and the cause has not been found.
     // The kernels stay in dense.hip; launch_spmm_dense is not reached.
-    set_error("the dense-MFMA path is disabled in this build");
+    set_error("the dense-MFMA path is disabled in this version of the library");
     return ROSKO_EUNSUPPORTED;
   }
   return launch_spmm_sparse(A, B, b_dtype, N, ldb, C, ldc, beta, p, static_cast<float*>(ws),
