@@ -390,7 +390,8 @@ def test_spmm_precision_form_sampled(s, dtype):
     """4096 x 4096 at 90/98% times 4096 x 2048 BF16 activations, full size on
     the GPU; 16 sampled rows checked against the oracle, with mr 32 and the
     library's plan, then with the plan scheduler's candidate (its panel
-    height and columns per lane) as the benchmark runs it."""
+    height and columns per lane) as the benchmark runs it; the re-pack into
+    the candidate's buffers is compared with Alg. 1 bit for bit."""
     say(f"spmm precision form s={s} values={dtype}")
     pr = synth.precision_problem(s)
     rows = np.sort(synth.rng(613).choice(4096, 16, replace=False))
@@ -408,6 +409,12 @@ def test_spmm_precision_form_sampled(s, dtype):
         say(f"  mr {mr} plan {'auto' if plan is None else cand.cols_per_lane}: "
             f"err vs FP32 source {e:.3e}")
         assert e <= tol
+    # the re-pack into those buffers (what the benchmark times) is Alg. 1 bit for bit
+    ws = torch.empty(max(ops.workspace_size(*pr.A.shape, mr_s), 1), dtype=torch.uint8,
+                     device=Ad.device)
+    ops.pack_into(Ad, P, ws)
+    torch.cuda.synchronize()
+    assert_pack_equal(P, O.pack(pr.A, mr_s, DT[dtype]))
 
 
 # --------------------------------------------------------------------------
