@@ -227,14 +227,29 @@ int32_t rosko_spmm(const rosko_packed *A, const void *B, int32_t b_dtype, int64_
  * kept entries of A, written as one FP32 value per kept entry in A's packed
  * order (an SDDMM; pruned entries get no gradient).  dC (device, A->M x N,
  * lddc), B (device FP32, A->K x N, ldb).  dB (device, A->K x N, lddb) or
- * dA_val (device, A's nnz floats) may be NULL to skip that gradient; At may
- * be NULL when dB is.  ws: device workspace of the size
+ * dA_val (device, dA_cap floats, at least A's nnz) may be NULL to skip that
+ * gradient; no entry at or beyond dA_cap (or A->nnz_cap) is written, and
+ * every index read from A's packed arrays is clamped into A's capacities,
+ * so a pack that overflowed its buffers cannot move an access outside them.
+ * At may be NULL when dB is.  ws: device workspace of the size
  * rosko_spmm_backward_workspace_size reports.  Asynchronous. */
 int32_t rosko_spmm_backward_workspace_size(const rosko_packed *At, int64_t N, size_t *bytes);
 int32_t rosko_spmm_backward(const rosko_packed *A, const rosko_packed *At, const float *B,
                             int64_t ldb, const float *dC, int64_t lddc, int64_t N, float *dB,
-                            int64_t lddb, float *dA_val, void *ws, size_t ws_bytes,
-                            void *stream);
+                            int64_t lddb, float *dA_val, int64_t dA_cap, void *ws,
+                            size_t ws_bytes, void *stream);
+
+/* Scatters one FP32 value per stored entry of A, given in A's packed order
+ * (as rosko_spmm_backward writes dA), into the dense M x K array out (device,
+ * row-major, ldo >= K): out[m][k] = vals[z] for the entry z at (m, k).  Other
+ * entries of out are not written (zero-fill them first for a dense
+ * gradient).  Only the first min(n_vals, A->nnz_cap) entries are read;
+ * indices are clamped as in rosko_spmm_backward.  This is the inverse of
+ * packing's value placement (Alg. 1), used to hand the masked weight
+ * gradient of the training decomposition (Sec. 5.4) back in the weight's own
+ * dense layout.  Asynchronous. */
+int32_t rosko_scatter_dense(const rosko_packed *A, const float *vals, int64_t n_vals,
+                            float *out, int64_t ldo, void *stream);
 
 /* ---- learned plan selection (in place of Sec. 4.2's analytic tiling; the
  * auto-tuning of the exposed parameters that Sec. 6 leaves open) ----------
@@ -304,7 +319,7 @@ int32_t rosko_sched_analytic(const float *features_host, int32_t *index);
 /* ---- errors ----------------------------------------------------------- */
 const char *rosko_status_str(int32_t status);
 const char *rosko_last_error(void);   /* per host thread; "" if none */
-int32_t rosko_abi_version(void);      /* 4 */
+int32_t rosko_abi_version(void);      /* 5 */
 
 #ifdef __cplusplus
 }

@@ -65,6 +65,13 @@ def lib():
         L.ro_grad_dA_packed.argtypes = [i64, i32, p, p, p, p, p, p, i64, p, i64, i64, p]
         L.ro_grad_dA_packed.restype = None
         L.ro_max_threads.argtypes = []; L.ro_max_threads.restype = i32
+        L.ro_abs_product_par.argtypes = [p, i64, i64, i64, p, i64, i64, p, i32]
+        L.ro_abs_product_par.restype = None
+        L.ro_grad_dB_par.argtypes = [p, i64, i64, i64, p, i64, i64, p, i32]
+        L.ro_grad_dB_par.restype = None
+        L.ro_grad_dA_packed_par.argtypes = [i64, i32, p, p, p, p, p, p, i64, p, i64, i64, p,
+                                            i32]
+        L.ro_grad_dA_packed_par.restype = None
         L.ro_records.argtypes = [i64, i64, i32, i32, i32, p, p, p, p, p, p, p, p]
         L.ro_records.restype = i64
         _lib = L
@@ -210,12 +217,15 @@ def dense_mm(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     return out
 
 
-def abs_product(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+def abs_product(A: np.ndarray, B: np.ndarray, threads: int = 1) -> np.ndarray:
     A, B = _f32(A), _f32(B)
     M, K = A.shape
     _, N = B.shape
     out = np.empty((M, N), np.float64)
-    lib().ro_abs_product(_ptr(A), M, K, K, _ptr(B), N, N, _ptr(out))
+    if threads > 1:
+        lib().ro_abs_product_par(_ptr(A), M, K, K, _ptr(B), N, N, _ptr(out), threads)
+    else:
+        lib().ro_abs_product(_ptr(A), M, K, K, _ptr(B), N, N, _ptr(out))
     return out
 
 
@@ -233,22 +243,28 @@ def spmm_packed(pk: Packed, B: np.ndarray, C_in: np.ndarray | None = None) -> np
 
 
 # ----------------------------------------------------------------- backward
-def grad_dB(A: np.ndarray, dC: np.ndarray) -> np.ndarray:
+def grad_dB(A: np.ndarray, dC: np.ndarray, threads: int = 1) -> np.ndarray:
     A, dC = _f32(A), _f32(dC)
     M, K = A.shape
     N = dC.shape[1]
     out = np.empty((K, N), np.float64)
-    lib().ro_grad_dB(_ptr(A), M, K, K, _ptr(dC), N, N, _ptr(out))
+    if threads > 1:
+        lib().ro_grad_dB_par(_ptr(A), M, K, K, _ptr(dC), N, N, _ptr(out), threads)
+    else:
+        lib().ro_grad_dB(_ptr(A), M, K, K, _ptr(dC), N, N, _ptr(out))
     return out
 
 
-def grad_dA_packed(pk: Packed, dC: np.ndarray, B: np.ndarray) -> np.ndarray:
+def grad_dA_packed(pk: Packed, dC: np.ndarray, B: np.ndarray, threads: int = 1) -> np.ndarray:
     dC, B = _f32(dC), _f32(B)
     N = B.shape[1]
     out = np.empty(max(pk.nnz, 1), np.float64)
-    lib().ro_grad_dA_packed(pk.M, pk.mr, _ptr(pk.panel_col_ptr), _ptr(pk.col_ind),
-                            _ptr(pk.col_nnz), _ptr(pk.col_ptr), _ptr(pk.loc), _ptr(dC), N,
-                            _ptr(B), N, N, _ptr(out))
+    args = (pk.M, pk.mr, _ptr(pk.panel_col_ptr), _ptr(pk.col_ind), _ptr(pk.col_nnz),
+            _ptr(pk.col_ptr), _ptr(pk.loc), _ptr(dC), N, _ptr(B), N, N, _ptr(out))
+    if threads > 1:
+        lib().ro_grad_dA_packed_par(*args, threads)
+    else:
+        lib().ro_grad_dA_packed(*args)
     return out[:pk.nnz]
 
 

@@ -421,6 +421,62 @@ void ro_spmm_csr_par(const float *A, int64_t M, int64_t K, int64_t lda,
   (void)threads;
 }
 
+/* Row-parallel variant of ro_abs_product (same per-row arithmetic). */
+void ro_abs_product_par(const float *A, int64_t M, int64_t K, int64_t lda,
+                        const float *B, int64_t N, int64_t ldb, double *C, int32_t threads) {
+#ifdef _OPENMP
+  #pragma omp parallel for num_threads(threads) schedule(dynamic, 4)
+#endif
+  for (int64_t m = 0; m < M; ++m)
+    ro_abs_product(A + m * lda, 1, K, lda, B, N, ldb, C + m * N);
+  (void)threads;
+}
+
+/* Parallel variant of ro_grad_dB: each thread owns whole rows k of dB, each
+ * computed exactly as in ro_grad_dB (ascending m). */
+void ro_grad_dB_par(const float *A, int64_t M, int64_t K, int64_t lda,
+                    const float *dC, int64_t N, int64_t lddc, double *dB, int32_t threads) {
+#ifdef _OPENMP
+  #pragma omp parallel for num_threads(threads) schedule(dynamic, 16)
+#endif
+  for (int64_t k = 0; k < K; ++k) {
+    double *row = dB + k * N;
+    for (int64_t n = 0; n < N; ++n) row[n] = 0.0;
+    for (int64_t m = 0; m < M; ++m) {
+      float x = A[m * lda + k];
+      if (!ro_is_nonzero(x)) continue;
+      double a = (double)x;
+      const float *g = dC + m * lddc;
+      for (int64_t n = 0; n < N; ++n) row[n] += a * (double)g[n];
+    }
+  }
+  (void)threads;
+}
+
+/* Panel-parallel variant of ro_grad_dA_packed (same per-entry sums). */
+void ro_grad_dA_packed_par(int64_t M, int32_t mr, const int64_t *panel_col_ptr,
+                           const int32_t *col_ind, const int32_t *col_nnz, const int64_t *col_ptr,
+                           const uint8_t *loc, const float *dC, int64_t lddc,
+                           const float *B, int64_t ldb, int64_t N, double *dA, int32_t threads) {
+  int64_t P = (M + mr - 1) / mr;
+#ifdef _OPENMP
+  #pragma omp parallel for num_threads(threads) schedule(dynamic, 1)
+#endif
+  for (int64_t p = 0; p < P; ++p) {
+    for (int64_t c = panel_col_ptr[p]; c < panel_col_ptr[p + 1]; ++c) {
+      const float *b = B + (int64_t)col_ind[c] * ldb;
+      for (int64_t j = 0; j < col_nnz[c]; ++j) {
+        int64_t z = col_ptr[c] + j;
+        const float *g = dC + (p * mr + loc[z]) * lddc;
+        double acc = 0.0;
+        for (int64_t n = 0; n < N; ++n) acc += (double)g[n] * (double)b[n];
+        dA[z] = acc;
+      }
+    }
+  }
+  (void)threads;
+}
+
 int32_t ro_max_threads(void) {
 #ifdef _OPENMP
   return (int32_t)omp_get_max_threads();

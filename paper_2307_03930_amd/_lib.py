@@ -86,7 +86,8 @@ SIGNATURES = {
     "rosko_spmm_backward_workspace_size": (_I32, [C.POINTER(RoskoPacked), _I64,
                                                   C.POINTER(_SZ)]),
     "rosko_spmm_backward": (_I32, [C.POINTER(RoskoPacked), C.POINTER(RoskoPacked), _P, _I64,
-                                   _P, _I64, _I64, _P, _I64, _P, _P, _SZ, _P]),
+                                   _P, _I64, _I64, _P, _I64, _P, _I64, _P, _SZ, _P]),
+    "rosko_scatter_dense": (_I32, [C.POINTER(RoskoPacked), _P, _I64, _P, _I64, _P]),
     "rosko_features_workspace_size": (_I32, [_I64, _I64, C.POINTER(_SZ)]),
     "rosko_features": (_I32, [_P, _I64, _I64, _I64, _I64, _P, _SZ, _P, _P]),
     "rosko_mlp_param_count": (_I32, [_I32, _I32, _I32, C.POINTER(_I64)]),

@@ -95,7 +95,7 @@ static int32_t check_packed_for_read(const rosko_packed* A) {
 
 extern "C" {
 
-int32_t rosko_abi_version(void) { return 4; }
+int32_t rosko_abi_version(void) { return 5; }
 
 const char* rosko_last_error(void) { return g_err; }
 
@@ -312,8 +312,8 @@ int32_t rosko_spmm_backward_workspace_size(const rosko_packed* At, int64_t N, si
 
 int32_t rosko_spmm_backward(const rosko_packed* A, const rosko_packed* At, const float* B,
                             int64_t ldb, const float* dC, int64_t lddc, int64_t N, float* dB,
-                            int64_t lddb, float* dA_val, void* ws, size_t ws_bytes,
-                            void* stream) {
+                            int64_t lddb, float* dA_val, int64_t dA_cap, void* ws,
+                            size_t ws_bytes, void* stream) {
   clear_error();
   int32_t st = check_packed_for_read(A);
   if (st) return st;
@@ -339,10 +339,25 @@ int32_t rosko_spmm_backward(const rosko_packed* A, const rosko_packed* At, const
   if (dA_val) {
     RK_REQUIRE(ldb >= N && ldb >= 1, ROSKO_EINVAL, "ldb < N");
     RK_REQUIRE(B != nullptr || A->K == 0 || N == 0, ROSKO_EINVAL, "B is null");
+    RK_REQUIRE(dA_cap >= 0, ROSKO_EINVAL, "negative dA capacity");
     (void)hipGetLastError();
-    if ((st = launch_sddmm(A, dC, lddc, B, ldb, N, dA_val, s))) return st;
+    if ((st = launch_sddmm(A, dC, lddc, B, ldb, N, dA_val, dA_cap, s))) return st;
   }
   return ROSKO_OK;
+}
+
+int32_t rosko_scatter_dense(const rosko_packed* A, const float* vals, int64_t n_vals,
+                            float* out, int64_t ldo, void* stream) {
+  clear_error();
+  int32_t st = check_packed_for_read(A);
+  if (st) return st;
+  RK_REQUIRE(n_vals >= 0, ROSKO_EINVAL, "negative value count");
+  RK_REQUIRE(ldo >= A->K && ldo >= 1, ROSKO_EINVAL, "ldo %lld < K %lld", (long long)ldo,
+             (long long)A->K);
+  if (A->M == 0 || A->K == 0 || n_vals == 0) return ROSKO_OK;
+  RK_REQUIRE(vals != nullptr && out != nullptr, ROSKO_EINVAL, "null argument");
+  (void)hipGetLastError();
+  return launch_scatter_dense(A, vals, n_vals, out, ldo, static_cast<hipStream_t>(stream));
 }
 
 // ---------------------------------------------------------- scheduler

@@ -149,7 +149,9 @@ int32_t launch_argmin(const float* Y, int64_t Bn, int32_t C, int32_t* out, hipSt
 
 // ---------------------------------------------------------------- SDDMM
 int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const float* B,
-                     int64_t ldb, int64_t N, float* dA_val, hipStream_t s);
+                     int64_t ldb, int64_t N, float* dA_val, int64_t dA_cap, hipStream_t s);
+int32_t launch_scatter_dense(const rosko_packed* A, const float* vals, int64_t n_vals,
+                             float* out, int64_t ldo, hipStream_t s);
 
 // Round x up to a multiple of a (a > 0).
 inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }

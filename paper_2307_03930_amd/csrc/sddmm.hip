@@ -8,6 +8,8 @@
 // (lanes over N) and reuses it for every value of the column, which is the
 // column-wise reuse the packed format exposes; each value's dot product is
 // finished with a wave reduction.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace rosko {
@@ -20,17 +22,22 @@ template <int VB>
 __global__ void __launch_bounds__(64 * kSdW)
 k_sddmm(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict__ col_ind,
         const int32_t* __restrict__ col_nnz, const int64_t* __restrict__ col_ptr,
-        const uint8_t* __restrict__ loc, int64_t M, int32_t mr, const float* __restrict__ dC,
-        int64_t lddc, const float* __restrict__ B, int64_t ldb, int64_t N,
-        float* __restrict__ dA) {
+        const uint8_t* __restrict__ loc, int64_t M, int64_t K, int32_t mr,
+        const float* __restrict__ dC, int64_t lddc, const float* __restrict__ B, int64_t ldb,
+        int64_t N, int64_t ncols_lim, int64_t nz_lim, float* __restrict__ dA) {
   const int64_t p = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t c_lo = panel_col_ptr[p], c_hi = panel_col_ptr[p + 1];
+  const int rows = (int)min((int64_t)mr, M - p * mr);
+  // the panel's column range and every index read from the packed arrays are
+  // clamped into the caller's buffers, so no content of them can move an
+  // access outside (a pack that overflowed its capacities, say)
+  const int64_t c_hi = min(panel_col_ptr[p + 1], ncols_lim);
+  const int64_t c_lo = min(max(panel_col_ptr[p], (int64_t)0), c_hi);
   for (int64_t c = c_lo + wid; c < c_hi; c += kSdW) {
-    const int64_t k = col_ind[c];
-    const int n = col_nnz[c];
-    const int64_t z0 = col_ptr[c];
+    const int64_t k = min(max((int64_t)col_ind[c], (int64_t)0), K - 1);
+    const int64_t z0 = max(col_ptr[c], (int64_t)0);
+    const int n = (int)max((int64_t)0, min((int64_t)col_nnz[c], nz_lim - z0));
     const float* brow = B + k * ldb;
     float b[VB];
 #pragma unroll
@@ -40,7 +47,7 @@ k_sddmm(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict__ c
     }
     for (int t = 0; t < n; ++t) {
       const int64_t z = z0 + t;
-      const int64_t m = p * mr + loc[z];
+      const int64_t m = p * mr + min((int)loc[z], rows - 1);
       const float* g = dC + m * lddc;
       float acc = 0.0f;
 #pragma unroll
@@ -94,8 +101,9 @@ template <int VQ>
 __global__ void __launch_bounds__(64 * kSdW)
 k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict__ col_ind,
             const int32_t* __restrict__ col_nnz, const int64_t* __restrict__ col_ptr,
-            const uint8_t* __restrict__ loc, int64_t M, int32_t mr, const float* __restrict__ dC,
-            int64_t lddc, const float* __restrict__ B, int64_t ldb, int64_t N, bool vec,
+            const uint8_t* __restrict__ loc, int64_t M, int64_t K, int32_t mr,
+            const float* __restrict__ dC, int64_t lddc, const float* __restrict__ B,
+            int64_t ldb, int64_t N, bool vec, int64_t ncols_lim, int64_t nz_lim,
             float* __restrict__ dA) {
   constexpr int RW = 256 * VQ;                    // LDS row width (floats)
   __shared__ float4 sdc4[kSdLdsRows * RW / 4];
@@ -111,7 +119,9 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
     sdc[idx] = n < N ? dC[(r0 + r) * lddc + n] : 0.0f;
   }
   __syncthreads();
-  const int64_t c_lo = panel_col_ptr[p], c_hi = panel_col_ptr[p + 1];
+  // clamped as in k_sddmm
+  const int64_t c_hi = min(panel_col_ptr[p + 1], ncols_lim);
+  const int64_t c_lo = min(max(panel_col_ptr[p], (int64_t)0), c_hi);
   const int64_t parts = (int64_t)kSdLdsG * kSdW, part = (int64_t)g * kSdW + w;
   const int64_t a = c_lo + (c_hi - c_lo) * part / parts;
   const int64_t e = c_lo + (c_hi - c_lo) * (part + 1) / parts;
@@ -133,9 +143,11 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
   for (int64_t cb = a; cb < e; cb += 64) {
     const int64_t c = cb + lane;
     const bool valid = c < e;
-    const int kk = valid ? col_ind[c] : 0;
-    const int nn = valid ? min(col_nnz[c], kSdLdsRows) : 0;
-    const int64_t zz = valid ? col_ptr[c] : 0;
+    const int kk = valid ? (int)min(max((int64_t)col_ind[c], (int64_t)0), K - 1) : 0;
+    const int64_t zz = valid ? max(col_ptr[c], (int64_t)0) : 0;
+    const int nn = valid ? (int)max((int64_t)0, min((int64_t)min(col_nnz[c], kSdLdsRows),
+                                                    nz_lim - zz))
+                         : 0;
     uint32_t rlo = 0, rhi = 0;                  // in-panel rows of the column, bytes
 #pragma unroll
     for (int t = 0; t < kSdLdsRows; ++t) {
@@ -185,16 +197,18 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
 }  // namespace
 
 int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const float* B,
-                     int64_t ldb, int64_t N, float* dA_val, hipStream_t s) {
-  if (A->n_panels == 0) return ROSKO_OK;
+                     int64_t ldb, int64_t N, float* dA_val, int64_t dA_cap, hipStream_t s) {
+  if (A->n_panels == 0 || A->K == 0) return ROSKO_OK;
+  const int64_t ncols_lim = A->ncols_cap;
+  const int64_t nz_lim = std::min(A->nnz_cap, dA_cap);
   const int64_t vb = ceil_div(N, 64);
   if (A->mr <= kSdLdsRows && N <= 1024 && (int64_t)A->n_panels * kSdLdsG <= INT32_MAX) {
     const dim3 grid((unsigned)(A->n_panels * kSdLdsG));
     const bool vec = (N % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)B % 16 == 0);
 #define RK_SDL(VQ_)                                                                          \
   hipLaunchKernelGGL(k_sddmm_lds<VQ_>, grid, dim3(64 * kSdW), 0, s, A->panel_col_ptr,        \
-                     A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M, A->mr, dC, lddc, B,   \
-                     ldb, N, vec, dA_val)
+                     A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M, A->K, A->mr, dC,      \
+                     lddc, B, ldb, N, vec, ncols_lim, nz_lim, dA_val)
     if (N <= 256) RK_SDL(1);
     else if (N <= 512) RK_SDL(2);
     else RK_SDL(4);
@@ -205,13 +219,56 @@ int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const
 #define RK_SD(VB_)                                                                          \
   hipLaunchKernelGGL(k_sddmm<VB_>, dim3((unsigned)A->n_panels), dim3(64 * kSdW), 0, s,       \
                      A->panel_col_ptr, A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M,     \
-                     A->mr, dC, lddc, B, ldb, N, dA_val)
+                     A->K, A->mr, dC, lddc, B, ldb, N, ncols_lim, nz_lim, dA_val)
   if (vb <= 1) RK_SD(1);
   else if (vb <= 4) RK_SD(4);
   else if (vb <= 16) RK_SD(16);
   else RK_SD(kSdMaxV);
 #undef RK_SD
   ROSKO_LAUNCH_CHECK("k_sddmm");
+  return ROSKO_OK;
+}
+
+}  // namespace rosko
+
+// ------------------------------------------------------------------ scatter
+// out[p*mr + loc[z]][col_ind[c]] = vals[z] for every stored entry z of A, in
+// packed order: the inverse of packing for a dense M x K gradient (the
+// weight gradient of the training decomposition is dA on the mask, zero
+// elsewhere; the caller zero-fills out).  One workgroup per panel, threads
+// over the panel's kept columns; indices clamped as in the SDDMM.
+namespace rosko {
+namespace {
+__global__ void __launch_bounds__(256)
+k_scatter_dense(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict__ col_ind,
+                const int32_t* __restrict__ col_nnz, const int64_t* __restrict__ col_ptr,
+                const uint8_t* __restrict__ loc, int64_t M, int64_t K, int32_t mr,
+                int64_t ncols_lim, int64_t nz_lim, const float* __restrict__ vals,
+                float* __restrict__ out, int64_t ldo) {
+  const int64_t p = blockIdx.x;
+  const int rows = (int)min((int64_t)mr, M - p * mr);
+  const int64_t c_hi = min(panel_col_ptr[p + 1], ncols_lim);
+  const int64_t c_lo = min(max(panel_col_ptr[p], (int64_t)0), c_hi);
+  for (int64_t c = c_lo + threadIdx.x; c < c_hi; c += 256) {
+    const int64_t k = col_ind[c];
+    if (k < 0 || k >= K) continue;
+    const int64_t z0 = max(col_ptr[c], (int64_t)0);
+    const int64_t n = max((int64_t)0, min((int64_t)col_nnz[c], nz_lim - z0));
+    for (int64_t t = 0; t < n; ++t) {
+      const int r = loc[z0 + t];
+      if (r < rows) out[(p * mr + r) * ldo + k] = vals[z0 + t];
+    }
+  }
+}
+}  // namespace
+
+int32_t launch_scatter_dense(const rosko_packed* A, const float* vals, int64_t n_vals,
+                             float* out, int64_t ldo, hipStream_t s) {
+  if (A->n_panels == 0 || A->K == 0) return ROSKO_OK;
+  hipLaunchKernelGGL(k_scatter_dense, dim3((unsigned)A->n_panels), dim3(256), 0, s,
+                     A->panel_col_ptr, A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M, A->K,
+                     A->mr, A->ncols_cap, std::min(A->nnz_cap, n_vals), vals, out, ldo);
+  ROSKO_LAUNCH_CHECK("k_scatter_dense");
   return ROSKO_OK;
 }
 

@@ -263,18 +263,37 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
   g.mr = A->mr;
   g.n_panels = A->n_panels;
   g.beta = beta;
-  const int V = plan.cols_per_lane, H = plan.waves_per_tile;
+  const int H = plan.waves_per_tile;
   g.k_split = std::max(1, plan.k_split);
   g.rec_bound = A->nrec >= 0 ? std::min(A->nrec, A->nrec_cap) : A->nrec_cap;
-  g.n_chunks = ceil_div(N, 64 * V);
   const size_t eb = (b_dtype == ROSKO_F32) ? 4 : 2;
-  // vector path: aligned V-wide rows, and B and every run of records within
-  // the 32-bit offsets of the buffer loads; otherwise element loads with
-  // clamped indices
-  g.vec = (ldb % V == 0) && (ldc % V == 0) && (N % V == 0) &&
-          ((uintptr_t)B % (eb * V) == 0) && ((uintptr_t)C % (4 * V) == 0) &&
-          ((uint64_t)A->K * (uint64_t)ldb * eb < (1ull << 32)) &&
-          ((uint64_t)(g.rec_bound + 64) * 64u < (1ull << 32));
+  // The record loop reads B and the records with buffer loads at 32-bit
+  // offsets and V-wide aligned B units, and stores V-wide C units.  When
+  // the requested tile's V does not fit B and C (N, ldb, ldc or a pointer
+  // not a multiple of V), the one-column tile (128 x 1) runs instead, which
+  // needs no alignment beyond the element size.  Beyond 32-bit offsets the
+  // call is refused.
+  auto vec_ok = [&](int v) {
+    return (ldb % v == 0) && (ldc % v == 0) && (N % v == 0) &&
+           ((uintptr_t)B % (eb * v) == 0) && ((uintptr_t)C % (4 * v) == 0);
+  };
+  int V = plan.cols_per_lane, MRt = tile_height(A->mr);
+  if (!vec_ok(V)) {
+    V = 1;
+    MRt = 128;
+    if (!vec_ok(1)) {
+      set_error("B or C is not aligned to its element size");
+      return ROSKO_EUNSUPPORTED;
+    }
+  }
+  if ((uint64_t)A->K * (uint64_t)ldb * eb >= (1ull << 32) ||
+      (uint64_t)(g.rec_bound + 64) * 64u >= (1ull << 32)) {
+    set_error("B (%lld x %lld elements) or the record array exceeds 4 GiB of buffer offsets",
+              (long long)A->K, (long long)ldb);
+    return ROSKO_EUNSUPPORTED;
+  }
+  g.n_chunks = ceil_div(N, 64 * V);
+  g.vec = 1;
   g.ws_vec = (N % V == 0) && ((uintptr_t)ws % (4 * V) == 0);
   if (g.k_split > 1) {
     const size_t need = spmm_ws_bytes(A, N, plan);
@@ -283,7 +302,6 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
       return ROSKO_ESMALLBUF;
     }
   }
-  const int MRt = tile_height(A->mr);
   const int32_t st = (b_dtype == ROSKO_BF16) ? spmm_dispatch_bbf16(g, MRt, V, H, plan.depth, s)
                                              : spmm_dispatch_bf32(g, MRt, V, H, plan.depth, s);
   if (st != ROSKO_OK || g.k_split == 1) return st;

@@ -245,6 +245,7 @@ def spmm_backward(P: PackedMatrix, Pt: PackedMatrix | None, B: torch.Tensor, dC:
         C.byref(st), C.byref(stt) if stt is not None else None, _ptr(B),
         max(B.stride(0), 1), _ptr(dC), max(dC.stride(0), 1), N, _ptr(dB),
         max(dB.stride(0), 1) if dB is not None else 1, _ptr(dA),
+        dA.numel() if dA is not None else 0,
         _ptr(ws) if need else None, ws.numel() if need else 0, _stream_ptr()))
     return (dA[: P.nnz] if dA is not None else None), dB
 
@@ -262,9 +263,38 @@ def pack_into(A: torch.Tensor, P: PackedMatrix, ws: torch.Tensor) -> PackedMatri
     return P
 
 
-def pack_result(P: PackedMatrix, ws: torch.Tensor) -> tuple[int, int]:
-    """Synchronises; (nnz, ncols) of the last pack_into with this workspace.
-    Raises if they exceeded P's capacities."""
+def pack_transpose_into(A: torch.Tensor, Pt: PackedMatrix, ws: torch.Tensor) -> PackedMatrix:
+    """Re-packs A^T (A: M x K) into Pt's existing buffers (Pt is K x M, FP32
+    values; its capacities must hold A's structure).  Asynchronous."""
+    _check_dense(A, "A")
+    M, K = A.shape
+    if (K, M) != (Pt.M, Pt.K):
+        raise ValueError("shape differs from the packed transpose buffers")
+    st = Pt.struct()
+    L.check(L.lib().rosko_pack_transpose(_ptr(A), M, K, max(A.stride(0), 1), Pt.mr,
+                                         L.ROSKO_F32, _ptr(ws), ws.numel(), C.byref(st),
+                                         _stream_ptr()))
+    return Pt
+
+
+def pack_result(P: PackedMatrix, ws: torch.Tensor, transpose: bool = False) -> tuple[int, int]:
+    """Synchronises; (nnz, ncols) of the last pack_into (pack_transpose_into
+    with transpose=True) with this workspace.  Raises if they exceeded P's
+    capacities."""
     st = P.struct()
     L.check(L.lib().rosko_pack_result(_ptr(ws), ws.numel(), C.byref(st), _stream_ptr()))
     return int(st.nnz), int(st.ncols)
+
+
+def scatter_dense(P: PackedMatrix, vals: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    """out[m][k] = vals[z] for every stored entry z of P (packed order); the
+    other entries of out are left as they are."""
+    if not (out.is_cuda and out.dtype == torch.float32 and out.dim() == 2
+            and out.shape == (P.M, P.K) and (out.stride(1) == 1 or out.numel() == 0)):
+        raise ValueError("out must be a row-major float32 CUDA tensor of A's shape")
+    if vals.dtype != torch.float32 or not vals.is_cuda:
+        raise ValueError("vals must be a float32 CUDA tensor")
+    st = P.struct()
+    L.check(L.lib().rosko_scatter_dense(C.byref(st), _ptr(vals), vals.numel(), _ptr(out),
+                                        max(out.stride(0), 1), _stream_ptr()))
+    return out

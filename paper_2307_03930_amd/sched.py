@@ -186,14 +186,29 @@ def load(device="cuda", path: str = WEIGHTS) -> MLP | None:
 _NETS: dict = {}
 
 
+REPORT = os.path.join(DATA_DIR, "fit_report.json")
+
+
+def network_beats_rule(path: str = REPORT) -> bool:
+    """True when the committed fit report shows the network strictly ahead of
+    the analytic rule on its held-out problems (geomean slowdown)."""
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        rep = json.load(f)["held_out"]
+    return rep["mlp"]["geomean"] < rep["analytic"]["geomean"]
+
+
 def default_net(device=None) -> MLP | None:
     """The committed network on `device` (the current CUDA device if None),
-    loaded once per device; None when no weights file is present."""
+    loaded once per device; None when no weights file is present or when the
+    network does not beat the analytic rule on its held-out problems (then
+    the rule, the method's own tiling choice, is used)."""
     dev = torch.device(device) if device is not None else torch.device(
         "cuda", torch.cuda.current_device())
     key = str(dev)
     if key not in _NETS:
-        _NETS[key] = load(dev)
+        _NETS[key] = load(dev) if network_beats_rule() else None
     return _NETS[key]
 
 

@@ -1,5 +1,6 @@
 """Shared helpers of the GPU parity tests (HIP path through the C ABI versus
 the CPU oracle)."""
+import functools
 import sys
 
 import numpy as np
@@ -58,3 +59,37 @@ def assert_pack_equal(P: ops.PackedMatrix, ref: O.Packed) -> None:
 
 def err(C_hat, C_ref, scale) -> float:
     return O.err_metric(np.asarray(C_hat, np.float64), C_ref, scale)
+
+
+def threads() -> int:
+    """Host threads for the full-size oracle runs (the GPU machine's CPU share)."""
+    return max(1, min(16, O.max_threads()))
+
+
+@functools.lru_cache(maxsize=None)
+def cnn_reference(s: float):
+    """(problem, C, |A||B|) of the 256 x 2304 x 3136 layer at sparsity s, full
+    size, from the threaded FP64 oracle (cached across tests)."""
+    from paper_2307_03930_amd import synth
+    pr = synth.cnn_layer(s)
+    t = threads()
+    return pr, O.spmm(pr.A, pr.B, threads=t), O.abs_product(pr.A, pr.B, threads=t)
+
+
+@functools.lru_cache(maxsize=None)
+def precision_reference(s: float):
+    """(problem, C on the FP32 source values, |A||B|) of the 4096 x 4096 x 2048
+    precision form at sparsity s, full size."""
+    from paper_2307_03930_amd import synth
+    pr = synth.precision_problem(s)
+    t = threads()
+    return pr, O.spmm(pr.A, pr.B, threads=t), O.abs_product(pr.A, pr.B, threads=t)
+
+
+def assert_nonfinite_match(C_hat: np.ndarray, C_ref: np.ndarray) -> np.ndarray:
+    """The positions where the oracle is +Inf, -Inf or NaN must hold the same
+    class on the GPU; returns the mask of positions finite in both."""
+    C_hat = np.asarray(C_hat, np.float64)
+    for f in (np.isnan, np.isposinf, np.isneginf):
+        assert np.array_equal(f(C_hat), f(C_ref)), f.__name__
+    return np.isfinite(C_ref)

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.rosko_abi_version() == 4
+    assert lib.rosko_abi_version() == 5
     assert lib.rosko_status_str(L.ROSKO_EINVAL) == b"ROSKO_EINVAL"
     assert lib.rosko_status_str(123) == b"ROSKO_UNKNOWN"
 
@@ -180,10 +180,13 @@ def test_backward_argument_checks():
     s = _packed(8, 6, 4)
     st = _packed(8, 6, 4)   # wrong: must be 6 x 8
     assert lib.rosko_spmm_backward(C.byref(s), C.byref(st), fake, 16, fake, 16, 16, fake, 16,
-                                   None, None, 0, None) == L.ROSKO_EINVAL
+                                   None, 0, None, 0, None) == L.ROSKO_EINVAL
     st = _packed(6, 8, 4, dtype=L.ROSKO_BF16)
     assert lib.rosko_spmm_backward(C.byref(s), C.byref(st), fake, 16, fake, 16, 16, fake, 16,
-                                   None, None, 0, None) == L.ROSKO_EUNSUPPORTED
+                                   None, 0, None, 0, None) == L.ROSKO_EUNSUPPORTED
+    # a negative dA capacity is rejected before any work
+    assert lib.rosko_spmm_backward(C.byref(s), None, fake, 16, fake, 16, 16, None, 16,
+                                   fake, -1, None, 0, None) == L.ROSKO_EINVAL
 
 
 def test_plan_validation_and_workspace_size():

@@ -10,7 +10,8 @@ import torch
 
 import oracle as O
 from paper_2307_03930_amd import ops, sched, synth
-from tests.gpu_helpers import DT, assert_pack_equal, dev, err, packed_to_np, say
+from tests.gpu_helpers import (DT, assert_nonfinite_match, assert_pack_equal, cnn_reference,
+                               dev, err, packed_to_np, precision_reference, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -218,13 +219,10 @@ def test_spmm_many_waves_per_tile(mr, V, H, N):
 
 
 @pytest.mark.skip(reason=MANY_WAVES_OFF)
-def test_spmm_many_waves_deterministic_and_cnn_sampled():
+def test_spmm_many_waves_deterministic_and_cnn_full():
     """H = 8 and 16 on the 256 x 2304 x 3136 layer at 70%: repeatable bit
-    for bit, and sampled rows within the FP32 bar."""
-    pr = synth.cnn_layer(0.7)
-    rows = np.sort(synth.rng(622).choice(256, 24, replace=False))
-    ref = O.spmm(pr.A[rows], pr.B)
-    scale = O.abs_product(pr.A[rows], pr.B)
+    for bit, and the whole output within the FP32 bar."""
+    pr, ref, scale = cnn_reference(0.7)
     Bd = dev(pr.B)
     for mr, V, H, S in ((8, 4, 16, 1), (8, 4, 16, 2), (16, 4, 8, 1), (16, 4, 8, 3)):
         say(f"spmm cnn 70% mr={mr} H={H} S={S}")
@@ -232,7 +230,7 @@ def test_spmm_many_waves_deterministic_and_cnn_sampled():
         c1 = ops.spmm(P, Bd, plan=ops.make_plan(V, H, S)).cpu().numpy()
         c2 = ops.spmm(P, Bd, plan=ops.make_plan(V, H, S)).cpu().numpy()
         assert c1.tobytes() == c2.tobytes()
-        assert err(c1[rows], ref, scale) <= TOL_F32
+        assert err(c1, ref, scale) <= TOL_F32
 
 
 def test_spmm_beta_one_and_strides():
@@ -307,19 +305,17 @@ def test_spmm_more_runs_than_records():
 
 
 @pytest.mark.parametrize("s", synth.CNN_SPARSITIES)
-def test_spmm_cnn_layer_sampled(s):
+def test_spmm_cnn_layer_full(s):
     """256 x 2304 magnitude-pruned weights times the 2304 x 3136 im2col
-    activations, full size on the GPU; 24 sampled rows of C checked."""
+    activations, full size; every element of C against the FP64 oracle, for
+    several register tiles and parallel shapes."""
     say(f"spmm cnn layer s={s}")
-    pr = synth.cnn_layer(s)
-    rows = np.sort(synth.rng(610).choice(256, 24, replace=False))
-    ref = O.spmm(pr.A[rows], pr.B)
-    scale = O.abs_product(pr.A[rows], pr.B)
+    pr, ref, scale = cnn_reference(s)
     P = ops.pack(dev(pr.A), 32)
     Bd = dev(pr.B)
     for V, H, S in ((4, 4, 1), (4, 4, 4), (2, 2, 2), (4, 1, 18)):
         C = ops.spmm(P, Bd, plan=ops.make_plan(V, H, S))
-        e = err(C.cpu().numpy()[rows], ref, scale)
+        e = err(C.cpu().numpy(), ref, scale)
         say(f"  V={V} H={H} S={S} err {e:.3e}")
         assert e <= TOL_F32
 
@@ -329,9 +325,9 @@ def test_timed_step_configuration(s):
     """The step as the benchmark times it on the 256 x 2304 x 3136 layer: the
     plan scheduler's candidate for the matrix, a re-pack into the buffers of
     a first pack (bit-exact with Alg. 1 both times), then the SpMM with that
-    candidate's columns per lane and the library's parallel shape.  24
-    sampled rows of C against the oracle; a second step gives the same bits."""
-    pr = synth.cnn_layer(s)
+    candidate's columns per lane and the library's parallel shape.  The whole
+    of C against the oracle; a second step gives the same bits."""
+    pr, ref, scale = cnn_reference(s)
     Ad, Bd = dev(pr.A), dev(pr.B)
     M, K = pr.A.shape
     N = pr.B.shape[1]
@@ -352,11 +348,48 @@ def test_timed_step_configuration(s):
         torch.cuda.synchronize()
         assert_pack_equal(P, ref_pack)
         outs.append(C.cpu().numpy().copy())
-    rows = np.sort(synth.rng(611).choice(M, 24, replace=False))
-    e = err(outs[0][rows], O.spmm(pr.A[rows], pr.B), O.abs_product(pr.A[rows], pr.B))
+    e = err(outs[0], ref, scale)
     say(f"  err {e:.3e}")
     assert e <= TOL_F32
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_spmm_beta_one_full_size():
+    """C += A B on the 256 x 2304 x 3136 layer at 90%, onto a random C, for a
+    split and an unsplit plan; the whole output against the oracle."""
+    say("spmm beta=1 full size")
+    pr, ref, scale = cnn_reference(0.90)
+    C0 = synth.dense_normal(256, 3136, 614)
+    P = ops.pack(dev(pr.A), 16)
+    Bd = dev(pr.B)
+    for plan in (ops.make_plan(4, 4, 1), ops.make_plan(4, 4, 5), None):
+        Cd = dev(C0)
+        ops.spmm(P, Bd, Cd, beta=1, plan=plan)
+        e = err(Cd.cpu().numpy(), ref + C0.astype(np.float64), scale + np.abs(C0))
+        say(f"  err {e:.3e}")
+        assert e <= TOL_F32
+
+
+def test_spmm_nonfinite_values_in_A():
+    """Inf, -Inf and NaN stored in A are kept by packing and multiply every B
+    value of their column (the sum over the stored entries); rows they reach
+    must carry the same non-finite class as the oracle, all others stay
+    within the FP32 bar."""
+    say("spmm with Inf/NaN stored in A")
+    A = synth.sparse_matrix(130, 300, 0.1, 615)
+    B = synth.dense_normal(300, 260, 616)
+    nz = np.flatnonzero(A)
+    pick = synth.rng(617).choice(nz, 6, replace=False)
+    A.reshape(-1)[pick] = np.array([np.inf, -np.inf, np.nan, np.inf, -np.inf, np.nan],
+                                   np.float32)
+    ref = O.spmm(A, B)
+    scale = O.abs_product(A, B)
+    for mr, plan in ((16, ops.make_plan(4, 4, 1)), (32, ops.make_plan(2, 2, 3)), (8, None)):
+        C = ops.spmm(ops.pack(dev(A), mr), dev(B), plan=plan).cpu().numpy()
+        fin = assert_nonfinite_match(C, ref)
+        assert (~fin).any() and fin.any()
+        e = err(np.where(fin, C, 0.0), np.where(fin, ref, 0.0), np.where(fin, scale, 1.0))
+        assert e <= TOL_F32
 
 
 # --------------------------------------------------------------------------
@@ -386,25 +419,22 @@ def test_spmm_quantised_values(dtype, b_bf16):
 
 @pytest.mark.parametrize("s", [0.90, 0.98])
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
-def test_spmm_precision_form_sampled(s, dtype):
-    """4096 x 4096 at 90/98% times 4096 x 2048 BF16 activations, full size on
-    the GPU; 16 sampled rows checked against the oracle, with mr 32 and the
-    library's plan, then with the plan scheduler's candidate (its panel
-    height and columns per lane) as the benchmark runs it; the re-pack into
-    the candidate's buffers is compared with Alg. 1 bit for bit."""
+def test_spmm_precision_form_full(s, dtype):
+    """4096 x 4096 at 90/98% times 4096 x 2048 BF16 activations, full size;
+    all 4096 x 2048 outputs against the oracle on the FP32 source values,
+    with mr 32 and the library's plan, then with the plan scheduler's
+    candidate (its panel height and columns per lane) as the benchmark runs
+    it; the re-pack into the candidate's buffers is compared with Alg. 1 bit
+    for bit."""
     say(f"spmm precision form s={s} values={dtype}")
-    pr = synth.precision_problem(s)
-    rows = np.sort(synth.rng(613).choice(4096, 16, replace=False))
-    Arows = pr.A[rows]
-    c_src = O.spmm(Arows, pr.B)
-    scale = O.abs_product(Arows, pr.B)
+    pr, c_src, scale = precision_reference(s)
     Ad = dev(pr.A)
     Bd = dev(pr.B).to(torch.bfloat16) if dtype != "f32" else dev(pr.B)
     mr_s, cand = sched.candidate(sched.choose(Ad, pr.B.shape[1]))
     tol = {"f32": TOL_F32, "bf16": TOL_BF16, "fp8": TOL_FP8}[dtype]
     for mr, plan in ((32, None), (mr_s, ops.make_plan(cand.cols_per_lane))):
         P = ops.pack(Ad, mr, dtype)
-        C = ops.spmm(P, Bd, plan=plan).cpu().numpy()[rows]
+        C = ops.spmm(P, Bd, plan=plan).cpu().numpy()
         e = err(C, c_src, scale)
         say(f"  mr {mr} plan {'auto' if plan is None else cand.cols_per_lane}: "
             f"err vs FP32 source {e:.3e}")

@@ -234,6 +234,41 @@ def test_spmm_matches_numpy_matmul():
     assert np.all(np.abs(C - ref) <= 1e-14 * scale + 1e-300)
 
 
+def test_abs_product_hand_case():
+    # (|A| |B|)_i over A's kept entries: row 0 = 1*|B0| + 2*|B2|, row 1 =
+    # 3*|B2|; the -0.0 entry is not kept, so the Inf in B's row 1 never meets
+    # a zero factor (a dense |A| @ |B| would give NaN there)
+    A = np.array([[1, 0, -2], [0, -0.0, -3]], np.float32)
+    B = np.array([[1, -2], [np.inf, 7], [0.5, -1]], np.float32)
+    np.testing.assert_array_equal(O.abs_product(A, B), [[2.0, 4.0], [1.5, 3.0]])
+
+
+def test_abs_product_matches_numpy_and_bounds_the_product():
+    A = synth.sparse_matrix(60, 140, 0.25, 25)
+    B = synth.dense_normal(140, 37, 26)
+    S = O.abs_product(A, B)
+    ref = np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64)
+    assert np.all(np.abs(S - ref) <= 1e-14 * ref + 1e-300)
+    # |sum a b| <= sum |a| |b|, with equality when every term is non-negative
+    assert np.all(np.abs(O.spmm(A, B)) <= S * (1 + 1e-14))
+    Ap, Bp = np.abs(A), np.abs(B)
+    np.testing.assert_array_equal(O.abs_product(Ap, Bp), O.spmm(Ap, Bp))
+    # bilinear: scaling B by 2 scales the bound exactly by 2
+    np.testing.assert_array_equal(O.abs_product(A, 2 * B), 2 * S)
+
+
+def test_threaded_oracle_routines_equal_single_thread():
+    A = synth.sparse_matrix(70, 90, 0.2, 27)
+    B = synth.dense_normal(90, 45, 28)
+    dC = synth.dense_normal(70, 45, 29)
+    for f in (O.spmm, O.abs_product):
+        assert f(A, B, threads=4).tobytes() == f(A, B).tobytes()
+    assert O.grad_dB(A, dC, threads=4).tobytes() == O.grad_dB(A, dC).tobytes()
+    pk = O.pack(A, 8)
+    assert (O.grad_dA_packed(pk, dC, B, threads=4).tobytes()
+            == O.grad_dA_packed(pk, dC, B).tobytes())
+
+
 def test_spmm_csr_equals_dense_bitwise_finite():
     # adding an exact zero product never changes a partial sum that starts at
     # +0, so skipping zero terms is exact (Sec. 3): CSR == dense bit for bit
