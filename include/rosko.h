@@ -221,6 +221,25 @@ int32_t rosko_spmm(const rosko_packed *A, const void *B, int32_t b_dtype, int64_
                    int64_t ldb, float *C, int64_t ldc, int32_t beta, const rosko_plan *plan,
                    void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid allocation): rosko_spmm on
+ * the sparse path with no workspace argument.  The K-split partial tiles go
+ * to a device array of ROSKO_NOALLOC_SCRATCH_BYTES inside the library, one
+ * per GPU, held until the process ends (its address is looked up on the
+ * first call on each device).  Nothing is allocated.  An automatic plan
+ * (plan NULL) takes only as many K splits as fit the scratch; a caller's
+ * plan whose partials (4 * k_split * M * N bytes) exceed it returns
+ * ROSKO_ESMALLBUF, and the dense path returns ROSKO_EUNSUPPORTED.  Every
+ * call on one GPU shares that GPU's scratch: calls that overlap in time on
+ * one GPU (other streams, other host threads) race and must be serialised
+ * by the caller.  No part of the scratch needs to start at zero: a call
+ * writes every partial it reads.  Arguments and results otherwise as
+ * rosko_spmm.  Asynchronous. */
+#define ROSKO_NOALLOC_SCRATCH_BYTES (32u << 20)
+int32_t rosko_spmm_noalloc(const rosko_packed *A, const void *B, int32_t b_dtype, int64_t N,
+                           int64_t ldb, float *C, int64_t ldc, int32_t beta,
+                           const rosko_plan *plan, void *stream);
+
 /* ---- backward of C = A*B (training decomposition, Sec. 5.4) ------------
  * dB = A^T dC, computed as a Rosko SpMM over At, the packed transpose of A
  * (from rosko_pack_transpose; FP32 values).  dA = (dC B^T) restricted to the
