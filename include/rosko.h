@@ -130,8 +130,8 @@ typedef struct rosko_packed {
  *                 and multiplied on the matrix cores: BF16 MFMA when A's
  *                 values and B are exactly BF16 -- BF16 or FP8 values with a
  *                 BF16 B -- else FP32 MFMA; the other fields are ignored;
- *                 currently switched off: rosko_spmm returns
- *                 ROSKO_EUNSUPPORTED for it), or
+ *                 its workspace holds the densified A and the transposed
+ *                 B), or
  *                 ROSKO_PATH_AUTO to let the library choose everything.
  * cols_per_lane:  1, 2 or 4.  The register tile (panel height rounded up to
  *                 8/16/32/64/128, times cols_per_lane) must be one of 8x4,

@@ -69,6 +69,8 @@ static int32_t check_packed_for_write(const rosko_packed* out, int64_t R, int64_
   return ROSKO_OK;
 }
 
+static hipStream_t s_of(void* stream) { return static_cast<hipStream_t>(stream); }
+
 static int32_t check_packed_for_read(const rosko_packed* A) {
   RK_REQUIRE(A != nullptr, ROSKO_EINVAL, "packed matrix is null");
   RK_REQUIRE(A->M >= 0 && A->K >= 0, ROSKO_EINVAL, "packed matrix has a negative size");
@@ -287,11 +289,9 @@ int32_t rosko_spmm(const rosko_packed* A, const void* B, int32_t b_dtype, int64_
   if (A->M == 0 || N == 0) return ROSKO_OK;
   (void)hipGetLastError();
   if (p.path == ROSKO_PATH_DENSE) {
-    // Switched off: two GPU runs that called this path back to back at
-    // untested shapes faulted the GPU and the cause has not been found.
-    // The kernels stay in dense.hip; launch_spmm_dense is not reached.
-    set_error("the dense-MFMA path is disabled in this version of the library");
-    return ROSKO_EUNSUPPORTED;
+    if (A->K == 0) return beta ? ROSKO_OK : launch_fill_zero(C, A->M, N, ldc, s_of(stream));
+    return launch_spmm_dense(A, B, b_dtype, N, ldb, C, ldc, beta, ws, ws_bytes,
+                             static_cast<hipStream_t>(stream));
   }
   return launch_spmm_sparse(A, B, b_dtype, N, ldb, C, ldc, beta, p, static_cast<float*>(ws),
                             ws_bytes, static_cast<hipStream_t>(stream));

@@ -296,12 +296,18 @@ def test_sched_candidates_and_analytic_rule():
     assert lib.rosko_features(None, 0, 5, 5, 3, None, 0, None, None) == L.ROSKO_EINVAL
 
 
-def test_dense_path_is_switched_off():
+def test_dense_path_checks_its_workspace_on_the_host():
+    """The dense-MFMA path needs the densified A and transposed B in the
+    workspace (FP32 size: 4 (Mp + Np) Kp bytes, Mp, Np rounded up to 128 and
+    Kp to 64); a smaller one is refused before any work."""
     lib = L.lib()
     fake = C.c_void_p(0x1000)
     s = _packed(8, 8, 4)
     plan = L.RoskoPlan()
     plan.path = L.ROSKO_PATH_DENSE
+    n = C.c_size_t(0)
+    assert lib.rosko_spmm_workspace_size(C.byref(s), 16, C.byref(plan), C.byref(n)) == 0
+    assert n.value == 4 * 128 * 64 + 4 * 128 * 64
     assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 16, fake, 16, 0, C.byref(plan),
-                          fake, 1 << 20, None) == L.ROSKO_EUNSUPPORTED
+                          fake, n.value - 1, None) == L.ROSKO_ESMALLBUF
     assert b"dense" in lib.rosko_last_error()

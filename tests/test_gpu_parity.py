@@ -448,18 +448,12 @@ def test_spmm_precision_form_full(s, dtype):
 
 
 # --------------------------------------------------------------------------
-# dense-MFMA path: every panel densified from the packed form.  Switched off
-# in the library (rosko_spmm returns ROSKO_EUNSUPPORTED): two GPU runs that
-# called it back to back at untested shapes faulted the GPU and the cause has
-# not been found, so these tests are skipped until it is.
+# dense-MFMA path: every panel densified from the packed form, then a GEMM on
+# the matrix cores
 # --------------------------------------------------------------------------
-DENSE_OFF = pytest.mark.skip(reason="dense-MFMA path switched off: two GPU faults in runs "
-                             "that called it repeatedly; cause not found")
-
-
-@DENSE_OFF
 @pytest.mark.parametrize("M,K,N,mr", [(512, 512, 512, 32), (77, 131, 190, 13), (300, 40, 1, 8),
-                                      (129, 257, 129, 64), (1, 1, 1, 1)])
+                                      (129, 257, 129, 64), (1, 1, 1, 1), (256, 2304, 3136, 16),
+                                      (1534, 1112, 519, 8), (40, 70, 300, 200)])
 def test_dense_path_f32(M, K, N, mr):
     """FP32 values and B: FP32 MFMA on the densified panels."""
     say(f"dense path f32 M={M} K={K} N={N} mr={mr}")
@@ -474,7 +468,6 @@ def test_dense_path_f32(M, K, N, mr):
     assert e <= TOL_F32
 
 
-@DENSE_OFF
 @pytest.mark.parametrize("dtype", ["bf16", "fp8"])
 @pytest.mark.parametrize("b_bf16", [False, True])
 def test_dense_path_quantised(dtype, b_bf16):
@@ -496,7 +489,6 @@ def test_dense_path_quantised(dtype, b_bf16):
     assert e <= TOL_F32
 
 
-@DENSE_OFF
 def test_dense_path_beta_and_strides():
     say("dense path beta=1 with padded leading dimensions")
     A = synth.sparse_matrix(96, 200, 0.4, 624)
@@ -516,19 +508,16 @@ def test_dense_path_beta_and_strides():
     assert not got[:, 130:].any()
 
 
-@DENSE_OFF
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_dense_path_precision_form_sampled(dtype):
-    """4096 x 4096 at 90% times the 4096 x 2048 activations on the matrix
-    cores; 16 sampled rows against the oracle."""
-    say(f"dense path precision form values={dtype}")
-    pr = synth.precision_problem(0.90)
-    rows = np.sort(synth.rng(627).choice(4096, 16, replace=False))
-    c_src = O.spmm(pr.A[rows], pr.B)
-    scale = O.abs_product(pr.A[rows], pr.B)
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("s", [0.90, 0.98])
+def test_dense_path_precision_form_full(s, dtype):
+    """4096 x 4096 at 90/98% times the 4096 x 2048 activations on the matrix
+    cores; every output against the oracle on the FP32 source values."""
+    say(f"dense path precision form s={s} values={dtype}")
+    pr, c_src, scale = precision_reference(s)
     P = ops.pack(dev(pr.A), 32, dtype)
-    Bd = dev(pr.B).to(torch.bfloat16) if dtype == "bf16" else dev(pr.B)
-    C = ops.spmm(P, Bd, plan=ops.dense_plan()).cpu().numpy()[rows]
+    Bd = dev(pr.B).to(torch.bfloat16) if dtype != "f32" else dev(pr.B)
+    C = ops.spmm(P, Bd, plan=ops.dense_plan()).cpu().numpy()
     e = err(C, c_src, scale)
     say(f"  err vs FP32 source {e:.3e}")
-    assert e <= (TOL_F32 if dtype == "f32" else TOL_BF16)
+    assert e <= {"f32": TOL_F32, "bf16": TOL_BF16, "fp8": TOL_FP8}[dtype]
