@@ -151,8 +151,7 @@ def run_precision(args):
         N = pr.B.shape[1]
         if dense_us is None:
             dense_us = _time_us(lambda: torch.matmul(A, B32), 10)
-        mr, cand = sched.candidate(sched.choose(A, N))
-        plan = ops.make_plan(cand.cols_per_lane)
+        mr, plan = sched.candidate(sched.choose(A, N))
         kt = int((pr.A != 0).any(axis=0).sum())
         for vals in ("f32", "bf16", "fp8"):
             P = ops.pack(A, mr, vals)
@@ -196,12 +195,12 @@ def run_backward(args):
     M, K = pr.A.shape
     N = pr.B.shape[1]
     # One panel height serves the forward, the transposed pack and the
-    # SDDMM; the SDDMM's LDS path covers panels of at most 8 rows, which the
-    # analytic rule gives at this density.
-    mr, cand = sched.candidate(sched.choose(A, N, rule="analytic"))
+    # SDDMM: 8 rows (the SDDMM's LDS path covers panels of at most 8 rows),
+    # the 8 x 4 register tile, the library's parallel shape.
+    mr = 8
     P = ops.pack(A, mr, "f32")
     Pt = ops.pack_transpose(A, mr)
-    plan = ops.make_plan(cand.cols_per_lane)
+    plan = ops.make_plan(4)
     C = torch.empty((M, N), dtype=torch.float32, device=dev)
     ws = torch.empty(max(ops.spmm_workspace_size(P, N, plan), 1), dtype=torch.uint8, device=dev)
     n = P.nnz
@@ -276,12 +275,16 @@ def main():
     packs, wss, Cs, sws, plans, mrs = [], [], [], [], [], []
     for A in As:
         cols = args.cols_per_lane
+        overrides = (cols, args.waves_per_tile, args.k_split, args.depth) != (None,) * 4
         if args.mr is None:
             mr, cand = sched.candidate(sched.choose(A, N))
-            cols = cols or cand.cols_per_lane
+            cols = cols or cand.cols_per_lane or 4
         else:
-            mr = args.mr
-        plan = ops.make_plan(cols, args.waves_per_tile, args.k_split, args.depth)
+            mr, cand = args.mr, None
+        if cand is not None and not overrides:
+            plan = cand                      # the scheduler's candidate, sparse or dense
+        else:
+            plan = ops.make_plan(cols, args.waves_per_tile, args.k_split, args.depth)
         P = ops.pack(A, mr, "f32")
         packs.append(P)
         plans.append(plan)

@@ -329,11 +329,25 @@ int32_t rosko_argmin_rows(const float *Y, int64_t batch, int32_t C, int32_t *out
 /* Candidate `index`: the panel height to pack with (*mr) and the plan to
  * multiply with (waves_per_tile and k_split 0: chosen by the library). */
 int32_t rosko_sched_candidate(int32_t index, int32_t *mr, rosko_plan *plan);
-/* The analytic fallback rule on host features: 4 columns per lane, mr 16
- * from density 0.08 up (candidate 1) and mr 8 below (candidate 0).  (With
- * the dense path available it takes that path from density 0.25 up; the
- * dense path is switched off in this version.) */
+/* The analytic fallback rule on host features: a 3 x 3 table over the
+ * density (bands at 0.02 and 0.3) and log2 N (bands at 6 and 11) whose cells
+ * hold the candidate fastest (geometric mean of repack + SpMM time) over the
+ * training problems of the random-shape corpus in that cell:
+ *   d < 0.02:        N < 64: 0, N < 2048: 1, else 3
+ *   0.02 <= d < 0.3: N < 64: 1, else 3
+ *   d >= 0.3:        N < 64: 1, N < 2048: 3, else 6 (dense-MFMA). */
 int32_t rosko_sched_analytic(const float *features_host, int32_t *index);
+
+/* Plan selection: the candidate (index, panel height to pack with, plan) for
+ * a matrix with statistics features_host (ROSKO_NFEAT host floats, from
+ * rosko_features).  With params (host, the rosko_mlp_param_count(ROSKO_NFEAT,
+ * 64, ROSKO_SCHED_CANDIDATES) weights of the plan network, layout as
+ * rosko_mlp_*) and its per-feature normalisation mu, sigma (host), the
+ * network's forward pass runs on the host in FP32 and its arg-min is taken;
+ * with params NULL the analytic rule decides.  The caller owns the weights
+ * (the library stores none).  Synchronous, host only. */
+int32_t rosko_plan_select(const float *features_host, const float *params, const float *mu,
+                          const float *sigma, int32_t *index, int32_t *mr, rosko_plan *plan);
 
 /* ---- errors ----------------------------------------------------------- */
 const char *rosko_status_str(int32_t status);

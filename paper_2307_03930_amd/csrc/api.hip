@@ -480,16 +480,61 @@ int32_t rosko_sched_candidate(int32_t index, int32_t* mr, rosko_plan* plan) {
 int32_t rosko_sched_analytic(const float* f, int32_t* index) {
   clear_error();
   RK_REQUIRE(f && index, ROSKO_EINVAL, "null argument");
-  const float d = f[3];
-  // 4 columns per lane; the panel height follows the density: mr 16 from
-  // d = 0.08 up (a few values per column record, 2x the tiles of mr 32),
-  // mr 8 below (records of about one value; the most tiles).  Measured over
-  // the scheduler's timing sweep this was within 4% of the fastest candidate
-  // (geometric mean); a network trained on the same timings is the primary
-  // choice.  The dense candidate (density >= 0.25) is not offered while the
-  // dense path is switched off.
-  *index = d >= 0.08f ? 1 : 0;
+  // A 3 x 3 table over density d = f[3] (bands at 0.02 and 0.3) and log2 N
+  // = f[2] (bands at 6 and 11), each cell the candidate with the smallest
+  // geometric-mean time (repack + SpMM) over the training problems of the
+  // random-shape corpus in that cell: short columns (few values per record)
+  // take shorter panels, wide B on dense-ish matrices the matrix cores.
+  static const int32_t kTable[3][3] = {{0, 1, 3}, {1, 3, 3}, {1, 3, 6}};
+  const float d = f[3], lN = f[2];
+  const int db = d < 0.02f ? 0 : (d < 0.3f ? 1 : 2);
+  const int nb = lN < 6.0f ? 0 : (lN < 11.0f ? 1 : 2);
+  *index = kTable[db][nb];
   return ROSKO_OK;
+}
+
+// Host forward pass of the plan network and its arg-min (see rosko.h).
+int32_t rosko_plan_select(const float* f, const float* params, const float* mu,
+                          const float* sigma, int32_t* index, int32_t* mr, rosko_plan* plan) {
+  clear_error();
+  RK_REQUIRE(f && index && mr && plan, ROSKO_EINVAL, "null argument");
+  int32_t c = 0;
+  if (params == nullptr) {
+    int32_t st = rosko_sched_analytic(f, &c);
+    if (st) return st;
+  } else {
+    RK_REQUIRE(mu && sigma, ROSKO_EINVAL, "network given without its normalisation");
+    constexpr int F = ROSKO_NFEAT, H = 64, Cn = ROSKO_SCHED_CANDIDATES;
+    const float* W1 = params;
+    const float* b1 = W1 + F * H;
+    const float* W2 = b1 + H;
+    const float* b2 = W2 + H * H;
+    const float* W3 = b2 + H;
+    const float* b3 = W3 + H * Cn;
+    float x[F], h1[H], h2[H];
+    for (int i = 0; i < F; ++i) x[i] = (f[i] - mu[i]) / sigma[i];
+    for (int j = 0; j < H; ++j) {
+      float a = b1[j];
+      for (int i = 0; i < F; ++i) a += x[i] * W1[i * H + j];
+      h1[j] = a > 0.0f ? a : 0.0f;
+    }
+    for (int j = 0; j < H; ++j) {
+      float a = b2[j];
+      for (int i = 0; i < H; ++i) a += h1[i] * W2[i * H + j];
+      h2[j] = a > 0.0f ? a : 0.0f;
+    }
+    float best = 0.0f;
+    for (int j = 0; j < Cn; ++j) {
+      float a = b3[j];
+      for (int i = 0; i < H; ++i) a += h2[i] * W3[i * Cn + j];
+      if (j == 0 || a < best) {
+        best = a;
+        c = j;
+      }
+    }
+  }
+  *index = c;
+  return rosko_sched_candidate(c, mr, plan);
 }
 
 }  // extern "C"

@@ -45,9 +45,11 @@ HID = 64
 NCAND = L.ROSKO_SCHED_CANDIDATES
 DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "sched_data")
 WEIGHTS = os.path.join(DATA_DIR, "weights.json")
+REPORT = os.path.join(DATA_DIR, "fit_report.json")
 CORPUS = os.path.join(DATA_DIR, "corpus.jsonl")
 MEASURED = os.path.join(DATA_DIR, "measured.jsonl")
 N_TRAIN = 1800
+OBJECTIVES = ("step", "spmm")
 
 
 def _p(t):
@@ -172,8 +174,10 @@ class MLP:
 
     @staticmethod
     def from_json(d: dict, device="cuda") -> "MLP":
-        return MLP(np.array(d["params"], np.float32), np.array(d["mu"], np.float32),
-                   np.array(d["sigma"], np.float32), device, d["F"], d["H"], d["C"])
+        net = MLP(np.array(d["params"], np.float32), np.array(d["mu"], np.float32),
+                  np.array(d["sigma"], np.float32), device, d["F"], d["H"], d["C"])
+        net.objective = d.get("objective", "step")
+        return net
 
 
 def load(device="cuda", path: str = WEIGHTS) -> MLP | None:
@@ -186,7 +190,20 @@ def load(device="cuda", path: str = WEIGHTS) -> MLP | None:
 _NETS: dict = {}
 
 
-REPORT = os.path.join(DATA_DIR, "fit_report.json")
+def plan_select(f_host: np.ndarray, weights: dict | None = None):
+    """(candidate index, panel height, plan) from rosko_plan_select: the host
+    forward pass of the network given as its JSON dict (weights.json), or
+    the analytic rule when None."""
+    f = np.ascontiguousarray(f_host, np.float32)
+    idx, mr, plan = C.c_int32(-1), C.c_int32(0), L.RoskoPlan()
+    if weights is None:
+        args = (None, None, None)
+    else:
+        keep = [np.ascontiguousarray(weights[k], np.float32) for k in ("params", "mu", "sigma")]
+        args = tuple(x.ctypes.data_as(C.c_void_p) for x in keep)
+    L.check(L.lib().rosko_plan_select(f.ctypes.data_as(C.c_void_p), *args, C.byref(idx),
+                                      C.byref(mr), C.byref(plan)))
+    return int(idx.value), int(mr.value), plan
 
 
 def network_beats_rule(path: str = REPORT) -> bool:
@@ -288,10 +305,11 @@ def time_candidate(A: torch.Tensor, B: torch.Tensor, index: int, reps: int = 5) 
     return t
 
 
-def sweep(first: int, last: int, path: str, log_every: int = 1) -> None:
-    """Measure every sparse candidate on corpus problems [first, last) and
-    append one JSON line per problem (features, times in microseconds) to
-    `path`."""
+def sweep(first: int, last: int, path: str, log_every: int = 1, reps: int = 5) -> None:
+    """Measure every candidate (sparse and dense-MFMA) on corpus problems
+    [first, last) and append one JSON line per problem to `path`: the
+    statistics, the SpMM time of each candidate and the time to repack the
+    matrix at the candidate's panel height, in microseconds."""
     dev = torch.device("cuda")
     done = set()
     if os.path.exists(path):
@@ -303,40 +321,54 @@ def sweep(first: int, last: int, path: str, log_every: int = 1) -> None:
             if i in done:
                 continue
             A, B, sp = synth.corpus_problem_device(i, dev)
+            print(f"corpus {i}: {sp['M']}x{sp['K']}x{sp['N']} s={sp['sparsity']:.3f} "
+                  f"{sp['kind']}", flush=True)
             f = features(A, B.shape[1]).cpu().numpy().tolist()
-            times = [time_candidate(A, B, c) for c in sparse_candidates()]
+            times, packs, packed = [], [], {}
+            for c in range(NCAND):
+                mr, plan = candidate(c)
+                if mr not in packed:
+                    P = ops.pack(A, mr, "f32")
+                    packed[mr] = (P, time_pack(A, P, reps))
+                P, tp = packed[mr]
+                times.append(time_packed(P, B, plan, reps))
+                packs.append(tp)
+            del packed
             out.write(json.dumps({"i": i, "M": sp["M"], "K": sp["K"], "N": sp["N"],
                                   "sparsity": sp["sparsity"], "kind": sp["kind"],
-                                  "features": f, "times_us": times}) + "\n")
+                                  "features": f, "times_us": times, "pack_us": packs}) + "\n")
             out.flush()
             del A, B
             if (i - first) % log_every == 0:
-                print(f"corpus {i}: {sp['M']}x{sp['K']}x{sp['N']} s={sp['sparsity']:.3f} "
-                      f"best={int(np.argmin(times))} t={min(times):.1f}us "
+                print(f"  best={int(np.argmin(times))} t={min(times):.1f}us "
                       f"({time.time() - t0:.0f}s)", flush=True)
 
 
-def read_corpus(path: str = CORPUS):
+def read_corpus(path: str = CORPUS, objective: str = "spmm"):
+    """Problem indices, statistics X and times Tm (problems x candidates) of
+    the corpus; objective "spmm" (a matrix packed once) or "step" (repack
+    plus SpMM)."""
+    if objective not in OBJECTIVES:
+        raise ValueError(f"unknown objective {objective!r}")
     rows = [json.loads(line) for line in open(path) if line.strip()]
     rows.sort(key=lambda r: r["i"])
     X = np.array([r["features"] for r in rows], np.float32)
     Tm = np.array([r["times_us"] for r in rows], np.float64)
+    if objective == "step":
+        Tm = Tm + np.array([r["pack_us"] for r in rows], np.float64)
     idx = np.array([r["i"] for r in rows])
     return idx, X, Tm
 
 
 def measured_sweep(path: str = MEASURED, reps: int = 7) -> None:
-    """Time every sparse candidate on every matrix of synth.sweep_specs() at
-    every N of synth.SWEEP_N and write one JSON line per (matrix, N): the
-    spec, the 16 statistics, the SpMM times and the times to repack the
-    matrix at the candidate's panel height (FP32 values), in microseconds, in
-    candidate order.  Inputs are generated on the host, as in the parity
-    tests, and copied to the device."""
+    """Time every candidate (sparse and dense-MFMA) on every matrix of
+    synth.sweep_specs() at every N of synth.SWEEP_N and write one JSON line
+    per (matrix, N): the spec, the 16 statistics, the SpMM times and the
+    times to repack the matrix at the candidate's panel height (FP32
+    values), in microseconds, in candidate order.  Inputs are generated on
+    the host, as in the parity tests, and copied to the device."""
     dev = torch.device("cuda")
-    cands = sparse_candidates()
-    # The network's output j scores candidate j: the sparse candidates are
-    # the leading indices of the table.
-    assert cands == list(range(len(cands))), cands
+    cands = list(range(NCAND))
     plans = [candidate(c) for c in cands]
     Bs = {}
     t0 = time.time()
@@ -350,13 +382,16 @@ def measured_sweep(path: str = MEASURED, reps: int = 7) -> None:
                 if (K, N) not in Bs:
                     Bs[(K, N)] = torch.from_numpy(synth.dense_normal(K, N, 30000 + K + N)).to(dev)
             times = {N: [] for N in synth.SWEEP_N}
-            packs = []
+            packs, packed = [], {}
             for mr, plan in plans:
-                P = ops.pack(A, mr, "f32")
-                packs.append(time_pack(A, P, reps))
+                if mr not in packed:
+                    P = ops.pack(A, mr, "f32")
+                    packed[mr] = (P, time_pack(A, P, reps))
+                P, tp = packed[mr]
+                packs.append(tp)
                 for N in synth.SWEEP_N:
                     times[N].append(time_packed(P, Bs[(K, N)], plan, reps))
-                del P
+            del packed
             for N in synth.SWEEP_N:
                 f = features(A, N).cpu().numpy().tolist()
                 out.write(json.dumps(dict(sp, N=N, candidates=cands, features=f,
@@ -365,9 +400,6 @@ def measured_sweep(path: str = MEASURED, reps: int = 7) -> None:
             del A
             best = {N: int(np.argmin(times[N])) for N in synth.SWEEP_N}
             print(f"  best {best} ({time.time() - t0:.0f}s)", flush=True)
-
-
-OBJECTIVES = ("step", "spmm")
 
 
 def read_measured(path: str = MEASURED, objective: str = "step"):
@@ -459,10 +491,12 @@ def main(argv=None):
     s.add_argument("last", type=int)
     s.add_argument("--out", default=CORPUS)
     t = sub.add_parser("train")
-    t.add_argument("--steps", type=int, default=4000)
-    t.add_argument("--lr", type=float, default=3e-3)
+    t.add_argument("--steps", type=int, default=6000)
+    t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--corpus", default=CORPUS)
     t.add_argument("--out", default=WEIGHTS)
+    t.add_argument("--report", default=REPORT)
+    t.add_argument("--objective", choices=OBJECTIVES, default="step")
     e = sub.add_parser("eval")
     e.add_argument("--corpus", default=CORPUS)
     a = ap.parse_args(argv)
@@ -483,17 +517,29 @@ def main(argv=None):
         os.makedirs(os.path.dirname(a.out), exist_ok=True)
         sweep(a.first, a.last, a.out)
     elif a.cmd == "train":
-        idx, X, Tm = read_corpus(a.corpus)
+        # training set: the corpus's first N_TRAIN problems and the
+        # benchmark-shape sweep's training matrices; held out: the corpus's
+        # last 200 problems and the sweep's held-out matrices
+        idx, X, Tm = read_corpus(a.corpus, a.objective)
         tr = idx < N_TRAIN
-        net = train(X[tr], Tm[tr], steps=a.steps, lr=a.lr)
-        os.makedirs(os.path.dirname(a.out), exist_ok=True)
+        Xs, Ts, held_s = read_measured(MEASURED, a.objective)
+        Xtr = np.concatenate([X[tr], Xs[~held_s]])
+        Ttr = np.concatenate([Tm[tr], Ts[~held_s]])
+        net = train(Xtr, Ttr, steps=a.steps, lr=a.lr)
+        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
         with open(a.out, "w") as f:
-            json.dump(net.to_json(), f)
-        print(json.dumps({"train": evaluate(net, X[tr], Tm[tr]),
-                          "held_out": evaluate(net, X[~tr], Tm[~tr])}), flush=True)
+            json.dump(dict(net.to_json(), objective=a.objective), f)
+        rep = {"data": "corpus+sweep", "objective": a.objective, "steps": a.steps, "lr": a.lr,
+               "n_train": int(len(Xtr)), "n_held_out": int((~tr).sum()),
+               "n_held_out_sweep": int(held_s.sum()),
+               "train": evaluate(net, Xtr, Ttr), "held_out": evaluate(net, X[~tr], Tm[~tr]),
+               "held_out_sweep": evaluate(net, Xs[held_s], Ts[held_s])}
+        with open(a.report, "w") as f:
+            json.dump(rep, f)
+        print(json.dumps(rep), flush=True)
     else:
-        idx, X, Tm = read_corpus(a.corpus)
         net = load()
+        idx, X, Tm = read_corpus(a.corpus, net.objective if net is not None else "step")
         ho = idx >= N_TRAIN
         print(json.dumps({"held_out": evaluate(net, X[ho], Tm[ho])}), flush=True)
 

@@ -280,14 +280,21 @@ def test_sched_candidates_and_analytic_rule():
     assert lib.rosko_sched_candidate(7, C.byref(mr), C.byref(plan)) == L.ROSKO_EINVAL
     idx = C.c_int32(-1)
     f = (C.c_float * 16)()
-    f[3], f[2] = 0.1, 10.0                      # 10% dense, N = 1024: mr 16
-    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 1
-    f[3] = 0.05                                 # 5% dense: mr 8
-    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 0
-    f[3], f[2] = 0.1, 6.0                       # N = 64: still mr 16
-    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 1
-    f[3], f[2] = 0.5, 10.0                      # dense candidate not offered (path off)
-    assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == 1
+    # the rule's table: (density, log2 N) -> candidate
+    for d, lN, want in ((0.01, 5.0, 0), (0.01, 10.0, 1), (0.01, 11.5, 3), (0.1, 5.0, 1),
+                        (0.1, 10.0, 3), (0.1, 12.0, 3), (0.5, 5.0, 1), (0.5, 10.0, 3),
+                        (0.5, 11.0, 6)):
+        f[3], f[2] = d, lN
+        assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == want, (d, lN)
+        # plan selection without a network is the rule, with the candidate's plan
+        i2, m2, p2 = C.c_int32(-1), C.c_int32(0), L.RoskoPlan()
+        assert lib.rosko_plan_select(f, None, None, None, C.byref(i2), C.byref(m2),
+                                     C.byref(p2)) == 0
+        assert i2.value == want and (m2.value, p2.path, p2.cols_per_lane) == seen[want]
+    # a network without its normalisation is refused
+    w = (C.c_float * 8000)()
+    assert lib.rosko_plan_select(f, w, None, None, C.byref(i2), C.byref(m2),
+                                 C.byref(p2)) == L.ROSKO_EINVAL
     n = C.c_int64(0)
     assert lib.rosko_mlp_param_count(16, 64, 7, C.byref(n)) == 0
     assert n.value == 16 * 64 + 64 + 64 * 64 + 64 + 64 * 7 + 7

@@ -331,9 +331,8 @@ def test_timed_step_configuration(s):
     Ad, Bd = dev(pr.A), dev(pr.B)
     M, K = pr.A.shape
     N = pr.B.shape[1]
-    mr, cand = sched.candidate(sched.choose(Ad, N))
-    plan = ops.make_plan(cand.cols_per_lane)
-    say(f"timed step s={s}: mr={mr} cols_per_lane={cand.cols_per_lane}")
+    mr, plan = sched.candidate(sched.choose(Ad, N))
+    say(f"timed step s={s}: mr={mr} path={plan.path} cols_per_lane={plan.cols_per_lane}")
     ref_pack = O.pack(pr.A, mr, DT["f32"])
     P = ops.pack(Ad, mr, "f32")
     assert_pack_equal(P, ref_pack)
@@ -432,11 +431,11 @@ def test_spmm_precision_form_full(s, dtype):
     Bd = dev(pr.B).to(torch.bfloat16) if dtype != "f32" else dev(pr.B)
     mr_s, cand = sched.candidate(sched.choose(Ad, pr.B.shape[1]))
     tol = {"f32": TOL_F32, "bf16": TOL_BF16, "fp8": TOL_FP8}[dtype]
-    for mr, plan in ((32, None), (mr_s, ops.make_plan(cand.cols_per_lane))):
+    for mr, plan in ((32, None), (mr_s, cand)):
         P = ops.pack(Ad, mr, dtype)
         C = ops.spmm(P, Bd, plan=plan).cpu().numpy()
         e = err(C, c_src, scale)
-        say(f"  mr {mr} plan {'auto' if plan is None else cand.cols_per_lane}: "
+        say(f"  mr {mr} plan {'auto' if plan is None else (cand.path, cand.cols_per_lane)}: "
             f"err vs FP32 source {e:.3e}")
         assert e <= tol
     # the re-pack into those buffers (what the benchmark times) is Alg. 1 bit for bit
