@@ -224,6 +224,56 @@ def run_backward(args):
           flush=True)
 
 
+def run_training(args):
+    """Pruned training with on-the-fly repacking (the training use of the
+    method): one SGD step of the two-layer chain of the CNN layer -- a 3x3
+    convolution 256 -> 256 channels (W1 256 x 2304) on the 56 x 56 im2col
+    activations (2304 x 3136), ReLU, a 1x1 convolution 256 -> 256 (W2) --
+    with both weights repacked every step, at several sparsities of both
+    weights; beside it the same step with dense FP32 GEMMs (torch)."""
+    import numpy as np
+    import torch
+    from paper_2307_03930_amd import synth, training
+    torch.backends.cuda.matmul.allow_tf32 = False
+    dev = torch.device("cuda:0")
+    pr = synth.cnn_layer(0.9)
+    X = torch.from_numpy(pr.B).to(dev)
+    g = synth.rng(730)
+    W1_0 = torch.from_numpy((g.standard_normal((256, 2304)) * 0.02).astype(np.float32)).to(dev)
+    W2_0 = torch.from_numpy((g.standard_normal((256, 256)) * 0.06).astype(np.float32)).to(dev)
+    T = torch.from_numpy(synth.dense_normal(256, 3136, 731)).to(dev)
+
+    def dense_step(W1, W2):
+        C2 = W2 @ torch.relu(W1 @ X)
+        loss = ((C2 - T) ** 2).mean()
+        loss.backward()
+        with torch.no_grad():
+            for W in (W1, W2):
+                W -= 1e-3 * W.grad
+                W.grad = None
+
+    Wd1, Wd2 = W1_0.clone().requires_grad_(True), W2_0.clone().requires_grad_(True)
+    dense_ms = _time_us(lambda: dense_step(Wd1, Wd2), 20) / 1e3
+    rows = []
+    for s in (0.75, 0.80, 0.90, 0.95):
+        W1, W2 = W1_0.clone(), W2_0.clone()
+        training.magnitude_prune(W1, s)
+        training.magnitude_prune(W2, s)
+        chain = training.PrunedChain(W1, W2, 16)
+        step_ms = _time_us(lambda: chain.step(X, T, 1e-3), 20) / 1e3
+        pack_ms = _time_us(lambda: (chain.pw1.repack(chain.W1.detach()),
+                                    chain.pw2.repack(chain.W2.detach())), 20) / 1e3
+        chain.pw1.check()
+        chain.pw2.check()
+        rows.append({"sparsity": s, "step_ms": round(step_ms, 4), "repack_ms": round(pack_ms, 4),
+                     "speedup_vs_dense": round(dense_ms / step_ms, 2)})
+    print(json.dumps({"workload": "pruned training step with repacking: W1 256x2304 (3x3 conv "
+                                  "256->256) on im2col 2304x3136, ReLU, W2 256x256 (1x1 conv), "
+                                  "MSE loss, SGD; mr 16; FP32",
+                      "unit": "ms", "dense_fp32_step_ms": round(dense_ms, 4),
+                      "data": "synthetic", "per_sparsity": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,7 +289,8 @@ def main():
     ap.add_argument("--mr", type=int, default=None,
                     help="panel height for every matrix (default: the library's analytic "
                          "plan rule picks it per matrix)")
-    ap.add_argument("--workload", choices=("cnn", "precision", "backward"), default="cnn",
+    ap.add_argument("--workload", choices=("cnn", "precision", "backward", "training"),
+                    default="cnn",
                     help="cnn: the pruned-CNN sweep (the headline line); precision: the "
                          "BF16 / FP8 value forms at 4096x4096; backward: forward + backward "
                          "at 1024x4096")
@@ -254,6 +305,8 @@ def main():
         return run_precision(args)
     if args.workload == "backward":
         return run_backward(args)
+    if args.workload == "training":
+        return run_training(args)
 
     import numpy as np
     import torch

@@ -250,9 +250,15 @@ int32_t rosko_spmm_noalloc(const rosko_packed *A, const void *B, int32_t b_dtype
  * gradient; no entry at or beyond dA_cap (or A->nnz_cap) is written, and
  * every index read from A's packed arrays is clamped into A's capacities,
  * so a pack that overflowed its buffers cannot move an access outside them.
- * At may be NULL when dB is.  ws: device workspace of the size
- * rosko_spmm_backward_workspace_size reports.  Asynchronous. */
-int32_t rosko_spmm_backward_workspace_size(const rosko_packed *At, int64_t N, size_t *bytes);
+ * At may be NULL when dB is.  ws: device workspace (256-byte aligned) of
+ * at least the size rosko_spmm_backward_workspace_size reports for the same
+ * A (NULL when dA is not wanted), At (NULL when dB is not wanted) and N: the
+ * K-split partials of dB's SpMM, and for N > 1024 with panels of up to 16
+ * rows the SDDMM's partial dot products over 1024-column chunks of N
+ * (4 * ceil(N / 1024) * A->nnz_cap bytes), added in chunk order into dA.
+ * A smaller ws returns ROSKO_ESMALLBUF.  Asynchronous. */
+int32_t rosko_spmm_backward_workspace_size(const rosko_packed *A, const rosko_packed *At,
+                                           int64_t N, size_t *bytes);
 int32_t rosko_spmm_backward(const rosko_packed *A, const rosko_packed *At, const float *B,
                             int64_t ldb, const float *dC, int64_t lddc, int64_t N, float *dB,
                             int64_t lddb, float *dA_val, int64_t dA_cap, void *ws,
@@ -352,7 +358,7 @@ int32_t rosko_plan_select(const float *features_host, const float *params, const
 /* ---- errors ----------------------------------------------------------- */
 const char *rosko_status_str(int32_t status);
 const char *rosko_last_error(void);   /* per host thread; "" if none */
-int32_t rosko_abi_version(void);      /* 5 */
+int32_t rosko_abi_version(void);      /* 6 */
 
 #ifdef __cplusplus
 }

@@ -85,7 +85,8 @@ SIGNATURES = {
                           C.POINTER(RoskoPlan), _P, _SZ, _P]),
     "rosko_spmm_noalloc": (_I32, [C.POINTER(RoskoPacked), _P, _I32, _I64, _I64, _P, _I64, _I32,
                                   C.POINTER(RoskoPlan), _P]),
-    "rosko_spmm_backward_workspace_size": (_I32, [C.POINTER(RoskoPacked), _I64,
+    "rosko_spmm_backward_workspace_size": (_I32, [C.POINTER(RoskoPacked),
+                                                  C.POINTER(RoskoPacked), _I64,
                                                   C.POINTER(_SZ)]),
     "rosko_spmm_backward": (_I32, [C.POINTER(RoskoPacked), C.POINTER(RoskoPacked), _P, _I64,
                                    _P, _I64, _I64, _P, _I64, _P, _I64, _P, _SZ, _P]),

@@ -4,6 +4,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace rosko {
@@ -97,7 +99,7 @@ static int32_t check_packed_for_read(const rosko_packed* A) {
 
 extern "C" {
 
-int32_t rosko_abi_version(void) { return 5; }
+int32_t rosko_abi_version(void) { return 6; }
 
 const char* rosko_last_error(void) { return g_err; }
 
@@ -297,16 +299,26 @@ int32_t rosko_spmm(const rosko_packed* A, const void* B, int32_t b_dtype, int64_
                             ws_bytes, static_cast<hipStream_t>(stream));
 }
 
-int32_t rosko_spmm_backward_workspace_size(const rosko_packed* At, int64_t N, size_t* bytes) {
+int32_t rosko_spmm_backward_workspace_size(const rosko_packed* A, const rosko_packed* At,
+                                           int64_t N, size_t* bytes) {
   clear_error();
   RK_REQUIRE(bytes != nullptr, ROSKO_EINVAL, "bytes is null");
   *bytes = 0;
-  if (At == nullptr) return ROSKO_OK;
-  RK_REQUIRE(At->M >= 0 && At->K >= 0 && N >= 0, ROSKO_EINVAL, "negative size");
-  int32_t st = check_mr(At->mr);
-  if (st) return st;
-  rosko_plan p = auto_plan(At, N);
-  *bytes = spmm_ws_bytes(At, N, p);
+  RK_REQUIRE(N >= 0, ROSKO_EINVAL, "negative N");
+  int32_t st;
+  if (At != nullptr) {
+    RK_REQUIRE(At->M >= 0 && At->K >= 0, ROSKO_EINVAL, "negative size");
+    if ((st = check_mr(At->mr))) return st;
+    rosko_plan p = auto_plan(At, N);
+    *bytes = spmm_ws_bytes(At, N, p);
+  }
+  if (A != nullptr) {
+    RK_REQUIRE(A->M >= 0 && A->K >= 0 && A->nnz_cap >= 0, ROSKO_EINVAL, "negative size");
+    if ((st = check_mr(A->mr))) return st;
+    // dB's SpMM and dA's SDDMM run one after the other on the stream: they
+    // share the workspace
+    *bytes = std::max(*bytes, sddmm_ws_bytes(A, N));
+  }
   return ROSKO_OK;
 }
 
@@ -341,7 +353,9 @@ int32_t rosko_spmm_backward(const rosko_packed* A, const rosko_packed* At, const
     RK_REQUIRE(B != nullptr || A->K == 0 || N == 0, ROSKO_EINVAL, "B is null");
     RK_REQUIRE(dA_cap >= 0, ROSKO_EINVAL, "negative dA capacity");
     (void)hipGetLastError();
-    if ((st = launch_sddmm(A, dC, lddc, B, ldb, N, dA_val, dA_cap, s))) return st;
+    if ((st = launch_sddmm(A, dC, lddc, B, ldb, N, dA_val, dA_cap, static_cast<float*>(ws),
+                             ws_bytes, s)))
+      return st;
   }
   return ROSKO_OK;
 }

@@ -148,8 +148,11 @@ int32_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, flo
 int32_t launch_argmin(const float* Y, int64_t Bn, int32_t C, int32_t* out, hipStream_t s);
 
 // ---------------------------------------------------------------- SDDMM
+// Workspace of the SDDMM (partial dot products over column chunks of N).
+size_t sddmm_ws_bytes(const rosko_packed* A, int64_t N);
 int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const float* B,
-                     int64_t ldb, int64_t N, float* dA_val, int64_t dA_cap, hipStream_t s);
+                     int64_t ldb, int64_t N, float* dA_val, int64_t dA_cap, float* ws,
+                     size_t ws_bytes, hipStream_t s);
 int32_t launch_scatter_dense(const rosko_packed* A, const float* vals, int64_t n_vals,
                              float* out, int64_t ldo, hipStream_t s);
 

@@ -3,8 +3,10 @@
 // mask), and the result is written in A's packed order so it lines up with
 // the packed values.
 //
-// General kernel (any mr, N): a workgroup takes one panel; its wavefronts
-// stride over the panel's kept columns.  For a column the wave keeps the selected B row in registers
+// Panels of up to 16 rows (the heights the training layers use) take the
+// LDS kernel below, over column chunks of N.  The general kernel (any mr, N)
+// gives a workgroup one panel; its wavefronts stride over the panel's kept
+// columns.  For a column the wave keeps the selected B row in registers
 // (lanes over N) and reuses it for every value of the column, which is the
 // column-wise reuse the packed format exposes; each value's dot product is
 // finished with a wave reduction.
@@ -84,39 +86,47 @@ __device__ __forceinline__ float wave_sum_f32(float x) {
 }
 #undef RK_DPPF
 
-// Panels of at most 8 rows and N <= 256 * VQ <= 1024.  The workgroup puts its
-// panel's dC rows in LDS once; each of its wavefronts takes a contiguous
+// Panels of at most ROWS (8 or 16) rows, one chunk of RW = 256 * VQ <= 1024
+// columns of dC and B per workgroup.  The workgroup puts its panel's dC rows
+// (that column chunk) in LDS once; each of its wavefronts takes a contiguous
 // range of the panel's kept columns (the panel's columns are also split over
 // kSdLdsG workgroups).  The column metadata and in-panel rows (packed as
 // bytes) come in 64 columns at a time, one column per lane.  Lane l holds
-// B columns 4l..4l+3 (+256 v) of a row as float4s; the B rows of the next
+// B columns 4l..4l+3 (+256 v) of the chunk as float4s; the B rows of the next
 // kSdDepth columns are in flight while a column is computed.  For each of a
-// column's values the wave forms the dot product with the LDS row and
-// reduces it across the wavefront.
-constexpr int kSdLdsRows = 8;
+// column's values the wave forms the dot product with the LDS row over the
+// chunk and reduces it across the wavefront.  With one chunk (N <= RW) the
+// result is dA; with several, each chunk writes its partial dot products to
+// out + chunk * nz_lim and k_sddmm_sum adds them in chunk order.
 constexpr int kSdLdsG = 4;       // workgroups per panel
 constexpr int kSdDepth = 4;      // B rows in flight per wavefront
+constexpr int kSdChunk = 1024;   // widest column chunk (VQ = 4)
 
-template <int VQ>
+template <int ROWS, int VQ>
 __global__ void __launch_bounds__(64 * kSdW)
 k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict__ col_ind,
             const int32_t* __restrict__ col_nnz, const int64_t* __restrict__ col_ptr,
-            const uint8_t* __restrict__ loc, int64_t M, int64_t K, int32_t mr,
+            const uint8_t* __restrict__ loc, int64_t M, int64_t K, int32_t mr, int32_t n_panels,
             const float* __restrict__ dC, int64_t lddc, const float* __restrict__ B,
             int64_t ldb, int64_t N, bool vec, int64_t ncols_lim, int64_t nz_lim,
-            float* __restrict__ dA) {
+            float* __restrict__ out) {
   constexpr int RW = 256 * VQ;                    // LDS row width (floats)
-  __shared__ float4 sdc4[kSdLdsRows * RW / 4];
+  constexpr int RWD = ROWS / 4;                   // dwords of row bytes per column
+  __shared__ float4 sdc4[ROWS * RW / 4];
   float* sdc = reinterpret_cast<float*>(sdc4);
-  const int64_t p = blockIdx.x / kSdLdsG;
-  const int g = blockIdx.x % kSdLdsG;
+  const int64_t chunk = blockIdx.x / ((int64_t)n_panels * kSdLdsG);
+  const int64_t pg = blockIdx.x % ((int64_t)n_panels * kSdLdsG);
+  const int64_t p = pg / kSdLdsG;
+  const int g = (int)(pg % kSdLdsG);
+  const int64_t n0 = chunk * RW;
+  float* dst = out + chunk * nz_lim;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t r0 = p * mr;
   const int rows = (int)min((int64_t)mr, M - r0);
-  for (int idx = threadIdx.x; idx < rows * RW; idx += 64 * kSdW) {
+  for (int idx = threadIdx.x; idx < ROWS * RW; idx += 64 * kSdW) {
     const int r = idx / RW, n = idx - r * RW;
-    sdc[idx] = n < N ? dC[(r0 + r) * lddc + n] : 0.0f;
+    sdc[idx] = (r < rows && n0 + n < N) ? dC[(r0 + r) * lddc + n0 + n] : 0.0f;
   }
   __syncthreads();
   // clamped as in k_sddmm
@@ -125,13 +135,13 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
   const int64_t parts = (int64_t)kSdLdsG * kSdW, part = (int64_t)g * kSdW + w;
   const int64_t a = c_lo + (c_hi - c_lo) * part / parts;
   const int64_t e = c_lo + (c_hi - c_lo) * (part + 1) / parts;
-  // B row k at this lane's columns; vec: aligned float4 loads, else element
-  // loads (columns past N read as 0 and meet zero LDS entries)
+  // B row k at this lane's columns of the chunk; vec: aligned float4 loads,
+  // else element loads (columns past N read as 0 and meet zero LDS entries)
   auto load_b = [&](int64_t k, float4* b) {
     const float* row = B + k * ldb;
 #pragma unroll
     for (int v = 0; v < VQ; ++v) {
-      const int64_t col = 4 * lane + 256 * v;
+      const int64_t col = n0 + 4 * lane + 256 * v;
       if (vec && col < N) {
         b[v] = *reinterpret_cast<const float4*>(row + col);
       } else {
@@ -145,15 +155,16 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
     const bool valid = c < e;
     const int kk = valid ? (int)min(max((int64_t)col_ind[c], (int64_t)0), K - 1) : 0;
     const int64_t zz = valid ? max(col_ptr[c], (int64_t)0) : 0;
-    const int nn = valid ? (int)max((int64_t)0, min((int64_t)min(col_nnz[c], kSdLdsRows),
+    const int nn = valid ? (int)max((int64_t)0, min((int64_t)min(col_nnz[c], ROWS),
                                                     nz_lim - zz))
                          : 0;
-    uint32_t rlo = 0, rhi = 0;                  // in-panel rows of the column, bytes
+    uint32_t rw[RWD];                           // in-panel rows of the column, bytes
 #pragma unroll
-    for (int t = 0; t < kSdLdsRows; ++t) {
+    for (int q = 0; q < RWD; ++q) rw[q] = 0u;
+#pragma unroll
+    for (int t = 0; t < ROWS; ++t) {
       const uint32_t r = t < nn ? loc[zz + t] : 0u;
-      if (t < 4) rlo |= r << (8 * t);
-      else rhi |= r << (8 * (t - 4));
+      rw[t / 4] |= r << (8 * (t % 4));
     }
     const int cnt = (int)min<int64_t>(64, e - cb);
     float4 bq[kSdDepth][VQ];
@@ -168,10 +179,15 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
           const int n = __builtin_amdgcn_readlane(nn, j);
           const int64_t z = ((int64_t)__builtin_amdgcn_readlane((int)(zz >> 32), j) << 32) |
                             (uint32_t)__builtin_amdgcn_readlane((int)zz, j);
-          const uint32_t lo = __builtin_amdgcn_readlane(rlo, j);
-          const uint32_t hi = __builtin_amdgcn_readlane(rhi, j);
+          uint32_t rj[RWD];
+#pragma unroll
+          for (int q = 0; q < RWD; ++q) rj[q] = __builtin_amdgcn_readlane(rw[q], j);
           for (int t = 0; t < n; ++t) {
-            const int r = (int)(((t < 4 ? lo : hi) >> (8 * (t & 3))) & 7u);   // rows < 8
+            uint32_t word = rj[0];
+#pragma unroll
+            for (int q = 1; q < RWD; ++q)
+              if (t / 4 == q) word = rj[q];
+            const int r = (int)((word >> (8 * (t & 3))) & (uint32_t)(ROWS - 1));
             const float4* row = sdc4 + (r * RW) / 4 + lane;
             float acc = 0.0f;
 #pragma unroll
@@ -183,7 +199,7 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
               acc = fmaf(x.w, y.w, acc);
             }
             const float sum = wave_sum_f32(acc);
-            if (lane == 0) dA[z + t] = sum;
+            if (lane == 0) dst[z + t] = sum;
           }
           // this slot's next column, kSdDepth ahead
           const int jn = j + kSdDepth;
@@ -194,28 +210,77 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
   }
 }
 
+// dA[z] = sum over chunks c (ascending) of part[c * stride + z], z < nz.
+__global__ void __launch_bounds__(256)
+k_sddmm_sum(const float* __restrict__ part, int32_t n_chunks, int64_t stride, int64_t nz,
+            float* __restrict__ dA) {
+  for (int64_t z = (int64_t)blockIdx.x * 256 + threadIdx.x; z < nz;
+       z += (int64_t)gridDim.x * 256) {
+    float acc = part[z];
+    for (int32_t c = 1; c < n_chunks; ++c) acc += part[c * stride + z];
+    dA[z] = acc;
+  }
+}
+
 }  // namespace
 
+size_t sddmm_ws_bytes(const rosko_packed* A, int64_t N) {
+  if (A == nullptr || A->mr > 16 || N <= kSdChunk) return 0;
+  return sizeof(float) * (size_t)ceil_div(N, kSdChunk) * (size_t)A->nnz_cap;
+}
+
 int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const float* B,
-                     int64_t ldb, int64_t N, float* dA_val, int64_t dA_cap, hipStream_t s) {
+                     int64_t ldb, int64_t N, float* dA_val, int64_t dA_cap, float* ws,
+                     size_t ws_bytes, hipStream_t s) {
   if (A->n_panels == 0 || A->K == 0) return ROSKO_OK;
   const int64_t ncols_lim = A->ncols_cap;
   const int64_t nz_lim = std::min(A->nnz_cap, dA_cap);
-  const int64_t vb = ceil_div(N, 64);
-  if (A->mr <= kSdLdsRows && N <= 1024 && (int64_t)A->n_panels * kSdLdsG <= INT32_MAX) {
-    const dim3 grid((unsigned)(A->n_panels * kSdLdsG));
+  if (A->mr <= 16) {
+    // LDS path: panels of up to 16 rows, N in chunks of up to 1024 columns
+    const int64_t n_chunks = ceil_div(std::max<int64_t>(N, 1), kSdChunk);
+    float* out = dA_val;
+    if (n_chunks > 1) {
+      const size_t need = sizeof(float) * (size_t)n_chunks * (size_t)A->nnz_cap;
+      if (ws == nullptr || ws_bytes < need) {
+        set_error("backward workspace %zu bytes < %zu (dA partials of %lld column chunks)",
+                  ws_bytes, need, (long long)n_chunks);
+        return ROSKO_ESMALLBUF;
+      }
+      out = ws;
+    }
+    const int64_t nb = (int64_t)A->n_panels * kSdLdsG * n_chunks;
+    if (nb > INT32_MAX) {
+      set_error("SDDMM grid too large");
+      return ROSKO_EUNSUPPORTED;
+    }
+    const dim3 grid((unsigned)nb);
     const bool vec = (N % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)B % 16 == 0);
-#define RK_SDL(VQ_)                                                                          \
-  hipLaunchKernelGGL(k_sddmm_lds<VQ_>, grid, dim3(64 * kSdW), 0, s, A->panel_col_ptr,        \
-                     A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M, A->K, A->mr, dC,      \
-                     lddc, B, ldb, N, vec, ncols_lim, nz_lim, dA_val)
-    if (N <= 256) RK_SDL(1);
-    else if (N <= 512) RK_SDL(2);
-    else RK_SDL(4);
+    const int64_t nz_out = n_chunks > 1 ? A->nnz_cap : nz_lim;
+#define RK_SDL(R_, VQ_)                                                                      \
+  hipLaunchKernelGGL((k_sddmm_lds<R_, VQ_>), grid, dim3(64 * kSdW), 0, s, A->panel_col_ptr,  \
+                     A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M, A->K, A->mr,          \
+                     A->n_panels, dC, lddc, B, ldb, N, vec, ncols_lim, nz_out, out)
+    const int64_t nc = n_chunks > 1 ? kSdChunk : N;   // columns of a chunk
+    if (A->mr <= 8) {
+      if (nc <= 256) RK_SDL(8, 1);
+      else if (nc <= 512) RK_SDL(8, 2);
+      else RK_SDL(8, 4);
+    } else {
+      if (nc <= 256) RK_SDL(16, 1);
+      else if (nc <= 512) RK_SDL(16, 2);
+      else RK_SDL(16, 4);
+    }
 #undef RK_SDL
     ROSKO_LAUNCH_CHECK("k_sddmm_lds");
+    if (n_chunks > 1) {
+      const int64_t blocks = std::min<int64_t>(ceil_div(std::max<int64_t>(nz_lim, 1), 256), 65536);
+      hipLaunchKernelGGL(k_sddmm_sum, dim3((unsigned)blocks), dim3(256), 0, s, ws,
+                         (int32_t)n_chunks, A->nnz_cap, nz_lim, dA_val);
+      ROSKO_LAUNCH_CHECK("k_sddmm_sum");
+    }
     return ROSKO_OK;
   }
+  const int64_t vb = ceil_div(N, 64);
 #define RK_SD(VB_)                                                                          \
   hipLaunchKernelGGL(k_sddmm<VB_>, dim3((unsigned)A->n_panels), dim3(64 * kSdW), 0, s,       \
                      A->panel_col_ptr, A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M,     \

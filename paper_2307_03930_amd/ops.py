@@ -234,13 +234,13 @@ def spmm_backward(P: PackedMatrix, Pt: PackedMatrix | None, B: torch.Tensor, dC:
     dA = torch.empty(max(P.nnz, 1), dtype=torch.float32, device=dC.device) if need_dA else None
     st = P.struct()
     stt = Pt.struct() if (Pt is not None and need_dB) else None
-    need = 0
-    if stt is not None:
-        n = C.c_size_t(0)
-        L.check(L.lib().rosko_spmm_backward_workspace_size(C.byref(stt), N, C.byref(n)))
-        need = int(n.value)
-        if need and (ws is None or ws.numel() < need):
-            ws = torch.empty(need, dtype=torch.uint8, device=dC.device)
+    n = C.c_size_t(0)
+    L.check(L.lib().rosko_spmm_backward_workspace_size(
+        C.byref(st) if need_dA else None, C.byref(stt) if stt is not None else None, N,
+        C.byref(n)))
+    need = int(n.value)
+    if need and (ws is None or ws.numel() < need):
+        ws = torch.empty(need, dtype=torch.uint8, device=dC.device)
     L.check(L.lib().rosko_spmm_backward(
         C.byref(st), C.byref(stt) if stt is not None else None, _ptr(B),
         max(B.stride(0), 1), _ptr(dC), max(dC.stride(0), 1), N, _ptr(dB),

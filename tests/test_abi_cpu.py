@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.rosko_abi_version() == 5
+    assert lib.rosko_abi_version() == 6
     assert lib.rosko_status_str(L.ROSKO_EINVAL) == b"ROSKO_EINVAL"
     assert lib.rosko_status_str(123) == b"ROSKO_UNKNOWN"
 
@@ -187,6 +187,30 @@ def test_backward_argument_checks():
     # a negative dA capacity is rejected before any work
     assert lib.rosko_spmm_backward(C.byref(s), None, fake, 16, fake, 16, 16, None, 16,
                                    fake, -1, None, 0, None) == L.ROSKO_EINVAL
+
+
+def test_backward_workspace_size():
+    """The SDDMM's column-chunk partials: 4 * ceil(N / 1024) * nnz_cap bytes
+    for N > 1024 and panels of up to 16 rows, none otherwise; with At the
+    larger of that and dB's SpMM workspace."""
+    lib = L.lib()
+    n = C.c_size_t(0)
+    for mr, N, want in [(8, 1024, 0), (8, 1025, 4 * 2 * 10), (16, 3136, 4 * 4 * 10),
+                        (4, 5000, 4 * 5 * 10), (32, 3136, 0), (8, 0, 0)]:
+        s = _packed(64, 128, mr)
+        assert lib.rosko_spmm_backward_workspace_size(C.byref(s), None, N, C.byref(n)) == 0
+        assert n.value == want, (mr, N)
+    s = _packed(64, 128, 8)
+    st = _packed(128, 64, 8)
+    assert lib.rosko_spmm_backward_workspace_size(None, C.byref(st), 3136, C.byref(n)) == 0
+    only_db = n.value
+    assert lib.rosko_spmm_backward_workspace_size(C.byref(s), C.byref(st), 3136,
+                                                  C.byref(n)) == 0
+    assert n.value == max(only_db, 4 * 4 * 10)
+    assert lib.rosko_spmm_backward_workspace_size(C.byref(s), None, -1,
+                                                  C.byref(n)) == L.ROSKO_EINVAL
+    assert lib.rosko_spmm_backward_workspace_size(None, None, 16, C.byref(n)) == 0
+    assert n.value == 0
 
 
 def test_plan_validation_and_workspace_size():

@@ -27,7 +27,11 @@ def _dA_scale(pk, dC, B):
                                       (64, 200, 700, 64), (70, 90, 2100, 32),
                                       # panels of <= 8 rows and N <= 1024: the LDS kernel
                                       (37, 300, 65, 8), (90, 128, 1024, 8), (50, 77, 1, 4),
-                                      (16, 40, 300, 1), (201, 513, 257, 8), (9, 1000, 511, 5)])
+                                      (16, 40, 300, 1), (201, 513, 257, 8), (9, 1000, 511, 5),
+                                      # panels of 9..16 rows, and N in 1024-column chunks
+                                      # (ragged last chunk; N % 4 != 0 takes element loads)
+                                      (50, 200, 700, 16), (40, 300, 2500, 16),
+                                      (33, 100, 1027, 8), (20, 64, 3136, 12), (64, 96, 2049, 4)])
 def test_backward_small(M, K, N, mr):
     say(f"backward {M}x{K}x{N} mr={mr}")
     A = synth.sparse_matrix(M, K, 0.1, 700 + M)
@@ -120,16 +124,18 @@ def test_autograd_training_steps_repack():
                 W[W.abs() <= thr] = 0.0
 
 
-def test_backward_after_overflowed_pack_stays_in_bounds():
+@pytest.mark.parametrize("N", [96, 1500])
+def test_backward_after_overflowed_pack_stays_in_bounds(N):
     """A repack into buffers too small for the matrix leaves pointer arrays
     that run past the capacities; the SDDMM clamps every index into them, so
-    dA is written only below its capacity (a sentinel beyond survives)."""
+    dA is written only below its capacity (a sentinel beyond survives), also
+    when N is split into column chunks."""
     import ctypes as C
     from paper_2307_03930_amd import _lib as L
-    say("backward after an overflowed pack")
+    say(f"backward after an overflowed pack, N={N}")
     A = synth.sparse_matrix(64, 256, 0.2, 710)
-    B = synth.dense_normal(256, 96, 711)
-    dC = synth.dense_normal(64, 96, 712)
+    B = synth.dense_normal(256, N, 711)
+    dC = synth.dense_normal(64, N, 712)
     Ad = dev(A)
     nnz, ncols, nrec = ops.pack_query(Ad, 8)
     P = ops._alloc(64, 256, 8, L.ROSKO_F32, nnz, ncols, nrec, Ad.device)
@@ -141,8 +147,14 @@ def test_backward_after_overflowed_pack_stays_in_bounds():
     P.nnz, P.ncols, P.nrec = nnz // 2, ncols // 2, nrec // 2
     dA = torch.full((nnz,), 123.0, dtype=torch.float32, device="cuda")
     st = P.struct()
+    n = C.c_size_t(0)
+    L.check(L.lib().rosko_spmm_backward_workspace_size(C.byref(st), None, N, C.byref(n)))
+    assert (n.value > 0) == (N > 1024)
+    bw = torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
+    Bd, dCd = dev(B), dev(dC)
     L.check(L.lib().rosko_spmm_backward(
-        C.byref(st), None, C.c_void_p(dev(B).data_ptr()), 96, C.c_void_p(dev(dC).data_ptr()),
-        96, 96, None, 96, C.c_void_p(dA.data_ptr()), nnz // 2, None, 0, ops._stream_ptr()))
+        C.byref(st), None, C.c_void_p(Bd.data_ptr()), N, C.c_void_p(dCd.data_ptr()),
+        N, N, None, N, C.c_void_p(dA.data_ptr()), nnz // 2, C.c_void_p(bw.data_ptr()),
+        n.value, ops._stream_ptr()))
     torch.cuda.synchronize()
     assert bool((dA[nnz // 2:] == 123.0).all())
