@@ -88,21 +88,32 @@ def alg_bytes(nnz, ncols, P, k_touched, N, M, s_val=4, s_b=4, s_c=4, beta=0):
             + M * N * s_c * (1 + beta))
 
 
-def cpu_baseline(As, B, budget_s: float = 20.0):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(As, B, mrs, budget_s: float = 20.0):
     """Time the CPU oracle (FP64 CSR loop, row-parallel) on a bounded sample
-    of the same workload; returns the baseline record."""
+    of the same workload: all six matrices on every host thread (up to 16,
+    the machine's CPU share), the 90% matrix on one thread, and the oracle's
+    packer (Alg. 1) on each matrix at the panel height the GPU step uses."""
     import numpy as np
     import oracle as O
     O.build(force=False)
     threads = max(1, min(16, os.cpu_count() or 1))
     N = B.shape[1]
-    flops = 0.0
-    t_total = 0.0
-    reps = 0
+    nnzs = [int(np.count_nonzero(A.view(np.uint32) & np.uint32(0x7FFFFFFF))) for A in As]
+    flops, t_total, reps = 0.0, 0.0, 0
     t_start = time.perf_counter()
     while time.perf_counter() - t_start < budget_s / 2 or reps == 0:
-        for A in As:
-            nnz = int(np.count_nonzero(A.view(np.uint32) & np.uint32(0x7FFFFFFF)))
+        for A, nnz in zip(As, nnzs):
             t0 = time.perf_counter()
             O.spmm(A, B, threads=threads)
             t_total += time.perf_counter() - t0
@@ -110,10 +121,31 @@ def cpu_baseline(As, B, budget_s: float = 20.0):
         reps += 1
         if reps >= 3:
             break
+    i90 = min(2, len(As) - 1)
+    t0 = time.perf_counter()
+    O.spmm(As[i90], B, threads=1)
+    t1 = time.perf_counter() - t0
+    pack_s = 0.0
+    for A, mr in zip(As, mrs):
+        t0 = time.perf_counter()
+        O.pack(A, mr)
+        pack_s += time.perf_counter() - t0
     return {"value": round(flops / t_total / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": _cpu_model(), "host_threads": os.cpu_count(),
+            "single_thread_value": round(2.0 * nnzs[i90] * N / t1 / 1e9, 3),
+            "single_thread_sample": "the 90% matrix once, one thread",
+            "oracle_pack_ms_all_six": round(pack_s * 1e3, 2),
             "sample": f"{reps} pass(es) over all six sparsities of the 256x2304x3136 layer, "
                       f"FP64 CSR loop, {threads} threads"}
+
+
+def _rel_err(x, ref, scale):
+    """max |x - ref| / scale over the entries (3 significant digits)."""
+    return float(f"{float(((x - ref).abs() / scale.clamp_min(1e-300)).max()):.3e}")
+
+
+def _path_name(plan):
+    return "dense-mfma" if plan is not None and plan.path == 1 else "sparse"
 
 
 def _time_us(fn, reps, warm=3):
@@ -141,7 +173,7 @@ def run_precision(args):
     torch.backends.cuda.matmul.allow_tf32 = False
     dev = torch.device("cuda:0")
     out = []
-    dense_us = None
+    dense_us = dense_bf16_us = None
     for sp in (0.90, 0.98):
         pr = synth.precision_problem(sp)
         A = torch.from_numpy(pr.A).to(dev)
@@ -151,8 +183,18 @@ def run_precision(args):
         N = pr.B.shape[1]
         if dense_us is None:
             dense_us = _time_us(lambda: torch.matmul(A, B32), 10)
+            A16 = A.to(torch.bfloat16).contiguous()
+            dense_bf16_us = _time_us(lambda: torch.matmul(A16, B16), 10)
+            del A16
         mr, plan = sched.candidate(sched.choose(A, N))
         kt = int((pr.A != 0).any(axis=0).sum())
+        # FP64 reference on the host (torch CPU): the exact product of the
+        # FP32 source values and its |A||B| scale
+        A64 = torch.from_numpy(pr.A).double()
+        B64 = torch.from_numpy(pr.B).double()
+        ref = A64 @ B64
+        scale = A64.abs() @ B64.abs()
+        del A64, B64
         for vals in ("f32", "bf16", "fp8"):
             P = ops.pack(A, mr, vals)
             Bd = B32 if vals == "f32" else B16
@@ -160,6 +202,7 @@ def run_precision(args):
             ws = torch.empty(max(ops.spmm_workspace_size(P, N, plan), 1), dtype=torch.uint8,
                              device=dev)
             t = _time_us(lambda: ops.spmm(P, Bd, C, plan=plan, ws=ws), args.reps)
+            e = _rel_err(C.cpu().double(), ref, scale)
             pws = torch.empty(max(ops.workspace_size(M, K, mr), 1), dtype=torch.uint8, device=dev)
             tp = _time_us(lambda: ops.pack_into(A, P, pws), args.reps)
             s_val = {"f32": 4, "bf16": 2, "fp8": 1}[vals]
@@ -168,15 +211,21 @@ def run_precision(args):
                 (4 * M if vals == "fp8" else 0)
             fl = 2.0 * P.nnz * N
             out.append({"sparsity": sp, "values": vals, "B": "f32" if vals == "f32" else "bf16",
-                        "mr": mr, "nnz": P.nnz, "spmm_us": round(t, 2), "pack_us": round(tp, 2),
+                        "mr": mr, "path": _path_name(plan), "nnz": P.nnz,
+                        "spmm_us": round(t, 2), "pack_us": round(tp, 2),
+                        "err_vs_fp64_fp32_source": e,
                         "gflops": round(fl / (t * 1e-6) / 1e9, 1),
                         "alu_frac": round(fl / (t * 1e-6) / 1e12 / VALU_FP32_PEAK_TFS, 3),
                         "hbm_frac": round(by / (t * 1e-6) / 1e9 / HBM_PEAK_GBS, 3),
-                        "speedup_vs_dense_fp32": round(dense_us / t, 2)})
-        del A, B32, B16
+                        "speedup_vs_dense_fp32": round(dense_us / t, 2),
+                        "speedup_vs_dense_bf16": round(dense_bf16_us / t, 2)})
+        del A, B32, B16, ref, scale
     print(json.dumps({"workload": "precision forms: A 4096x4096 at 90/98% (i.i.d.), values "
                                   "FP32/BF16/FP8+row scales, B 4096x2048, FP32 accumulate",
-                      "unit": "us", "dense_fp32_gemm_us": round(dense_us, 2), "data": "synthetic",
+                      "unit": "us", "dense_fp32_gemm_us": round(dense_us, 2),
+                      "dense_bf16_gemm_us": round(dense_bf16_us, 2),
+                      "err": "max |C - C64| / (|A||B|), C64 the FP64 product of the FP32 source "
+                             "values (torch CPU)", "data": "synthetic",
                       "forms": out}), flush=True)
 
 
@@ -214,6 +263,19 @@ def run_backward(args):
     dense_us = _time_us(lambda: torch.matmul(A, B), 10)
     fl = 2.0 * n * N
     res = {k: round(v, 2) for k, v in parts.items()}
+    # errors against FP64 references on the host (torch CPU): dB = A^T dC,
+    # dA = (dC B^T) on A's mask, scattered back to A's dense layout
+    dA, dB = ops.spmm_backward(P, Pt, B, dC, True, True)
+    dA_dense = torch.zeros((M, K), dtype=torch.float32, device=dev)
+    ops.scatter_dense(P, dA, dA_dense)
+    A64, B64, G64 = (torch.from_numpy(x).double() for x in (pr.A, pr.B, pr.dC))
+    mask = A64 != 0
+    rdB = A64.t() @ G64
+    sdB = A64.abs().t() @ G64.abs()
+    rdA = (G64 @ B64.t())[mask]
+    sdA = (G64.abs() @ B64.abs().t())[mask]
+    res["err_dB_vs_fp64"] = _rel_err(dB.cpu().double(), rdB, sdB)
+    res["err_dA_vs_fp64"] = _rel_err(dA_dense.cpu().double()[mask], rdA, sdA)
     for k in ("forward_spmm_us", "dB_spmm_us", "dA_sddmm_us"):
         res[k.replace("_us", "_gflops")] = round(fl / (parts[k] * 1e-6) / 1e9, 1)
         res[k.replace("_us", "_alu_frac")] = round(fl / (parts[k] * 1e-6) / 1e12 /
@@ -386,9 +448,13 @@ def main():
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / args.reps
         by = alg_bytes(nnz, nc, P_panels, kt, N, M)
+        A_s = As[sparsities.index(s)]
+        ws_s = wss[sparsities.index(s)]
+        pack_us = _time_us(lambda: ops.pack_into(A_s, P, ws_s), args.reps)
         tot_bytes += by
         tot_ms += ms
-        per.append({"sparsity": s, "nnz": nnz, "mr": mr, "spmm_us": round(ms * 1e3, 2),
+        per.append({"sparsity": s, "nnz": nnz, "mr": mr, "path": _path_name(plan),
+                    "spmm_us": round(ms * 1e3, 2), "pack_us": round(pack_us, 2),
                     "gflops": round(2.0 * nnz * N / (ms * 1e-3) / 1e9, 1),
                     "alu_frac": round(2.0 * nnz * N / (ms * 1e-3) / 1e12 / VALU_FP32_PEAK_TFS, 3),
                     "alg_MB": round(by / 1e6, 2),
@@ -490,7 +556,7 @@ def main():
     }
     out.update(extras)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(As_np, B_np)
+        out["cpu_baseline"] = cpu_baseline(As_np, B_np, mrs)
     print(json.dumps(out), flush=True)
 
 
