@@ -89,6 +89,16 @@ extern "C" {
  *                              (the panel's end if none); j = nkb is the end
  *                              of the panel.  Lets a workgroup start a K
  *                              range inside a panel.
+ *   row_perm [M]       int32   optional row order (NULL: none): packed row i
+ *                              holds row row_perm[i] of the matrix, which must
+ *                              be a permutation of 0..M-1.  Set by the caller
+ *                              before rosko_pack_csr (which packs in that
+ *                              order); the dense packers require NULL.
+ *                              rosko_spmm writes packed row i's result to C
+ *                              row row_perm[i], so C keeps the matrix's own
+ *                              row order; rosko_spmm_backward reads dC row
+ *                              row_perm[i] for it and rosko_scatter_dense
+ *                              writes it to row row_perm[i].
  * nnz_cap, ncols_cap and nrec_cap are the capacities of the caller's
  * buffers (col_ptr must hold ncols_cap+1 entries).  rosko_spmm reads values in
  * batches of 8 and row bytes by aligned dwords, so val and loc must stay
@@ -114,6 +124,7 @@ typedef struct rosko_packed {
   float *row_scale;
   int64_t *kblk_ptr;
   uint32_t *rec;
+  int32_t *row_perm;
 } rosko_packed;
 
 /* ---- execution plan for rosko_spmm ----------------------------------
@@ -198,6 +209,67 @@ int32_t rosko_pack_transpose_query(const float *A, int64_t M, int64_t K, int64_t
  * stream, stores the totals in packed->nnz / ncols, and returns
  * ROSKO_ESMALLBUF if they exceeded the capacities. */
 int32_t rosko_pack_result(const void *ws, size_t ws_bytes, rosko_packed *packed, void *stream);
+
+/* ---- packing from compressed sparse rows (graph matrices, Sec. 5.5) ----
+ * The input is an M x K matrix in CSR form on the device: row_ptr [M+1]
+ * int64 (row m's entries are [row_ptr[m], row_ptr[m+1]), within
+ * 0..nnz_in), col_idx [nnz_in] int32 (columns in 0..K-1, in any order within
+ * a row, no column twice in a row), val [nnz_in] FP32.  Entries whose FP32
+ * bits other than the sign are all zero are dropped, as in the dense
+ * packers.  The packed arrays are bit-identical to rosko_pack of the dense
+ * matrix whose row i is CSR row row_perm[i] (row i when row_perm is NULL).
+ * Limits: M and nnz_in below 2^31, K below 2^24.  Any mr in 1..256.  The
+ * workspace holds the sort of each panel's entries by column (rocPRIM) and
+ * is about 52 bytes per stored entry; its size depends on the device, so
+ * the size call needs a current HIP device (ROSKO_EHIP otherwise). */
+int32_t rosko_pack_csr_workspace_size(int64_t M, int64_t K, int64_t nnz_in, int32_t mr,
+                                      size_t *bytes);
+
+/* Counts the kept values, kept columns and column records of packing the
+ * CSR matrix in the row order row_perm (NULL: none).  SYNCHRONISES `stream`
+ * and returns the totals in *nnz, *ncols, *nrec (host).  ROSKO_EINVAL if
+ * the input breaks the rules above (row_perm not a permutation, row
+ * pointers outside 0..nnz_in or decreasing, a column outside 0..K-1, a
+ * column twice in a row); the checks run on the device. */
+int32_t rosko_pack_csr_query(const int64_t *row_ptr, const int32_t *col_idx, const float *val,
+                             const int32_t *row_perm, int64_t M, int64_t K, int64_t nnz_in,
+                             int32_t mr, void *ws, size_t ws_bytes, void *stream, int64_t *nnz,
+                             int64_t *ncols, int64_t *nrec);
+
+/* Packs the CSR matrix into `out` in the row order out->row_perm (set by
+ * the caller, NULL for none).  The caller sets out->M, K, mr, the
+ * capacities and the buffer pointers as for rosko_pack.  Writes never
+ * exceed the capacities.  Asynchronous; rosko_pack_csr_result reports the
+ * outcome. */
+int32_t rosko_pack_csr(const int64_t *row_ptr, const int32_t *col_idx, const float *val,
+                       int64_t M, int64_t K, int64_t nnz_in, int32_t mr, int32_t val_dtype,
+                       void *ws, size_t ws_bytes, rosko_packed *out, void *stream);
+
+/* After rosko_pack_csr with the same ws: SYNCHRONISES the stream, stores
+ * the totals in packed->nnz / ncols / nrec, and returns ROSKO_EINVAL for
+ * invalid input (the packed arrays are then unusable) or ROSKO_ESMALLBUF if
+ * the totals exceeded the capacities. */
+int32_t rosko_pack_csr_result(const void *ws, size_t ws_bytes, rosko_packed *packed,
+                              void *stream);
+
+/* ---- row order (an inspector for the row reordering of Sec. 6) --------
+ * Chooses row_perm for rosko_pack_csr from the CSR row lengths alone
+ * (stored entries per row, row_ptr [M+1] int64, device):
+ *   ROSKO_ORDER_DEGREE:   rows by descending length, ties by ascending row,
+ *                         so each panel holds rows of similar density;
+ *   ROSKO_ORDER_BALANCED: the length-sorted rows dealt to the panels in a
+ *                         serpentine (panel order reversing every round of
+ *                         mr rows' worth), so every panel gets one row from
+ *                         each band of lengths and the panels' entry counts
+ *                         come out close (nonzero-balanced panels).
+ * perm [M] int32 (device) receives the order.  ws: device workspace of the
+ * size rosko_row_order_workspace_size reports (needs a current device).
+ * Asynchronous. */
+#define ROSKO_ORDER_DEGREE 0
+#define ROSKO_ORDER_BALANCED 1
+int32_t rosko_row_order_workspace_size(int64_t M, size_t *bytes);
+int32_t rosko_row_order(const int64_t *row_ptr, int64_t M, int32_t mr, int32_t mode, void *ws,
+                        size_t ws_bytes, int32_t *perm, void *stream);
 
 /* ---- SpMM (Alg. 2) ------------------------------------------------------ */
 
@@ -358,7 +430,7 @@ int32_t rosko_plan_select(const float *features_host, const float *params, const
 /* ---- errors ----------------------------------------------------------- */
 const char *rosko_status_str(int32_t status);
 const char *rosko_last_error(void);   /* per host thread; "" if none */
-int32_t rosko_abi_version(void);      /* 6 */
+int32_t rosko_abi_version(void);      /* 7 */
 
 #ifdef __cplusplus
 }

@@ -281,3 +281,30 @@ def err_metric(C_hat: np.ndarray, C_ref: np.ndarray, scale: np.ndarray) -> float
     with np.errstate(divide="ignore", invalid="ignore"):
         r = np.where(s > 0, d / np.where(s > 0, s, 1.0), np.where(d > 0, np.inf, 0.0))
     return float(r.max()) if r.size else 0.0
+
+
+# ------------------------------------------------------------ CSR input
+def _csr_rows(row_ptr, col_idx, val, B, rows, absolute: bool) -> np.ndarray:
+    B = _f32(B).astype(np.float64)
+    if absolute:
+        B = np.abs(B)
+    out = np.zeros((len(rows), B.shape[1]), np.float64)
+    for i, m in enumerate(rows):
+        b, e = int(row_ptr[m]), int(row_ptr[m + 1])
+        a = np.asarray(val[b:e], np.float32).astype(np.float64)
+        if absolute:
+            a = np.abs(a)
+        out[i] = a @ B[np.asarray(col_idx[b:e], np.int64)]
+    return out
+
+
+def spmm_csr_rows(row_ptr, col_idx, val, B, rows) -> np.ndarray:
+    """Rows `rows` of C = A B in FP64 for A given in CSR form, by the
+    definition of the product (Sec. 3): C[m] is the sum over the stored
+    entries (m, k, a) of row m of a * B[k]."""
+    return _csr_rows(row_ptr, col_idx, val, B, rows, False)
+
+
+def abs_spmm_csr_rows(row_ptr, col_idx, val, B, rows) -> np.ndarray:
+    """The same rows of |A| |B| (the error scale of a computed product)."""
+    return _csr_rows(row_ptr, col_idx, val, B, rows, True)

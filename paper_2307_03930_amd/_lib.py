@@ -25,6 +25,8 @@ ROSKO_FP8_E4M3 = 2
 ROSKO_PATH_AUTO = -1
 ROSKO_PATH_SPARSE = 0
 ROSKO_PATH_DENSE = 1
+ROSKO_ORDER_DEGREE = 0
+ROSKO_ORDER_BALANCED = 1
 ROSKO_NFEAT = 16
 ROSKO_SCHED_CANDIDATES = 7
 ROSKO_KSTEP = 128
@@ -40,7 +42,7 @@ class RoskoPacked(C.Structure):
         ("panel_nz_ptr", C.c_void_p), ("panel_col_ptr", C.c_void_p),
         ("col_ind", C.c_void_p), ("col_nnz", C.c_void_p), ("col_ptr", C.c_void_p),
         ("loc", C.c_void_p), ("val", C.c_void_p), ("row_scale", C.c_void_p),
-        ("kblk_ptr", C.c_void_p), ("rec", C.c_void_p),
+        ("kblk_ptr", C.c_void_p), ("rec", C.c_void_p), ("row_perm", C.c_void_p),
     ]
 
 
@@ -79,6 +81,14 @@ SIGNATURES = {
     "rosko_pack_transpose": (_I32, [_P, _I64, _I64, _I64, _I32, _I32, _P, _SZ,
                                     C.POINTER(RoskoPacked), _P]),
     "rosko_pack_result": (_I32, [_P, _SZ, C.POINTER(RoskoPacked), _P]),
+    "rosko_pack_csr_workspace_size": (_I32, [_I64, _I64, _I64, _I32, C.POINTER(_SZ)]),
+    "rosko_pack_csr_query": (_I32, [_P, _P, _P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P,
+                                    C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
+    "rosko_pack_csr": (_I32, [_P, _P, _P, _I64, _I64, _I64, _I32, _I32, _P, _SZ,
+                              C.POINTER(RoskoPacked), _P]),
+    "rosko_pack_csr_result": (_I32, [_P, _SZ, C.POINTER(RoskoPacked), _P]),
+    "rosko_row_order_workspace_size": (_I32, [_I64, C.POINTER(_SZ)]),
+    "rosko_row_order": (_I32, [_P, _I64, _I32, _I32, _P, _SZ, _P, _P]),
     "rosko_spmm_workspace_size": (_I32, [C.POINTER(RoskoPacked), _I64, C.POINTER(RoskoPlan),
                                          C.POINTER(_SZ)]),
     "rosko_spmm": (_I32, [C.POINTER(RoskoPacked), _P, _I32, _I64, _I64, _P, _I64, _I32,

@@ -99,7 +99,7 @@ static int32_t check_packed_for_read(const rosko_packed* A) {
 
 extern "C" {
 
-int32_t rosko_abi_version(void) { return 6; }
+int32_t rosko_abi_version(void) { return 7; }
 
 const char* rosko_last_error(void) { return g_err; }
 
@@ -206,6 +206,8 @@ int32_t rosko_pack(const float* A, int64_t M, int64_t K, int64_t lda, int32_t mr
   if (st) return st;
   if ((st = check_mr(mr))) return st;
   if ((st = check_packed_for_write(out, M, K, mr, val_dtype))) return st;
+  RK_REQUIRE(out->row_perm == nullptr, ROSKO_EUNSUPPORTED,
+             "the dense packer keeps the row order: row_perm must be NULL");
   const PackWs L = pack_ws_layout(M, K, mr, false);
   RK_REQUIRE(L.P <= INT32_MAX, ROSKO_EUNSUPPORTED, "too many panels");
   RK_REQUIRE(ws != nullptr && ws_bytes >= L.bytes, ROSKO_ESMALLBUF,
@@ -221,6 +223,8 @@ int32_t rosko_pack_transpose(const float* A, int64_t M, int64_t K, int64_t lda, 
   if (st) return st;
   if ((st = check_mr(mr))) return st;
   if ((st = check_packed_for_write(out, K, M, mr, val_dtype))) return st;
+  RK_REQUIRE(out->row_perm == nullptr, ROSKO_EUNSUPPORTED,
+             "the dense packer keeps the row order: row_perm must be NULL");
   const PackWs L = pack_ws_layout(K, M, mr, true);
   RK_REQUIRE(L.P <= INT32_MAX, ROSKO_EUNSUPPORTED, "too many panels");
   RK_REQUIRE(ws != nullptr && ws_bytes >= L.bytes, ROSKO_ESMALLBUF,
@@ -255,6 +259,164 @@ int32_t rosko_pack_result(const void* ws, size_t ws_bytes, rosko_packed* packed,
              (long long)packed->nnz_cap, (long long)packed->ncols_cap,
              (long long)packed->nrec_cap);
   return ROSKO_OK;
+}
+
+// ------------------------------------------------------- CSR packing
+
+static int32_t check_csr_sizes(int64_t M, int64_t K, int64_t nnz_in, int32_t mr) {
+  RK_REQUIRE(M >= 0 && K >= 0 && nnz_in >= 0, ROSKO_EINVAL, "negative size");
+  int32_t st = check_mr(mr);
+  if (st) return st;
+  RK_REQUIRE(M < (int64_t(1) << 31) && nnz_in < (int64_t(1) << 31), ROSKO_EUNSUPPORTED,
+             "CSR packing takes M and nnz below 2^31");
+  RK_REQUIRE(K < (int64_t(1) << 24), ROSKO_EUNSUPPORTED, "K = %lld >= 2^24 columns",
+             (long long)K);
+  return ROSKO_OK;
+}
+
+static int32_t check_csr(const int64_t* row_ptr, const int32_t* col_idx, const float* val,
+                         int64_t M, int64_t K, int64_t nnz_in, int32_t mr) {
+  int32_t st = check_csr_sizes(M, K, nnz_in, mr);
+  if (st) return st;
+  RK_REQUIRE(M == 0 || row_ptr != nullptr, ROSKO_EINVAL, "row_ptr is null");
+  RK_REQUIRE(nnz_in == 0 || (col_idx && val), ROSKO_EINVAL, "col_idx / val is null");
+  return ROSKO_OK;
+}
+
+static int32_t csr_ws_need(int64_t M, int64_t K, int64_t nnz_in, int32_t mr, hipStream_t s,
+                           size_t* need) {
+  const CsrWs L = csr_ws_layout(M, nnz_in, mr);
+  size_t temp = 0;
+  if (M > 0) {
+    int32_t st = csr_temp_bytes(L, M, K, &temp, s);
+    if (st) return st;
+  }
+  *need = L.bytes + (size_t)round_up((int64_t)temp, 256);
+  return ROSKO_OK;
+}
+
+int32_t rosko_pack_csr_workspace_size(int64_t M, int64_t K, int64_t nnz_in, int32_t mr,
+                                      size_t* bytes) {
+  clear_error();
+  RK_REQUIRE(bytes != nullptr, ROSKO_EINVAL, "bytes is null");
+  *bytes = 0;
+  int32_t st = check_csr_sizes(M, K, nnz_in, mr);
+  if (st) return st;
+  return csr_ws_need(M, K, nnz_in, mr, nullptr, bytes);
+}
+
+int32_t rosko_pack_csr_query(const int64_t* row_ptr, const int32_t* col_idx, const float* val,
+                             const int32_t* row_perm, int64_t M, int64_t K, int64_t nnz_in,
+                             int32_t mr, void* ws, size_t ws_bytes, void* stream, int64_t* nnz,
+                             int64_t* ncols, int64_t* nrec) {
+  clear_error();
+  int32_t st = check_csr(row_ptr, col_idx, val, M, K, nnz_in, mr);
+  if (st) return st;
+  RK_REQUIRE(nnz && ncols && nrec, ROSKO_EINVAL, "nnz / ncols / nrec outputs are null");
+  hipStream_t s = s_of(stream);
+  size_t need = 0;
+  if ((st = csr_ws_need(M, K, nnz_in, mr, s, &need))) return st;
+  RK_REQUIRE(ws != nullptr && ws_bytes >= need, ROSKO_ESMALLBUF, "workspace %zu bytes < %zu",
+             ws_bytes, need);
+  (void)hipGetLastError();
+  if ((st = launch_pack_csr(row_ptr, col_idx, val, row_perm, M, K, nnz_in, mr, ROSKO_F32, ws,
+                            ws_bytes, nullptr, s)))
+    return st;
+  int64_t tot[kCsrTotals];
+  ROSKO_HIP_CHECK(hipMemcpyAsync(tot, ws, sizeof(tot), hipMemcpyDeviceToHost, s));
+  ROSKO_HIP_CHECK(hipStreamSynchronize(s));
+  RK_REQUIRE(tot[kCsrTotBad] == 0, ROSKO_EINVAL,
+             "invalid CSR input (flags 0x%llx: 1 row_perm entry out of range, 2 row_perm "
+             "repeats a row, 4 bad row pointers, 8 column out of range, 16 repeated entry)",
+             (unsigned long long)tot[kCsrTotBad]);
+  *nnz = tot[kCsrTotNnz];
+  *ncols = tot[kCsrTotNcols];
+  *nrec = tot[kCsrTotNrec];
+  return ROSKO_OK;
+}
+
+int32_t rosko_pack_csr(const int64_t* row_ptr, const int32_t* col_idx, const float* val,
+                       int64_t M, int64_t K, int64_t nnz_in, int32_t mr, int32_t val_dtype,
+                       void* ws, size_t ws_bytes, rosko_packed* out, void* stream) {
+  clear_error();
+  int32_t st = check_csr(row_ptr, col_idx, val, M, K, nnz_in, mr);
+  if (st) return st;
+  if ((st = check_packed_for_write(out, M, K, mr, val_dtype))) return st;
+  hipStream_t s = s_of(stream);
+  size_t need = 0;
+  if ((st = csr_ws_need(M, K, nnz_in, mr, s, &need))) return st;
+  RK_REQUIRE(ws != nullptr && ws_bytes >= need, ROSKO_ESMALLBUF, "workspace %zu bytes < %zu",
+             ws_bytes, need);
+  RK_REQUIRE(ceil_div(M, mr) <= INT32_MAX, ROSKO_EUNSUPPORTED, "too many panels");
+  out->n_panels = (int32_t)ceil_div(M, mr);
+  out->val_dtype = val_dtype;
+  out->nnz = -1;
+  out->ncols = -1;
+  out->nrec = -1;
+  (void)hipGetLastError();
+  return launch_pack_csr(row_ptr, col_idx, val, out->row_perm, M, K, nnz_in, mr, val_dtype, ws,
+                         ws_bytes, out, s);
+}
+
+int32_t rosko_pack_csr_result(const void* ws, size_t ws_bytes, rosko_packed* packed,
+                              void* stream) {
+  clear_error();
+  RK_REQUIRE(packed != nullptr, ROSKO_EINVAL, "packed is null");
+  RK_REQUIRE(ws != nullptr && ws_bytes >= sizeof(int64_t) * kCsrTotals, ROSKO_ESMALLBUF,
+             "workspace too small");
+  hipStream_t s = s_of(stream);
+  int64_t tot[kCsrTotals];
+  ROSKO_HIP_CHECK(hipMemcpyAsync(tot, ws, sizeof(tot), hipMemcpyDeviceToHost, s));
+  ROSKO_HIP_CHECK(hipStreamSynchronize(s));
+  packed->nnz = tot[kCsrTotNnz];
+  packed->ncols = tot[kCsrTotNcols];
+  packed->nrec = tot[kCsrTotNrec];
+  RK_REQUIRE(tot[kCsrTotBad] == 0, ROSKO_EINVAL,
+             "invalid CSR input (flags 0x%llx: 1 row_perm entry out of range, 2 row_perm "
+             "repeats a row, 4 bad row pointers, 8 column out of range, 16 repeated entry)",
+             (unsigned long long)tot[kCsrTotBad]);
+  RK_REQUIRE(tot[kCsrTotOverflow] == 0, ROSKO_ESMALLBUF,
+             "packing needs %lld values / %lld columns / %lld records, capacities are "
+             "%lld / %lld / %lld",
+             (long long)tot[kCsrTotNnz], (long long)tot[kCsrTotNcols],
+             (long long)tot[kCsrTotNrec], (long long)packed->nnz_cap,
+             (long long)packed->ncols_cap, (long long)packed->nrec_cap);
+  return ROSKO_OK;
+}
+
+int32_t rosko_row_order_workspace_size(int64_t M, size_t* bytes) {
+  clear_error();
+  RK_REQUIRE(bytes != nullptr, ROSKO_EINVAL, "bytes is null");
+  *bytes = 0;
+  RK_REQUIRE(M >= 0, ROSKO_EINVAL, "negative size");
+  RK_REQUIRE(M < (int64_t(1) << 31), ROSKO_EUNSUPPORTED, "M >= 2^31");
+  if (M == 0) return ROSKO_OK;
+  size_t temp = 0;
+  int32_t st = order_temp_bytes(M, &temp, nullptr);
+  if (st) return st;
+  *bytes = order_ws_bytes_fixed(M) + (size_t)round_up((int64_t)temp, 256);
+  return ROSKO_OK;
+}
+
+int32_t rosko_row_order(const int64_t* row_ptr, int64_t M, int32_t mr, int32_t mode, void* ws,
+                        size_t ws_bytes, int32_t* perm, void* stream) {
+  clear_error();
+  RK_REQUIRE(M >= 0, ROSKO_EINVAL, "negative size");
+  int32_t st = check_mr(mr);
+  if (st) return st;
+  RK_REQUIRE(mode == ROSKO_ORDER_DEGREE || mode == ROSKO_ORDER_BALANCED, ROSKO_EINVAL,
+             "unknown row order mode %d", mode);
+  RK_REQUIRE(M < (int64_t(1) << 31), ROSKO_EUNSUPPORTED, "M >= 2^31");
+  if (M == 0) return ROSKO_OK;
+  RK_REQUIRE(row_ptr != nullptr && perm != nullptr, ROSKO_EINVAL, "null argument");
+  hipStream_t s = s_of(stream);
+  size_t temp = 0;
+  if ((st = order_temp_bytes(M, &temp, s))) return st;
+  const size_t need = order_ws_bytes_fixed(M) + (size_t)round_up((int64_t)temp, 256);
+  RK_REQUIRE(ws != nullptr && ws_bytes >= need, ROSKO_ESMALLBUF, "workspace %zu bytes < %zu",
+             ws_bytes, need);
+  (void)hipGetLastError();
+  return launch_row_order(row_ptr, M, mr, mode, ws, ws_bytes, perm, s);
 }
 
 int32_t rosko_spmm_workspace_size(const rosko_packed* A, int64_t N, const rosko_plan* plan,

@@ -177,7 +177,8 @@ template <bool BF>
 __global__ void __launch_bounds__(256, 2)
 k_dense_gemm(const typename Op<BF>::T* __restrict__ Ad, const typename Op<BF>::T* __restrict__ Bt,
              int64_t Kp, int64_t M, int64_t N, int64_t tiles_n, float* __restrict__ C,
-             int64_t ldc, const float* __restrict__ row_scale, int32_t beta) {
+             int64_t ldc, const float* __restrict__ row_scale,
+             const int32_t* __restrict__ row_perm, int32_t beta) {
   using T = typename Op<BF>::T;
   constexpr int BK = Op<BF>::BK, LDK = Op<BF>::LDK, EPC = Op<BF>::EPC;
   __shared__ __align__(16) T As[kTile * LDK];
@@ -260,7 +261,7 @@ k_dense_gemm(const typename Op<BF>::T* __restrict__ Ad, const typename Op<BF>::T
         if (row < M && col < N) {
           float v = acc[i][j][r];
           if (row_scale) v *= row_scale[row];
-          float* c = C + row * ldc + col;
+          float* c = C + perm_row(row_perm, row, M) * ldc + col;
           *c = beta ? *c + v : v;
         }
       }
@@ -311,7 +312,7 @@ int32_t run_dense(const rosko_packed* A, const void* B, int32_t b_dtype, int64_t
   const int64_t tm = L.Mp / kTile, tn = L.Np / kTile;
   const float* rs = A->val_dtype == ROSKO_FP8_E4M3 ? A->row_scale : nullptr;
   hipLaunchKernelGGL(k_dense_gemm<BF>, dim3((unsigned)(tm * tn)), dim3(256), 0, s, Ad, Bt, L.Kp,
-                     A->M, N, tn, C, ldc, rs, beta);
+                     A->M, N, tn, C, ldc, rs, A->row_perm, beta);
   ROSKO_LAUNCH_CHECK("k_dense_gemm");
   return ROSKO_OK;
 }

@@ -95,6 +95,7 @@ struct SpmmArgs {
   const uint32_t* rec;          // column records, 16 dwords each
   const float* row_scale;       // FP8 row scales, else null
   const int64_t* kblk_ptr;      // record index per (panel, K block)
+  const int32_t* row_perm;      // C row of each packed row, or null
   const void* B;
   float* C;
   float* ws;           // k_split x M x N partial tiles (k_split > 1)
@@ -155,6 +156,41 @@ int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const
                      size_t ws_bytes, hipStream_t s);
 int32_t launch_scatter_dense(const rosko_packed* A, const float* vals, int64_t n_vals,
                              float* out, int64_t ldo, hipStream_t s);
+
+// --------------------------------------------------------- CSR packing
+// Workspace of rosko_pack_csr (byte offsets, 256-byte aligned): totals
+// first (so rosko_pack_csr_result finds them at offset 0), then the row and
+// panel offsets, the sort's keys and values (in and out), the column
+// numbering, per-column starts, keys and record counts, the record offsets,
+// and the library scratch of the sort and scans at `temp`.
+constexpr int kCsrTotals = 8;
+constexpr int kCsrTotNnz = 0, kCsrTotNcols = 1, kCsrTotOverflow = 2, kCsrTotNrec = 3,
+              kCsrTotBad = 4;
+struct CsrWs {
+  size_t totals, rowlen, rowoff, seen, pofs, kin, kout, vin, vout, hd, cid, colstart, colk, nr,
+      rptr, temp, bytes;
+  int64_t P, nz;
+};
+CsrWs csr_ws_layout(int64_t M, int64_t nz, int32_t mr);
+int32_t csr_temp_bytes(const CsrWs& L, int64_t M, int64_t K, size_t* bytes, hipStream_t s);
+// out == nullptr: the counting passes only (for rosko_pack_csr_query).
+int32_t launch_pack_csr(const int64_t* row_ptr, const int32_t* col_idx, const float* val,
+                        const int32_t* perm, int64_t M, int64_t K, int64_t nz_in, int32_t mr,
+                        int32_t val_dtype, void* ws, size_t ws_bytes, const rosko_packed* out,
+                        hipStream_t s);
+// Row order (inspector): fixed workspace part and the sort's scratch.
+size_t order_ws_bytes_fixed(int64_t M);
+int32_t order_temp_bytes(int64_t M, size_t* bytes, hipStream_t s);
+int32_t launch_row_order(const int64_t* row_ptr, int64_t M, int32_t mr, int32_t mode,
+                         void* ws, size_t ws_bytes, int32_t* perm, hipStream_t s);
+
+// Matrix row of packed row `row` under an optional row order (clamped into
+// 0..M-1, so no content of the order can move an access outside).
+__device__ __forceinline__ int64_t perm_row(const int32_t* perm, int64_t row, int64_t M) {
+  if (perm == nullptr) return row;
+  const int64_t m = perm[row];
+  return m < 0 ? 0 : (m >= M ? M - 1 : m);
+}
 
 // Round x up to a multiple of a (a > 0).
 inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }

@@ -25,8 +25,9 @@ __global__ void __launch_bounds__(64 * kSdW)
 k_sddmm(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict__ col_ind,
         const int32_t* __restrict__ col_nnz, const int64_t* __restrict__ col_ptr,
         const uint8_t* __restrict__ loc, int64_t M, int64_t K, int32_t mr,
-        const float* __restrict__ dC, int64_t lddc, const float* __restrict__ B, int64_t ldb,
-        int64_t N, int64_t ncols_lim, int64_t nz_lim, float* __restrict__ dA) {
+        const int32_t* __restrict__ row_perm, const float* __restrict__ dC, int64_t lddc,
+        const float* __restrict__ B, int64_t ldb, int64_t N, int64_t ncols_lim, int64_t nz_lim,
+        float* __restrict__ dA) {
   const int64_t p = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -50,7 +51,7 @@ k_sddmm(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict__ c
     for (int t = 0; t < n; ++t) {
       const int64_t z = z0 + t;
       const int64_t m = p * mr + min((int)loc[z], rows - 1);
-      const float* g = dC + m * lddc;
+      const float* g = dC + perm_row(row_perm, m, M) * lddc;
       float acc = 0.0f;
 #pragma unroll
       for (int j = 0; j < VB; ++j) {
@@ -107,7 +108,8 @@ __global__ void __launch_bounds__(64 * kSdW)
 k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict__ col_ind,
             const int32_t* __restrict__ col_nnz, const int64_t* __restrict__ col_ptr,
             const uint8_t* __restrict__ loc, int64_t M, int64_t K, int32_t mr, int32_t n_panels,
-            const float* __restrict__ dC, int64_t lddc, const float* __restrict__ B,
+            const int32_t* __restrict__ row_perm, const float* __restrict__ dC, int64_t lddc,
+            const float* __restrict__ B,
             int64_t ldb, int64_t N, bool vec, int64_t ncols_lim, int64_t nz_lim,
             float* __restrict__ out) {
   constexpr int RW = 256 * VQ;                    // LDS row width (floats)
@@ -126,7 +128,8 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
   const int rows = (int)min((int64_t)mr, M - r0);
   for (int idx = threadIdx.x; idx < ROWS * RW; idx += 64 * kSdW) {
     const int r = idx / RW, n = idx - r * RW;
-    sdc[idx] = (r < rows && n0 + n < N) ? dC[(r0 + r) * lddc + n0 + n] : 0.0f;
+    sdc[idx] = (r < rows && n0 + n < N)
+                   ? dC[perm_row(row_perm, r0 + r, M) * lddc + n0 + n] : 0.0f;
   }
   __syncthreads();
   // clamped as in k_sddmm
@@ -259,7 +262,8 @@ int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const
 #define RK_SDL(R_, VQ_)                                                                      \
   hipLaunchKernelGGL((k_sddmm_lds<R_, VQ_>), grid, dim3(64 * kSdW), 0, s, A->panel_col_ptr,  \
                      A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M, A->K, A->mr,          \
-                     A->n_panels, dC, lddc, B, ldb, N, vec, ncols_lim, nz_out, out)
+                     A->n_panels, A->row_perm, dC, lddc, B, ldb, N, vec, ncols_lim, nz_out,  \
+                     out)
     const int64_t nc = n_chunks > 1 ? kSdChunk : N;   // columns of a chunk
     if (A->mr <= 8) {
       if (nc <= 256) RK_SDL(8, 1);
@@ -284,7 +288,7 @@ int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const
 #define RK_SD(VB_)                                                                          \
   hipLaunchKernelGGL(k_sddmm<VB_>, dim3((unsigned)A->n_panels), dim3(64 * kSdW), 0, s,       \
                      A->panel_col_ptr, A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M,     \
-                     A->K, A->mr, dC, lddc, B, ldb, N, ncols_lim, nz_lim, dA_val)
+                     A->K, A->mr, A->row_perm, dC, lddc, B, ldb, N, ncols_lim, nz_lim, dA_val)
   if (vb <= 1) RK_SD(1);
   else if (vb <= 4) RK_SD(4);
   else if (vb <= 16) RK_SD(16);
@@ -297,7 +301,8 @@ int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const
 }  // namespace rosko
 
 // ------------------------------------------------------------------ scatter
-// out[p*mr + loc[z]][col_ind[c]] = vals[z] for every stored entry z of A, in
+// out[row(p*mr + loc[z])][col_ind[c]] = vals[z] for every stored entry z of A
+// (row() the optional row order), in
 // packed order: the inverse of packing for a dense M x K gradient (the
 // weight gradient of the training decomposition is dA on the mask, zero
 // elsewhere; the caller zero-fills out).  One workgroup per panel, threads
@@ -308,8 +313,8 @@ __global__ void __launch_bounds__(256)
 k_scatter_dense(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict__ col_ind,
                 const int32_t* __restrict__ col_nnz, const int64_t* __restrict__ col_ptr,
                 const uint8_t* __restrict__ loc, int64_t M, int64_t K, int32_t mr,
-                int64_t ncols_lim, int64_t nz_lim, const float* __restrict__ vals,
-                float* __restrict__ out, int64_t ldo) {
+                const int32_t* __restrict__ row_perm, int64_t ncols_lim, int64_t nz_lim,
+                const float* __restrict__ vals, float* __restrict__ out, int64_t ldo) {
   const int64_t p = blockIdx.x;
   const int rows = (int)min((int64_t)mr, M - p * mr);
   const int64_t c_hi = min(panel_col_ptr[p + 1], ncols_lim);
@@ -321,7 +326,7 @@ k_scatter_dense(const int64_t* __restrict__ panel_col_ptr, const int32_t* __rest
     const int64_t n = max((int64_t)0, min((int64_t)col_nnz[c], nz_lim - z0));
     for (int64_t t = 0; t < n; ++t) {
       const int r = loc[z0 + t];
-      if (r < rows) out[(p * mr + r) * ldo + k] = vals[z0 + t];
+      if (r < rows) out[perm_row(row_perm, p * mr + r, M) * ldo + k] = vals[z0 + t];
     }
   }
 }
@@ -332,7 +337,8 @@ int32_t launch_scatter_dense(const rosko_packed* A, const float* vals, int64_t n
   if (A->n_panels == 0 || A->K == 0) return ROSKO_OK;
   hipLaunchKernelGGL(k_scatter_dense, dim3((unsigned)A->n_panels), dim3(256), 0, s,
                      A->panel_col_ptr, A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M, A->K,
-                     A->mr, A->ncols_cap, std::min(A->nnz_cap, n_vals), vals, out, ldo);
+                     A->mr, A->row_perm, A->ncols_cap, std::min(A->nnz_cap, n_vals), vals, out,
+                     ldo);
   ROSKO_LAUNCH_CHECK("k_scatter_dense");
   return ROSKO_OK;
 }

@@ -55,14 +55,14 @@ k_fill_zero(float* __restrict__ C, int64_t M, int64_t N, int64_t ldc) {
 template <bool VEC>
 __global__ void __launch_bounds__(256)
 k_reduce_splits(const float* __restrict__ ws, int32_t S, int64_t M, int64_t N,
-                const float* __restrict__ row_scale, float* __restrict__ C, int64_t ldc,
-                int32_t beta) {
+                const float* __restrict__ row_scale, const int32_t* __restrict__ row_perm,
+                float* __restrict__ C, int64_t ldc, int32_t beta) {
   const int64_t MN = M * N;
   const int64_t n = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
   if (n >= N) return;
   for (int64_t m = blockIdx.y; m < M; m += gridDim.y) {
     const float* src = ws + m * N + n;
-    float* c = C + m * ldc + n;
+    float* c = C + perm_row(row_perm, m, M) * ldc + n;
     const float sc = row_scale ? row_scale[m] : 1.0f;
     if (VEC) {
       float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -252,6 +252,7 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
   g.rec = A->rec;
   g.row_scale = (A->val_dtype == ROSKO_FP8_E4M3) ? A->row_scale : nullptr;
   g.kblk_ptr = A->kblk_ptr;
+  g.row_perm = A->row_perm;
   g.B = B;
   g.C = C;
   g.ws = ws;
@@ -286,9 +287,11 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
       return ROSKO_EUNSUPPORTED;
     }
   }
-  if ((uint64_t)A->K * (uint64_t)ldb * eb >= (1ull << 32) ||
-      (uint64_t)(g.rec_bound + 64) * 64u >= (1ull << 32)) {
-    set_error("B (%lld x %lld elements) or the record array exceeds 4 GiB of buffer offsets",
+  // a wavefront's records lie inside one panel: at most K kept columns of
+  // ceil(mr / 12) records each (plus the loop's read-ahead)
+  const uint64_t panel_rec = (uint64_t)A->K * (uint64_t)ceil_div(A->mr, kRecVals) + 64;
+  if ((uint64_t)A->K * (uint64_t)ldb * eb >= (1ull << 32) || panel_rec * 64u >= (1ull << 32)) {
+    set_error("B (%lld x %lld elements) or a panel's records exceed 4 GiB of buffer offsets",
               (long long)A->K, (long long)ldb);
     return ROSKO_EUNSUPPORTED;
   }
@@ -312,10 +315,10 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
   const float* rs = A->val_dtype == ROSKO_FP8_E4M3 ? A->row_scale : nullptr;
   if (rvec)
     hipLaunchKernelGGL(k_reduce_splits<true>, grid, dim3(256), 0, s, ws, g.k_split, A->M, N,
-                       rs, C, ldc, beta);
+                       rs, A->row_perm, C, ldc, beta);
   else
     hipLaunchKernelGGL(k_reduce_splits<false>, grid, dim3(256), 0, s, ws, g.k_split, A->M, N,
-                       rs, C, ldc, beta);
+                       rs, A->row_perm, C, ldc, beta);
   ROSKO_LAUNCH_CHECK("k_reduce_splits");
   return ROSKO_OK;
 }

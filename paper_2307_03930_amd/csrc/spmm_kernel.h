@@ -146,11 +146,13 @@ k_spmm_rows(SpmmArgs g) {
       // the record loop in one asm block (spmm_loop.inc); buffer loads with
       // 32-bit offsets from this run's first record and from B.  Each buffer
       // is sized exactly (the records from this run's first to the array's
-      // end; K rows of ldb elements), so the hardware returns zero for any
-      // load outside it instead of touching other memory
+      // end, capped below 4 GiB -- a run is far shorter; K rows of ldb
+      // elements), so the hardware returns zero for any load outside it
+      // instead of touching other memory
       constexpr uint32_t esz = TB == ROSKO_F32 ? 4 : 2;
+      const int64_t rbytes = min((g.rec_bound - a) * 64, (int64_t)0xFFFFFFC0);
       const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)(g.rec + a * 16), 0, (int)(uint32_t)((g.rec_bound - a) * 64), 0x00020000);
+          (void*)(g.rec + a * 16), 0, (int)(uint32_t)rbytes, 0x00020000);
       const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
           (void*)g.B, 0, (int)(uint32_t)(g.K * g.ldb * esz), 0x00020000);
       const int64_t cl = n0 < g.N - V ? n0 : g.N - V;
@@ -197,7 +199,7 @@ k_spmm_rows(SpmmArgs g) {
 #pragma unroll
           for (int j = 0; j < V; ++j) v[j] *= sc;
         }
-        store_c<V>(g.C, row * g.ldc, n0, g.N, true, v, g.beta);
+        store_c<V>(g.C, perm_row(g.row_perm, row, g.M) * g.ldc, n0, g.N, true, v, g.beta);
       } else {
         store_c<V>(g.ws, (s * g.M + row) * g.N, n0, g.N, g.ws_vec != 0, v, 0);
       }

@@ -5,6 +5,8 @@ torch, every step of the computation runs in librosko.so.
   pack_transpose(A, mr)         packs A^T (for dB = A^T dC)
   spmm(P, B, C=None, beta=0)    Alg. 2 on the GPU: C = A B (or C += A B)
   spmm_backward(P, Pt, B, dC)   dB = A^T dC and dA (packed order)
+  pack_csr(row_ptr, col, val)   Alg. 1 from CSR input (graphs), optional row order
+  row_order(row_ptr, mr, mode)  the inspector's row order for pack_csr
 """
 from __future__ import annotations
 
@@ -56,6 +58,7 @@ class PackedMatrix:
     row_scale: torch.Tensor | None
     kblk_ptr: torch.Tensor
     rec: torch.Tensor
+    row_perm: torch.Tensor | None = None   # packed row i holds matrix row row_perm[i]
 
     @property
     def n_panels(self) -> int:
@@ -77,6 +80,7 @@ class PackedMatrix:
         s.row_scale = 0 if self.row_scale is None else self.row_scale.data_ptr()
         s.kblk_ptr = self.kblk_ptr.data_ptr()
         s.rec = self.rec.data_ptr()
+        s.row_perm = 0 if self.row_perm is None else self.row_perm.data_ptr()
         return s
 
     def values(self) -> torch.Tensor:
@@ -298,3 +302,80 @@ def scatter_dense(P: PackedMatrix, vals: torch.Tensor, out: torch.Tensor) -> tor
     L.check(L.lib().rosko_scatter_dense(C.byref(st), _ptr(vals), vals.numel(), _ptr(out),
                                         max(out.stride(0), 1), _stream_ptr()))
     return out
+
+
+# ------------------------------------------------------------ CSR input
+
+ORDERS = {"degree": L.ROSKO_ORDER_DEGREE, "balanced": L.ROSKO_ORDER_BALANCED}
+
+
+def _check_csr(row_ptr, col_idx, val):
+    ok = (row_ptr.is_cuda and row_ptr.dtype == torch.int64 and row_ptr.dim() == 1
+          and row_ptr.is_contiguous() and col_idx.is_cuda and col_idx.dtype == torch.int32
+          and col_idx.is_contiguous() and val.is_cuda and val.dtype == torch.float32
+          and val.is_contiguous() and col_idx.numel() == val.numel())
+    if not ok:
+        raise ValueError("CSR input: row_ptr int64, col_idx int32 and val float32 contiguous "
+                         "CUDA tensors, col_idx and val of one length")
+
+
+def csr_workspace_size(M: int, K: int, nnz_in: int, mr: int) -> int:
+    n = C.c_size_t(0)
+    L.check(L.lib().rosko_pack_csr_workspace_size(M, K, nnz_in, mr, C.byref(n)))
+    return int(n.value)
+
+
+def pack_csr(row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor, K: int,
+             mr: int = 8, dtype="f32", perm: torch.Tensor | None = None) -> PackedMatrix:
+    """Alg. 1 on the CSR matrix (M = len(row_ptr) - 1 rows, K columns), its
+    packed row i taken from CSR row perm[i] when perm is given; the result's
+    SpMM writes C in the matrix's own row order.  Synchronises (sizing)."""
+    _check_csr(row_ptr, col_idx, val)
+    if perm is not None and not (perm.is_cuda and perm.dtype == torch.int32
+                                 and perm.is_contiguous()):
+        raise ValueError("perm must be a contiguous int32 CUDA tensor")
+    dt = _dtype_code(dtype)
+    M = row_ptr.numel() - 1
+    nz = col_idx.numel()
+    ws = torch.empty(max(csr_workspace_size(M, K, nz, mr), 1), dtype=torch.uint8,
+                     device=row_ptr.device)
+    nnz, ncols, nrec = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    L.check(L.lib().rosko_pack_csr_query(
+        _ptr(row_ptr), _ptr(col_idx), _ptr(val), _ptr(perm), M, K, nz, mr, _ptr(ws), ws.numel(),
+        _stream_ptr(), C.byref(nnz), C.byref(ncols), C.byref(nrec)))
+    P = _alloc(M, K, mr, dt, int(nnz.value), int(ncols.value), int(nrec.value),
+               row_ptr.device)
+    P.row_perm = perm
+    st = P.struct()
+    L.check(L.lib().rosko_pack_csr(_ptr(row_ptr), _ptr(col_idx), _ptr(val), M, K, nz, mr, dt,
+                                   _ptr(ws), ws.numel(), C.byref(st), _stream_ptr()))
+    L.check(L.lib().rosko_pack_csr_result(_ptr(ws), ws.numel(), C.byref(st), _stream_ptr()))
+    P.nnz, P.ncols, P.nrec = int(st.nnz), int(st.ncols), int(st.nrec)
+    P._ws = ws
+    return P
+
+
+def pack_csr_into(row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor,
+                  P: PackedMatrix, ws: torch.Tensor) -> PackedMatrix:
+    """Re-packs a CSR matrix of the same shape into P's buffers (P.row_perm
+    as the row order).  Asynchronous."""
+    _check_csr(row_ptr, col_idx, val)
+    st = P.struct()
+    L.check(L.lib().rosko_pack_csr(_ptr(row_ptr), _ptr(col_idx), _ptr(val), P.M, P.K,
+                                   col_idx.numel(), P.mr, P.val_dtype, _ptr(ws), ws.numel(),
+                                   C.byref(st), _stream_ptr()))
+    return P
+
+
+def row_order(row_ptr: torch.Tensor, mr: int, mode: str = "balanced") -> torch.Tensor:
+    """The inspector's row order (int32 permutation) for pack_csr."""
+    if not (row_ptr.is_cuda and row_ptr.dtype == torch.int64 and row_ptr.is_contiguous()):
+        raise ValueError("row_ptr must be a contiguous int64 CUDA tensor")
+    M = row_ptr.numel() - 1
+    n = C.c_size_t(0)
+    L.check(L.lib().rosko_row_order_workspace_size(M, C.byref(n)))
+    ws = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=row_ptr.device)
+    perm = torch.empty(max(M, 1), dtype=torch.int32, device=row_ptr.device)
+    L.check(L.lib().rosko_row_order(_ptr(row_ptr), M, mr, ORDERS[mode], _ptr(ws), ws.numel(),
+                                    _ptr(perm), _stream_ptr()))
+    return perm[:M]

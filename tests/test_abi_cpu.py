@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.rosko_abi_version() == 6
+    assert lib.rosko_abi_version() == 7
     assert lib.rosko_status_str(L.ROSKO_EINVAL) == b"ROSKO_EINVAL"
     assert lib.rosko_status_str(123) == b"ROSKO_UNKNOWN"
 
@@ -342,3 +342,41 @@ def test_dense_path_checks_its_workspace_on_the_host():
     assert lib.rosko_spmm(C.byref(s), fake, L.ROSKO_F32, 16, 16, fake, 16, 0, C.byref(plan),
                           fake, n.value - 1, None) == L.ROSKO_ESMALLBUF
     assert b"dense" in lib.rosko_last_error()
+
+
+def test_csr_and_row_order_argument_checks():
+    """Host-side checks of the CSR packer and the row order, before any
+    device work: sizes, limits, null arrays, the dense packers' refusal of
+    a row order, an unknown order mode."""
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)
+    n = C.c_size_t(0)
+    assert lib.rosko_pack_csr_workspace_size(-1, 4, 0, 8, C.byref(n)) == L.ROSKO_EINVAL
+    assert lib.rosko_pack_csr_workspace_size(4, 1 << 24, 0, 8, C.byref(n)) == \
+        L.ROSKO_EUNSUPPORTED
+    assert lib.rosko_pack_csr_workspace_size(4, 4, 1 << 31, 8, C.byref(n)) == \
+        L.ROSKO_EUNSUPPORTED
+    assert lib.rosko_pack_csr_workspace_size(4, 4, 0, 0, C.byref(n)) == L.ROSKO_EINVAL
+    i64 = C.c_int64(0)
+    s = _packed(8, 8, 4)
+    assert lib.rosko_pack_csr(None, fake, fake, 8, 8, 3, 4, L.ROSKO_F32, fake, 1 << 20,
+                              C.byref(s), None) == L.ROSKO_EINVAL
+    assert lib.rosko_pack_csr(fake, None, fake, 8, 8, 3, 4, L.ROSKO_F32, fake, 1 << 20,
+                              C.byref(s), None) == L.ROSKO_EINVAL
+    assert lib.rosko_pack_csr(fake, fake, fake, 8, 9, 3, 4, L.ROSKO_F32, fake, 1 << 20,
+                              C.byref(s), None) == L.ROSKO_EINVAL      # shape mismatch
+    assert lib.rosko_pack_csr_query(fake, fake, fake, None, 8, 8, 3, 4, fake, 1 << 20, None,
+                                    None, C.byref(i64), C.byref(i64)) == L.ROSKO_EINVAL
+    # the dense packers keep the row order
+    s.row_perm = 0x1000
+    assert lib.rosko_pack(fake, 8, 8, 8, 4, L.ROSKO_F32, fake, 1 << 20, C.byref(s),
+                          None) == L.ROSKO_EUNSUPPORTED
+    st = _packed(8, 8, 4)
+    st.row_perm = 0x1000
+    assert lib.rosko_pack_transpose(fake, 8, 8, 8, 4, L.ROSKO_F32, fake, 1 << 20, C.byref(st),
+                                    None) == L.ROSKO_EUNSUPPORTED
+    assert lib.rosko_row_order(fake, 10, 4, 7, fake, 1 << 20, fake, None) == L.ROSKO_EINVAL
+    assert lib.rosko_row_order(fake, 10, 0, 0, fake, 1 << 20, fake, None) == L.ROSKO_EINVAL
+    assert lib.rosko_row_order(None, 0, 4, 0, None, 0, None, None) == L.ROSKO_OK
+    assert lib.rosko_row_order_workspace_size(0, C.byref(n)) == 0 and n.value == 0
+    assert lib.rosko_row_order_workspace_size(-2, C.byref(n)) == L.ROSKO_EINVAL

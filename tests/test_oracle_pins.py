@@ -257,6 +257,53 @@ def test_abs_product_matches_numpy_and_bounds_the_product():
     np.testing.assert_array_equal(O.abs_product(A, 2 * B), 2 * S)
 
 
+def test_spmm_csr_rows_hand_case():
+    # rows 0 and 2 of a 3 x 3 CSR matrix with an explicit zero in row 0:
+    # C[0] = 2*B[1] + 0*B[2], C[2] = -1*B[0] + 4*B[2]
+    row_ptr = np.array([0, 2, 2, 4], np.int64)
+    col_idx = np.array([1, 2, 2, 0], np.int32)
+    val = np.array([2, 0, 4, -1], np.float32)
+    B = np.array([[1, 2], [3, -4], [0.5, 8]], np.float32)
+    np.testing.assert_array_equal(O.spmm_csr_rows(row_ptr, col_idx, val, B, [0, 2]),
+                                  [[6.0, -8.0], [1.0, 30.0]])
+    np.testing.assert_array_equal(O.abs_spmm_csr_rows(row_ptr, col_idx, val, B, [2]),
+                                  [[3.0, 34.0]])
+    np.testing.assert_array_equal(O.spmm_csr_rows(row_ptr, col_idx, val, B, [1]), [[0.0, 0.0]])
+
+
+def test_spmm_csr_rows_matches_dense_oracle_on_a_graph():
+    """On a small power-law graph the CSR definition agrees with the dense
+    oracle (a different summation route) to FP64 rounding, and so does the
+    absolute-value scale."""
+    gr = synth.power_law_graph(600, 12.0, 31)
+    A = synth.csr_to_dense(gr)
+    B = synth.dense_normal(600, 24, 32)
+    rows = list(range(0, 600, 7))
+    C = O.spmm_csr_rows(gr.row_ptr, gr.col_idx, gr.val, B, rows)
+    S = O.abs_spmm_csr_rows(gr.row_ptr, gr.col_idx, gr.val, B, rows)
+    np.testing.assert_allclose(S, O.abs_product(A, B)[rows], rtol=1e-14, atol=0)
+    assert np.all(np.abs(C - O.spmm(A, B)[rows]) <= 1e-14 * S + 1e-300)
+
+
+def test_power_law_graph_structure():
+    """The graph generator's output: symmetric, self loops, no repeated
+    entries, rows sorted, the GCN normalisation (each value is
+    1 / sqrt(d_u d_v)), and the requested mean degree within 3%."""
+    gr = synth.power_law_graph(3000, 30.0, 33)
+    A = synth.csr_to_dense(gr)
+    assert np.array_equal(A != 0, (A != 0).T)
+    assert np.all(np.diag(A) > 0)
+    d = np.diff(gr.row_ptr)
+    for m in range(0, 3000, 97):
+        seg = gr.col_idx[gr.row_ptr[m]:gr.row_ptr[m + 1]]
+        assert np.all(np.diff(seg) > 0)
+    rows = np.repeat(np.arange(3000), d)
+    np.testing.assert_allclose(gr.val, 1.0 / np.sqrt(d[rows] * d[gr.col_idx].astype(np.float64)),
+                               rtol=1e-6)
+    assert abs((gr.nnz - 3000) / 3000 - 30.0) <= 0.9
+    assert d.max() > 5 * d.mean()        # heavy tail
+
+
 def test_threaded_oracle_routines_equal_single_thread():
     A = synth.sparse_matrix(70, 90, 0.2, 27)
     B = synth.dense_normal(90, 45, 28)
