@@ -380,10 +380,12 @@ def power_law_graph(n: int, avg_degree: float, seed: int, exponent: float = 2.5,
     return Graph(n, row_ptr, cols.astype(np.int32), val)
 
 
-# Two graph shapes of the GCN aggregation experiment: the node counts and
-# mean degrees of a social graph with 99.79% sparsity and of a protein
-# association graph with 99.55% sparsity; the feature lengths it sweeps.
-GCN_GRAPHS = {"social_233k": (232_965, 492.0, 11), "protein_133k": (132_534, 597.0, 12)}
+# Graph shapes of the GCN aggregation experiment: the node counts and mean
+# degrees of a social graph with 99.79% sparsity and of a protein association
+# graph with 99.55% sparsity, and a 60000-node graph at 99.8% (7.3M entries);
+# the feature lengths the experiment sweeps.
+GCN_GRAPHS = {"social_233k": (232_965, 492.0, 11), "protein_133k": (132_534, 597.0, 12),
+              "medium_60k": (60_000, 120.0, 911)}
 GCN_FEATURES = (32, 64, 128, 256, 512)
 
 
