@@ -186,7 +186,6 @@ def run_precision(args):
             A16 = A.to(torch.bfloat16).contiguous()
             dense_bf16_us = _time_us(lambda: torch.matmul(A16, B16), 10)
             del A16
-        mr, plan = sched.candidate(sched.choose(A, N))
         kt = int((pr.A != 0).any(axis=0).sum())
         # FP64 reference on the host (torch CPU): the exact product of the
         # FP32 source values and its |A||B| scale
@@ -196,6 +195,8 @@ def run_precision(args):
         scale = A64.abs() @ B64.abs()
         del A64, B64
         for vals in ("f32", "bf16", "fp8"):
+            mr, plan = sched.candidate(sched.choose(A, N, val_dtype=vals,
+                                                    b_dtype="f32" if vals == "f32" else "bf16"))
             P = ops.pack(A, mr, vals)
             Bd = B32 if vals == "f32" else B16
             C = torch.empty((M, N), dtype=torch.float32, device=dev)

@@ -416,21 +416,37 @@ int32_t rosko_sched_candidate(int32_t index, int32_t *mr, rosko_plan *plan);
  *   d >= 0.3:        N < 64: 1, N < 2048: 3, else 6 (dense-MFMA). */
 int32_t rosko_sched_analytic(const float *features_host, int32_t *index);
 
+/* The value-type rule: the network and the analytic rule were fitted on
+ * FP32 values times FP32 B.  When the values are BF16 or FP8 and B is BF16,
+ * the dense path runs on the BF16 matrix cores (16x the FP32 vector rate),
+ * so from density features_host[3] >= 0.025 it sets *index to the dense
+ * candidate (ROSKO_SCHED_CANDIDATES - 1); otherwise *index is left as it is.
+ * The threshold is the crossover measured on a 4096 x 4096 matrix times a
+ * 4096 x 2048 BF16 B (dense 131 us; sparse 324 us at density 0.10 and 116 us
+ * at 0.02); both paths' times scale with N, and the dense one with M*K
+ * against the sparse one's nnz, so the crossover is a density.  val_dtype
+ * ROSKO_F32 / BF16 / FP8_E4M3, b_dtype ROSKO_F32 / BF16.  Host only. */
+int32_t rosko_sched_precision(const float *features_host, int32_t val_dtype, int32_t b_dtype,
+                              int32_t *index);
+
 /* Plan selection: the candidate (index, panel height to pack with, plan) for
  * a matrix with statistics features_host (ROSKO_NFEAT host floats, from
- * rosko_features).  With params (host, the rosko_mlp_param_count(ROSKO_NFEAT,
- * 64, ROSKO_SCHED_CANDIDATES) weights of the plan network, layout as
+ * rosko_features), stored as val_dtype and multiplied by a B of b_dtype.
+ * With params (host, the rosko_mlp_param_count(ROSKO_NFEAT, 64,
+ * ROSKO_SCHED_CANDIDATES) weights of the plan network, layout as
  * rosko_mlp_*) and its per-feature normalisation mu, sigma (host), the
  * network's forward pass runs on the host in FP32 and its arg-min is taken;
- * with params NULL the analytic rule decides.  The caller owns the weights
- * (the library stores none).  Synchronous, host only. */
+ * with params NULL the analytic rule decides; then rosko_sched_precision
+ * applies the value-type rule.  The caller owns the weights (the library
+ * stores none).  Synchronous, host only. */
 int32_t rosko_plan_select(const float *features_host, const float *params, const float *mu,
-                          const float *sigma, int32_t *index, int32_t *mr, rosko_plan *plan);
+                          const float *sigma, int32_t val_dtype, int32_t b_dtype,
+                          int32_t *index, int32_t *mr, rosko_plan *plan);
 
 /* ---- errors ----------------------------------------------------------- */
 const char *rosko_status_str(int32_t status);
 const char *rosko_last_error(void);   /* per host thread; "" if none */
-int32_t rosko_abi_version(void);      /* 7 */
+int32_t rosko_abi_version(void);      /* 8 */
 
 #ifdef __cplusplus
 }

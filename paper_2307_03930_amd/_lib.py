@@ -113,7 +113,8 @@ SIGNATURES = {
     "rosko_argmin_rows": (_I32, [_P, _I64, _I32, _P, _P]),
     "rosko_sched_candidate": (_I32, [_I32, C.POINTER(_I32), C.POINTER(RoskoPlan)]),
     "rosko_sched_analytic": (_I32, [_P, C.POINTER(_I32)]),
-    "rosko_plan_select": (_I32, [_P, _P, _P, _P, C.POINTER(_I32), C.POINTER(_I32),
+    "rosko_sched_precision": (_I32, [_P, _I32, _I32, C.POINTER(_I32)]),
+    "rosko_plan_select": (_I32, [_P, _P, _P, _P, _I32, _I32, C.POINTER(_I32), C.POINTER(_I32),
                                  C.POINTER(RoskoPlan)]),
     "rosko_status_str": (C.c_char_p, [_I32]),
     "rosko_last_error": (C.c_char_p, []),

@@ -99,7 +99,7 @@ static int32_t check_packed_for_read(const rosko_packed* A) {
 
 extern "C" {
 
-int32_t rosko_abi_version(void) { return 7; }
+int32_t rosko_abi_version(void) { return 8; }
 
 const char* rosko_last_error(void) { return g_err; }
 
@@ -669,9 +669,29 @@ int32_t rosko_sched_analytic(const float* f, int32_t* index) {
   return ROSKO_OK;
 }
 
+// The value-type rule (see rosko.h): products the BF16 matrix cores can
+// take (BF16 or FP8 values times a BF16 B) go dense from this density up.
+constexpr float kBf16DenseDensity = 0.025f;
+constexpr int32_t kDenseCandidate = ROSKO_SCHED_CANDIDATES - 1;
+
+int32_t rosko_sched_precision(const float* f, int32_t val_dtype, int32_t b_dtype,
+                              int32_t* index) {
+  clear_error();
+  RK_REQUIRE(f && index, ROSKO_EINVAL, "null argument");
+  RK_REQUIRE(val_dtype == ROSKO_F32 || val_dtype == ROSKO_BF16 ||
+                 val_dtype == ROSKO_FP8_E4M3,
+             ROSKO_EINVAL, "value dtype %d", val_dtype);
+  RK_REQUIRE(b_dtype == ROSKO_F32 || b_dtype == ROSKO_BF16, ROSKO_EINVAL, "B dtype %d",
+             b_dtype);
+  if (val_dtype != ROSKO_F32 && b_dtype == ROSKO_BF16 && f[3] >= kBf16DenseDensity)
+    *index = kDenseCandidate;
+  return ROSKO_OK;
+}
+
 // Host forward pass of the plan network and its arg-min (see rosko.h).
 int32_t rosko_plan_select(const float* f, const float* params, const float* mu,
-                          const float* sigma, int32_t* index, int32_t* mr, rosko_plan* plan) {
+                          const float* sigma, int32_t val_dtype, int32_t b_dtype,
+                          int32_t* index, int32_t* mr, rosko_plan* plan) {
   clear_error();
   RK_REQUIRE(f && index && mr && plan, ROSKO_EINVAL, "null argument");
   int32_t c = 0;
@@ -709,6 +729,8 @@ int32_t rosko_plan_select(const float* f, const float* params, const float* mu,
       }
     }
   }
+  int32_t st = rosko_sched_precision(f, val_dtype, b_dtype, &c);
+  if (st) return st;
   *index = c;
   return rosko_sched_candidate(c, mr, plan);
 }

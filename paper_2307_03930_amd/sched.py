@@ -190,10 +190,24 @@ def load(device="cuda", path: str = WEIGHTS) -> MLP | None:
 _NETS: dict = {}
 
 
-def plan_select(f_host: np.ndarray, weights: dict | None = None):
+_DT = {"f32": L.ROSKO_F32, "bf16": L.ROSKO_BF16, "fp8": L.ROSKO_FP8_E4M3}
+
+
+def precision_rule(f_host: np.ndarray, index: int, val_dtype="f32", b_dtype="f32") -> int:
+    """The library's value-type rule (rosko_sched_precision) applied to a
+    candidate index chosen for FP32 operands."""
+    f = np.ascontiguousarray(f_host, np.float32)
+    idx = C.c_int32(int(index))
+    L.check(L.lib().rosko_sched_precision(f.ctypes.data_as(C.c_void_p), _DT[val_dtype],
+                                          _DT[b_dtype], C.byref(idx)))
+    return int(idx.value)
+
+
+def plan_select(f_host: np.ndarray, weights: dict | None = None, val_dtype="f32",
+                b_dtype="f32"):
     """(candidate index, panel height, plan) from rosko_plan_select: the host
     forward pass of the network given as its JSON dict (weights.json), or
-    the analytic rule when None."""
+    the analytic rule when None, then the value-type rule."""
     f = np.ascontiguousarray(f_host, np.float32)
     idx, mr, plan = C.c_int32(-1), C.c_int32(0), L.RoskoPlan()
     if weights is None:
@@ -201,8 +215,8 @@ def plan_select(f_host: np.ndarray, weights: dict | None = None):
     else:
         keep = [np.ascontiguousarray(weights[k], np.float32) for k in ("params", "mu", "sigma")]
         args = tuple(x.ctypes.data_as(C.c_void_p) for x in keep)
-    L.check(L.lib().rosko_plan_select(f.ctypes.data_as(C.c_void_p), *args, C.byref(idx),
-                                      C.byref(mr), C.byref(plan)))
+    L.check(L.lib().rosko_plan_select(f.ctypes.data_as(C.c_void_p), *args, _DT[val_dtype],
+                                      _DT[b_dtype], C.byref(idx), C.byref(mr), C.byref(plan)))
     return int(idx.value), int(mr.value), plan
 
 
@@ -229,18 +243,23 @@ def default_net(device=None) -> MLP | None:
     return _NETS[key]
 
 
-def choose(A: torch.Tensor, N: int, net: MLP | None = None, rule: str = "auto") -> int:
-    """Candidate index for A times N columns.  rule "auto": the network
-    `net`, else the committed network, else the analytic rule; rule
-    "analytic": the analytic rule."""
+def choose(A: torch.Tensor, N: int, net: MLP | None = None, rule: str = "auto",
+           val_dtype: str = "f32", b_dtype: str = "f32") -> int:
+    """Candidate index for A (stored as val_dtype) times N columns of a B of
+    b_dtype.  rule "auto": the network `net`, else the committed network,
+    else the analytic rule; rule "analytic": the analytic rule; then the
+    library's value-type rule."""
     if rule not in ("auto", "analytic"):
         raise ValueError(f"unknown rule {rule!r}")
     f = features(A, N)
     if rule == "auto" and net is None:
         net = default_net(A.device)
+    fh = f.cpu().numpy().reshape(-1)
     if rule == "analytic" or net is None:
-        return analytic(f.cpu().numpy())
-    return int(net.choose(f.view(1, F)).item())
+        idx = analytic(fh)
+    else:
+        idx = int(net.choose(f.view(1, F)).item())
+    return precision_rule(fh, idx, val_dtype, b_dtype)
 
 
 def chooser_name(device=None) -> str:

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.rosko_abi_version() == 7
+    assert lib.rosko_abi_version() == 8
     assert lib.rosko_status_str(L.ROSKO_EINVAL) == b"ROSKO_EINVAL"
     assert lib.rosko_status_str(123) == b"ROSKO_UNKNOWN"
 
@@ -312,13 +312,28 @@ def test_sched_candidates_and_analytic_rule():
         assert lib.rosko_sched_analytic(f, C.byref(idx)) == 0 and idx.value == want, (d, lN)
         # plan selection without a network is the rule, with the candidate's plan
         i2, m2, p2 = C.c_int32(-1), C.c_int32(0), L.RoskoPlan()
-        assert lib.rosko_plan_select(f, None, None, None, C.byref(i2), C.byref(m2),
-                                     C.byref(p2)) == 0
+        assert lib.rosko_plan_select(f, None, None, None, L.ROSKO_F32, L.ROSKO_F32,
+                                     C.byref(i2), C.byref(m2), C.byref(p2)) == 0
         assert i2.value == want and (m2.value, p2.path, p2.cols_per_lane) == seen[want]
+        # the value-type rule: BF16/FP8 values times a BF16 B go dense from
+        # density 0.025 up; FP32 operands, or an FP32 B, keep the choice
+        for vd, bd in ((L.ROSKO_BF16, L.ROSKO_BF16), (L.ROSKO_FP8_E4M3, L.ROSKO_BF16),
+                       (L.ROSKO_F32, L.ROSKO_BF16), (L.ROSKO_BF16, L.ROSKO_F32)):
+            assert lib.rosko_plan_select(f, None, None, None, vd, bd, C.byref(i2),
+                                         C.byref(m2), C.byref(p2)) == 0
+            mfma = vd != L.ROSKO_F32 and bd == L.ROSKO_BF16
+            assert i2.value == (6 if mfma and d >= 0.025 else want), (d, lN, vd, bd)
+    for d, want in ((0.0249, 1), (0.025, 6), (0.9, 6)):
+        f[3], f[2], idx.value = d, 10.0, 1
+        assert lib.rosko_sched_precision(f, L.ROSKO_BF16, L.ROSKO_BF16, C.byref(idx)) == 0
+        assert idx.value == want
+    assert lib.rosko_sched_precision(f, 7, L.ROSKO_BF16, C.byref(idx)) == L.ROSKO_EINVAL
+    assert lib.rosko_sched_precision(f, L.ROSKO_BF16, L.ROSKO_FP8_E4M3,
+                                     C.byref(idx)) == L.ROSKO_EINVAL
     # a network without its normalisation is refused
     w = (C.c_float * 8000)()
-    assert lib.rosko_plan_select(f, w, None, None, C.byref(i2), C.byref(m2),
-                                 C.byref(p2)) == L.ROSKO_EINVAL
+    assert lib.rosko_plan_select(f, w, None, None, L.ROSKO_F32, L.ROSKO_F32, C.byref(i2),
+                                 C.byref(m2), C.byref(p2)) == L.ROSKO_EINVAL
     n = C.c_int64(0)
     assert lib.rosko_mlp_param_count(16, 64, 7, C.byref(n)) == 0
     assert n.value == 16 * 64 + 64 + 64 * 64 + 64 + 64 * 7 + 7

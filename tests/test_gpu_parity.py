@@ -429,7 +429,8 @@ def test_spmm_precision_form_full(s, dtype):
     pr, c_src, scale = precision_reference(s)
     Ad = dev(pr.A)
     Bd = dev(pr.B).to(torch.bfloat16) if dtype != "f32" else dev(pr.B)
-    mr_s, cand = sched.candidate(sched.choose(Ad, pr.B.shape[1]))
+    mr_s, cand = sched.candidate(sched.choose(Ad, pr.B.shape[1], val_dtype=dtype,
+                                              b_dtype="f32" if dtype == "f32" else "bf16"))
     tol = {"f32": TOL_F32, "bf16": TOL_BF16, "fp8": TOL_FP8}[dtype]
     for mr, plan in ((32, None), (mr_s, cand)):
         P = ops.pack(Ad, mr, dtype)
