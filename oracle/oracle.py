@@ -72,6 +72,8 @@ def lib():
         L.ro_grad_dA_packed_par.argtypes = [i64, i32, p, p, p, p, p, p, i64, p, i64, i64, p,
                                             i32]
         L.ro_grad_dA_packed_par.restype = None
+        L.ro_conv3x3.argtypes = [p, i64, i64, i64, i64, p, p, i32, i32]
+        L.ro_conv3x3.restype = None
         L.ro_records.argtypes = [i64, i64, i32, i32, i32, p, p, p, p, p, p, p, p]
         L.ro_records.restype = i64
         _lib = L
@@ -308,3 +310,21 @@ def spmm_csr_rows(row_ptr, col_idx, val, B, rows) -> np.ndarray:
 def abs_spmm_csr_rows(row_ptr, col_idx, val, B, rows) -> np.ndarray:
     """The same rows of |A| |B| (the error scale of a computed product)."""
     return _csr_rows(row_ptr, col_idx, val, B, rows, True)
+
+
+# ----------------------------------------------------- direct convolution
+def conv3x3_direct(A: np.ndarray, X: np.ndarray, threads: int = 1,
+                   absolute: bool = False) -> np.ndarray:
+    """FP64 direct 3x3 convolution (stride 1, zero padding 1) of X (C_in, H,
+    W) with the weight matrix A (C_out x C_in*9, column c*9 + ky*3 + kx) over
+    A's kept entries: the product the method computes without im2col (Sec. 1).
+    absolute: the same sum of |weight| |input| (the error scale).
+    Returns (C_out, H, W)."""
+    A, X = _f32(A), _f32(X)
+    C_out, K = A.shape
+    C_in, H, W = X.shape
+    assert K == 9 * C_in
+    out = np.empty((C_out, H, W), np.float64)
+    lib().ro_conv3x3(_ptr(A), C_out, C_in, H, W, _ptr(X), _ptr(out), 1 if absolute else 0,
+                     max(1, threads))
+    return out

@@ -25,6 +25,10 @@
  *                     training decomposition, Sec. 5.4), over A's nonzeros.
  *   ro_grad_dA_packed dA = (dC B^T) restricted to A's nonzeros, emitted in
  *                     packed order (an SDDMM on A's mask).
+ *   ro_conv3x3        direct 3x3 convolution (stride 1, zero padding 1) with
+ *                     the weight matrix A (C_out x C_in*9, column c*9+ky*3+kx),
+ *                     by its definition over A's nonzeros: the product the
+ *                     method computes without forming im2col (Sec. 1).
  *
  * Readings of the paper taken here:
  *   - "A[k + mK] != 0" is tested on the bits: (bits & 0x7fffffff) != 0, so
@@ -471,6 +475,40 @@ void ro_grad_dA_packed_par(int64_t M, int32_t mr, const int64_t *panel_col_ptr,
         double acc = 0.0;
         for (int64_t n = 0; n < N; ++n) acc += (double)g[n] * (double)b[n];
         dA[z] = acc;
+      }
+    }
+  }
+  (void)threads;
+}
+
+/* out[o][y][x] = sum over kept A[o][c*9 + ky*3 + kx] of that weight times
+ * X[c][y+ky-1][x+kx-1] (zero outside the C_in x H x W input); with
+ * absolute != 0 the same sum of |weight| * |input| (the error scale).  FP64,
+ * weights in ascending column order; rows o split over the threads. */
+void ro_conv3x3(const float *A, int64_t C_out, int64_t C_in, int64_t H, int64_t W,
+                const float *X, double *out, int32_t absolute, int32_t threads) {
+  const int64_t K = C_in * 9;
+#ifdef _OPENMP
+  #pragma omp parallel for num_threads(threads) schedule(dynamic, 1)
+#endif
+  for (int64_t o = 0; o < C_out; ++o) {
+    double *y_o = out + o * H * W;
+    for (int64_t i = 0; i < H * W; ++i) y_o[i] = 0.0;
+    for (int64_t k = 0; k < K; ++k) {
+      float wv = A[o * K + k];
+      if (!ro_is_nonzero(wv)) continue;
+      double w = absolute ? fabs((double)wv) : (double)wv;
+      int64_t c = k / 9, ky = (k % 9) / 3, kx = k % 3;
+      const float *xc = X + c * H * W;
+      for (int64_t y = 0; y < H; ++y) {
+        int64_t yy = y + ky - 1;
+        if (yy < 0 || yy >= H) continue;
+        for (int64_t x = 0; x < W; ++x) {
+          int64_t xx = x + kx - 1;
+          if (xx < 0 || xx >= W) continue;
+          double v = (double)xc[yy * W + xx];
+          y_o[y * W + x] += w * (absolute ? fabs(v) : v);
+        }
       }
     }
   }

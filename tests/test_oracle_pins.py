@@ -304,6 +304,34 @@ def test_power_law_graph_structure():
     assert d.max() > 5 * d.mean()        # heavy tail
 
 
+def test_conv3x3_direct_hand_case():
+    # one input channel 3 x 3 holding 1..9, one output channel; the centre tap
+    # (ky = kx = 1) copies the input, the top-left tap (ky = kx = 0) shifts it
+    # down-right with zeros entering, so out = X + 2 * shift(X)
+    X = np.arange(1, 10, dtype=np.float32).reshape(1, 3, 3)
+    A = np.zeros((1, 9), np.float32)
+    A[0, 4] = 1.0
+    A[0, 0] = 2.0
+    want = X[0].astype(np.float64).copy()
+    want[1:, 1:] += 2.0 * X[0, :-1, :-1]
+    np.testing.assert_array_equal(O.conv3x3_direct(A, X)[0], want)
+    # the scale uses |weight| |input|
+    np.testing.assert_array_equal(O.conv3x3_direct(-A, -X, absolute=True)[0], want)
+
+
+def test_conv3x3_direct_equals_im2col_route():
+    """The direct definition against the im2col route (im2col then the CSR
+    definition of the product), on a pruned layer with ragged sizes."""
+    g = synth.rng(41)
+    X = np.maximum(g.standard_normal((5, 7, 9)), 0).astype(np.float32)
+    A = synth.sparse_matrix(6, 45, 0.3, 42)
+    direct = O.conv3x3_direct(A, X)
+    via = O.spmm(A, synth.im2col_3x3(X)).reshape(6, 7, 9)
+    scale = O.conv3x3_direct(A, X, absolute=True)
+    assert np.all(np.abs(direct - via) <= 1e-14 * scale + 1e-300)
+    np.testing.assert_array_equal(O.conv3x3_direct(A, X, threads=4), direct)
+
+
 def test_threaded_oracle_routines_equal_single_thread():
     A = synth.sparse_matrix(70, 90, 0.2, 27)
     B = synth.dense_normal(90, 45, 28)
