@@ -428,6 +428,51 @@ def run_gcn(args):
                       "unit": "us", "data": "synthetic", "graphs": out}), flush=True)
 
 
+def run_conv(args):
+    """Sparse direct convolution (no im2col) against the im2col route, for the
+    pruned 3x3 layer of the CNN workload: 256 -> 256 channels on 56 x 56
+    ReLU(N(0,1)) activations, weights pruned to 70..99.8%, FP32.  Direct: the
+    shifted input copies plus the SpMM over the padded-pitch grid (the
+    records remapped once per input size).  im2col route: the im2col matrix
+    (torch unfold) plus the SpMM.  Same packed weight, panel height by the
+    scheduler for the im2col product."""
+    import numpy as np
+    import torch
+    import torch.nn.functional as F
+    from paper_2307_03930_amd import ops, sched, synth
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(np.maximum(synth.rng(3).standard_normal((256, 56, 56)), 0)
+                         .astype(np.float32)).to(dev)
+    rows = []
+    for sp in synth.CNN_SPARSITIES:
+        A = torch.from_numpy(synth.cnn_weights(sp)).to(dev)
+        mr, _ = sched.candidate(sched.choose(A, 3136))
+        P = ops.pack(A, mr)
+        layer = ops.ConvLayer(P, 256, 56, 56)
+        Yq = torch.empty((256, 56 * layer.Wq), dtype=torch.float32, device=dev)
+        C = torch.empty((256, 3136), dtype=torch.float32, device=dev)
+        sw = torch.empty(max(ops.spmm_workspace_size(P, 3136), 1), dtype=torch.uint8,
+                         device=dev)
+        t_direct = _time_us(lambda: layer.run(X, Yq), args.reps)
+        t_input = _time_us(lambda: ops.L.lib().rosko_conv_input(
+            ops._ptr(X), 256, 56, 56, ops._ptr(layer.Bc), ops._stream_ptr()), args.reps)
+
+        def im2col_route():
+            B = F.unfold(X.unsqueeze(0), 3, padding=1)[0]
+            ops.spmm(P, B, C, ws=sw)
+        t_im2col = _time_us(im2col_route, args.reps)
+        B = F.unfold(X.unsqueeze(0), 3, padding=1)[0].contiguous()
+        t_spmm = _time_us(lambda: ops.spmm(P, B, C, ws=sw), args.reps)
+        rows.append({"sparsity": sp, "mr": mr, "nnz": P.nnz,
+                     "direct_us": round(t_direct, 2), "direct_input_copies_us": round(t_input, 2),
+                     "im2col_route_us": round(t_im2col, 2), "spmm_on_im2col_us": round(t_spmm, 2),
+                     "speedup_direct_vs_im2col_route": round(t_im2col / t_direct, 2)})
+        del A, P, layer, Yq, C, sw, B
+    print(json.dumps({"workload": "sparse direct 3x3 convolution 256->256 channels at 56x56 "
+                                  "(stride 1, padding 1) vs im2col + SpMM, FP32",
+                      "unit": "us", "data": "synthetic", "per_sparsity": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -444,7 +489,8 @@ def main():
                     help="panel height for every matrix (default: the library's analytic "
                          "plan rule picks it per matrix)")
     ap.add_argument("--graphs", default=None, help="gcn workload: comma-separated graph names")
-    ap.add_argument("--workload", choices=("cnn", "precision", "backward", "training", "gcn"),
+    ap.add_argument("--workload", choices=("cnn", "precision", "backward", "training", "gcn",
+                                           "conv"),
                     default="cnn",
                     help="cnn: the pruned-CNN sweep (the headline line); precision: the "
                          "BF16 / FP8 value forms at 4096x4096; backward: forward + backward "
@@ -464,6 +510,8 @@ def main():
         return run_training(args)
     if args.workload == "gcn":
         return run_gcn(args)
+    if args.workload == "conv":
+        return run_conv(args)
 
     import numpy as np
     import torch

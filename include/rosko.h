@@ -293,6 +293,54 @@ int32_t rosko_spmm(const rosko_packed *A, const void *B, int32_t b_dtype, int64_
                    int64_t ldb, float *C, int64_t ldc, int32_t beta, const rosko_plan *plan,
                    void *ws, size_t ws_bytes, void *stream);
 
+/* ---- sparse direct convolution (Sec. 1: the outer-product method applied
+ * to convolution without im2col) ----------------------------------------
+ * A 3x3 convolution, stride 1, zero padding 1, of a channels-first input X
+ * (device FP32, C_in x H x W) with a pruned weight, as the row-skipping
+ * product of the packed weight matrix A (C_out x 9*C_in, column
+ * c*9 + ky*3 + kx -- the im2col order; packed with rosko_pack) and the input
+ * itself.  The output is produced on a padded-pitch grid: Yq[o][y*Wq + x] is
+ * Y[o][y][x] for x < W; columns x >= W of each grid row hold values of no
+ * meaning.  Row k of the implicit im2col matrix is the run of the
+ * zero-padded input (C_in planes of (H+2) x Wq, the image at rows 1..H and
+ * columns 1..W) that starts at c*(H+2)*Wq + ky*Wq + kx, so the SpMM kernels
+ * run unchanged on records that name those starts; the input is stored four
+ * times, copy r shifted left by r elements, so every start is a multiple of
+ * 4 elements of one copy (aligned vector loads).  Limit: 4*T < 2^24. */
+
+/* Row pitch Wq (>= W + 2, H*Wq a multiple of 4) and copy length T (host). */
+int32_t rosko_conv_geometry(int32_t C_in, int32_t H, int32_t W, int64_t *Wq, int64_t *T);
+
+/* Writes the four shifted copies of the zero-padded input: Bc (device,
+ * 4*T floats).  Asynchronous. */
+int32_t rosko_conv_input(const float *X, int32_t C_in, int32_t H, int32_t W, float *Bc,
+                         void *stream);
+
+/* A's column records with each column index replaced by its tap's start in
+ * the four copies (for this C_in, H, W), into rec_out (device, rec_cap >=
+ * A->nrec records of 16 dwords).  A->K must be 9*C_in and A->nrec known.
+ * Asynchronous. */
+int32_t rosko_conv_records(const rosko_packed *A, int32_t C_in, int32_t H, int32_t W,
+                           uint32_t *rec_out, int64_t rec_cap, void *stream);
+
+/* Workspace bytes of rosko_conv for A and plan (NULL: automatic), as
+ * rosko_spmm's for N = H*Wq columns. */
+int32_t rosko_conv_workspace_size(const rosko_packed *A, int32_t H, int32_t W,
+                                  const rosko_plan *plan, size_t *bytes);
+
+/* Yq = conv(X) (beta 0) or Yq += conv(X) (beta 1) on the padded-pitch grid:
+ * Yq device FP32, A->M x (H*Wq), ldy >= H*Wq; Bc from rosko_conv_input,
+ * rec_conv from rosko_conv_records.  Sparse path only (a dense plan returns
+ * ROSKO_EUNSUPPORTED); FP8 row scales and A's row order apply as in
+ * rosko_spmm.  Asynchronous. */
+int32_t rosko_conv(const rosko_packed *A, const uint32_t *rec_conv, const float *Bc,
+                   int32_t C_in, int32_t H, int32_t W, float *Yq, int64_t ldy, int32_t beta,
+                   const rosko_plan *plan, void *ws, size_t ws_bytes, void *stream);
+
+/* Y (device, C_out x H x W) = the meaningful columns of Yq.  Asynchronous. */
+int32_t rosko_conv_unpad(const float *Yq, int64_t ldy, int64_t C_out, int32_t H, int32_t W,
+                         float *Y, void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, hosts that forbid allocation): rosko_spmm on
  * the sparse path with no workspace argument.  The K-split partial tiles go
@@ -446,7 +494,7 @@ int32_t rosko_plan_select(const float *features_host, const float *params, const
 /* ---- errors ----------------------------------------------------------- */
 const char *rosko_status_str(int32_t status);
 const char *rosko_last_error(void);   /* per host thread; "" if none */
-int32_t rosko_abi_version(void);      /* 8 */
+int32_t rosko_abi_version(void);      /* 9 */
 
 #ifdef __cplusplus
 }

@@ -89,6 +89,14 @@ SIGNATURES = {
     "rosko_pack_csr_result": (_I32, [_P, _SZ, C.POINTER(RoskoPacked), _P]),
     "rosko_row_order_workspace_size": (_I32, [_I64, C.POINTER(_SZ)]),
     "rosko_row_order": (_I32, [_P, _I64, _I32, _I32, _P, _SZ, _P, _P]),
+    "rosko_conv_geometry": (_I32, [_I32, _I32, _I32, C.POINTER(_I64), C.POINTER(_I64)]),
+    "rosko_conv_input": (_I32, [_P, _I32, _I32, _I32, _P, _P]),
+    "rosko_conv_records": (_I32, [C.POINTER(RoskoPacked), _I32, _I32, _I32, _P, _I64, _P]),
+    "rosko_conv_workspace_size": (_I32, [C.POINTER(RoskoPacked), _I32, _I32,
+                                         C.POINTER(RoskoPlan), C.POINTER(_SZ)]),
+    "rosko_conv": (_I32, [C.POINTER(RoskoPacked), _P, _P, _I32, _I32, _I32, _P, _I64, _I32,
+                          C.POINTER(RoskoPlan), _P, _SZ, _P]),
+    "rosko_conv_unpad": (_I32, [_P, _I64, _I64, _I32, _I32, _P, _P]),
     "rosko_spmm_workspace_size": (_I32, [C.POINTER(RoskoPacked), _I64, C.POINTER(RoskoPlan),
                                          C.POINTER(_SZ)]),
     "rosko_spmm": (_I32, [C.POINTER(RoskoPacked), _P, _I32, _I64, _I64, _P, _I64, _I32,

@@ -99,7 +99,7 @@ static int32_t check_packed_for_read(const rosko_packed* A) {
 
 extern "C" {
 
-int32_t rosko_abi_version(void) { return 8; }
+int32_t rosko_abi_version(void) { return 9; }
 
 const char* rosko_last_error(void) { return g_err; }
 
@@ -534,6 +534,112 @@ int32_t rosko_scatter_dense(const rosko_packed* A, const float* vals, int64_t n_
   RK_REQUIRE(vals != nullptr && out != nullptr, ROSKO_EINVAL, "null argument");
   (void)hipGetLastError();
   return launch_scatter_dense(A, vals, n_vals, out, ldo, static_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------- direct convolution
+
+static int32_t check_conv_shape(int64_t C_in, int64_t H, int64_t W) {
+  RK_REQUIRE(C_in >= 1 && H >= 1 && W >= 1, ROSKO_EINVAL, "convolution sizes must be >= 1");
+  RK_REQUIRE(C_in < (int64_t(1) << 20) && H < (int64_t(1) << 20) && W < (int64_t(1) << 20),
+             ROSKO_EUNSUPPORTED, "convolution sizes too large");
+  const ConvGeom g = conv_geometry(C_in, H, W);
+  RK_REQUIRE(4 * g.T < (int64_t(1) << 24), ROSKO_EUNSUPPORTED,
+             "the padded input (4 x %lld elements) exceeds the records' 24-bit column field",
+             (long long)g.T);
+  return ROSKO_OK;
+}
+
+int32_t rosko_conv_geometry(int32_t C_in, int32_t H, int32_t W, int64_t* Wq, int64_t* T) {
+  clear_error();
+  RK_REQUIRE(Wq && T, ROSKO_EINVAL, "null argument");
+  int32_t st = check_conv_shape(C_in, H, W);
+  if (st) return st;
+  const ConvGeom g = conv_geometry(C_in, H, W);
+  *Wq = g.Wq;
+  *T = g.T;
+  return ROSKO_OK;
+}
+
+int32_t rosko_conv_input(const float* X, int32_t C_in, int32_t H, int32_t W, float* Bc,
+                         void* stream) {
+  clear_error();
+  int32_t st = check_conv_shape(C_in, H, W);
+  if (st) return st;
+  RK_REQUIRE(X && Bc, ROSKO_EINVAL, "null argument");
+  (void)hipGetLastError();
+  return launch_conv_input(X, C_in, H, W, Bc, s_of(stream));
+}
+
+int32_t rosko_conv_records(const rosko_packed* A, int32_t C_in, int32_t H, int32_t W,
+                           uint32_t* rec_out, int64_t rec_cap, void* stream) {
+  clear_error();
+  int32_t st = check_packed_for_read(A);
+  if (st) return st;
+  if ((st = check_conv_shape(C_in, H, W))) return st;
+  RK_REQUIRE(A->K == 9 * (int64_t)C_in, ROSKO_EINVAL, "A has %lld columns, expected 9 x %d",
+             (long long)A->K, C_in);
+  RK_REQUIRE(A->nrec >= 0, ROSKO_EINVAL, "A's record count is not known (pack result first)");
+  const int64_t nrec = std::min(A->nrec, A->nrec_cap);
+  RK_REQUIRE(rec_cap >= nrec, ROSKO_ESMALLBUF, "rec_out holds %lld records < %lld",
+             (long long)rec_cap, (long long)nrec);
+  RK_REQUIRE(nrec == 0 || rec_out != nullptr, ROSKO_EINVAL, "rec_out is null");
+  (void)hipGetLastError();
+  return launch_conv_records(A, nrec, C_in, H, W, rec_out, s_of(stream));
+}
+
+int32_t rosko_conv_workspace_size(const rosko_packed* A, int32_t H, int32_t W,
+                                  const rosko_plan* plan, size_t* bytes) {
+  clear_error();
+  RK_REQUIRE(A != nullptr && bytes != nullptr, ROSKO_EINVAL, "null argument");
+  *bytes = 0;
+  int32_t st = check_mr(A->mr);
+  if (st) return st;
+  RK_REQUIRE(A->K % 9 == 0 && A->K > 0, ROSKO_EINVAL, "A's columns are not 9 x C_in");
+  if ((st = check_conv_shape(A->K / 9, H, W))) return st;
+  const int64_t N = conv_geometry(A->K / 9, H, W).N;
+  rosko_plan p = plan ? *plan : auto_plan(A, N);
+  RK_REQUIRE(p.path != ROSKO_PATH_DENSE, ROSKO_EUNSUPPORTED,
+             "the direct convolution runs on the sparse path");
+  if ((st = normalize_plan(A, N, &p))) return st;
+  *bytes = spmm_ws_bytes(A, N, p);
+  return ROSKO_OK;
+}
+
+int32_t rosko_conv(const rosko_packed* A, const uint32_t* rec_conv, const float* Bc,
+                   int32_t C_in, int32_t H, int32_t W, float* Yq, int64_t ldy, int32_t beta,
+                   const rosko_plan* plan, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  int32_t st = check_packed_for_read(A);
+  if (st) return st;
+  if ((st = check_conv_shape(C_in, H, W))) return st;
+  RK_REQUIRE(A->K == 9 * (int64_t)C_in, ROSKO_EINVAL, "A has %lld columns, expected 9 x %d",
+             (long long)A->K, C_in);
+  RK_REQUIRE(beta == 0 || beta == 1, ROSKO_EINVAL, "beta must be 0 or 1");
+  const ConvGeom g = conv_geometry(C_in, H, W);
+  RK_REQUIRE(ldy >= g.N, ROSKO_EINVAL, "ldy %lld < H * Wq = %lld", (long long)ldy,
+             (long long)g.N);
+  RK_REQUIRE(A->M == 0 || (Yq && Bc && (rec_conv || A->nrec_cap == 0)), ROSKO_EINVAL,
+             "null argument");
+  rosko_plan p = plan ? *plan : auto_plan(A, g.N);
+  RK_REQUIRE(p.path != ROSKO_PATH_DENSE, ROSKO_EUNSUPPORTED,
+             "the direct convolution runs on the sparse path");
+  if ((st = normalize_plan(A, g.N, &p))) return st;
+  if (A->M == 0) return ROSKO_OK;
+  (void)hipGetLastError();
+  return launch_spmm_sparse_flat(A, rec_conv, Bc, 4 * g.T, g.N, Yq, ldy, beta, p,
+                                 static_cast<float*>(ws), ws_bytes, s_of(stream));
+}
+
+int32_t rosko_conv_unpad(const float* Yq, int64_t ldy, int64_t C_out, int32_t H, int32_t W,
+                         float* Y, void* stream) {
+  clear_error();
+  RK_REQUIRE(C_out >= 0 && H >= 1 && W >= 1, ROSKO_EINVAL, "bad size");
+  const int64_t Wq = conv_geometry(1, H, W).Wq;
+  RK_REQUIRE(ldy >= H * Wq, ROSKO_EINVAL, "ldy < H * Wq");
+  if (C_out == 0) return ROSKO_OK;
+  RK_REQUIRE(Yq && Y, ROSKO_EINVAL, "null argument");
+  (void)hipGetLastError();
+  return launch_conv_unpad(Yq, ldy, C_out, H, W, Wq, Y, s_of(stream));
 }
 
 // ---------------------------------------------------------- scheduler

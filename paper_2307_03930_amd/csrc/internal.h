@@ -103,6 +103,8 @@ struct SpmmArgs {
   int64_t n_chunks;    // ceil(N / (64 * cols_per_lane))
   int64_t rec_bound;   // records the record array holds (nrec when known, never above
                        // its capacity): every record read stays below it
+  int64_t b_rows;      // rows of B the buffer holds (K; more for the direct convolution,
+                       // whose records name element offsets of a flat input)
   int32_t mr, n_panels;
   int32_t beta;
   int32_t k_split;
@@ -123,6 +125,13 @@ size_t spmm_ws_bytes(const rosko_packed* A, int64_t N, const rosko_plan& p);
 int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype, int64_t N,
                            int64_t ldb, float* C, int64_t ldc, int32_t beta,
                            const rosko_plan& plan, float* ws, size_t ws_bytes, hipStream_t s);
+// The same with the records taken from `rec` (nullptr: A's) and B a flat
+// array of b_rows "rows" one element apart (ldb 1) whose row starts are all
+// multiples of 4 elements, so V-wide loads stay aligned (direct convolution).
+int32_t launch_spmm_sparse_flat(const rosko_packed* A, const uint32_t* rec, const float* B,
+                                int64_t b_rows, int64_t N, float* C, int64_t ldc, int32_t beta,
+                                const rosko_plan& plan, float* ws, size_t ws_bytes,
+                                hipStream_t s);
 int32_t launch_fill_zero(float* C, int64_t M, int64_t N, int64_t ldc, hipStream_t s);
 
 // Dense-MFMA path (dense.hip): workspace bytes (b_dtype ROSKO_F32 gives the
@@ -183,6 +192,21 @@ size_t order_ws_bytes_fixed(int64_t M);
 int32_t order_temp_bytes(int64_t M, size_t* bytes, hipStream_t s);
 int32_t launch_row_order(const int64_t* row_ptr, int64_t M, int32_t mr, int32_t mode,
                          void* ws, size_t ws_bytes, int32_t* perm, hipStream_t s);
+
+// ------------------------------------------------ direct convolution
+// Geometry of the padded-pitch grid (conv.hip): row pitch Wq >= W + 2 with
+// H * Wq a multiple of 4, plane (H + 2) * Wq, T the length of each of the
+// four shifted input copies, N = H * Wq output columns.
+struct ConvGeom {
+  int64_t Wq, plane, T, N;
+};
+ConvGeom conv_geometry(int64_t C_in, int64_t H, int64_t W);
+int32_t launch_conv_input(const float* X, int64_t C_in, int64_t H, int64_t W, float* Bc,
+                          hipStream_t s);
+int32_t launch_conv_records(const rosko_packed* A, int64_t nrec, int64_t C_in, int64_t H,
+                            int64_t W, uint32_t* rec_out, hipStream_t s);
+int32_t launch_conv_unpad(const float* Yq, int64_t ldy, int64_t C_out, int64_t H, int64_t W,
+                          int64_t Wq, float* Y, hipStream_t s);
 
 // Matrix row of packed row `row` under an optional row order (clamped into
 // 0..M-1, so no content of the order can move an access outside).

@@ -245,11 +245,15 @@ size_t spmm_ws_bytes(const rosko_packed* A, int64_t N, const rosko_plan& p) {
   return sizeof(float) * (size_t)p.k_split * (size_t)A->M * (size_t)N;
 }
 
-int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype, int64_t N,
-                           int64_t ldb, float* C, int64_t ldc, int32_t beta,
-                           const rosko_plan& plan, float* ws, size_t ws_bytes, hipStream_t s) {
+// Shared body: rec (A's or a caller's copy), B with b_rows rows of ldb
+// elements (flat: ldb 1 and every row start a multiple of 4 elements).
+static int32_t spmm_sparse_core(const rosko_packed* A, const uint32_t* rec, const void* B,
+                                int32_t b_dtype, int64_t N, int64_t ldb, int64_t b_rows,
+                                bool flat, float* C, int64_t ldc, int32_t beta,
+                                const rosko_plan& plan, float* ws, size_t ws_bytes,
+                                hipStream_t s) {
   SpmmArgs g{};
-  g.rec = A->rec;
+  g.rec = rec;
   g.row_scale = (A->val_dtype == ROSKO_FP8_E4M3) ? A->row_scale : nullptr;
   g.kblk_ptr = A->kblk_ptr;
   g.row_perm = A->row_perm;
@@ -261,6 +265,7 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
   g.N = N;
   g.ldb = ldb;
   g.ldc = ldc;
+  g.b_rows = b_rows;
   g.mr = A->mr;
   g.n_panels = A->n_panels;
   g.beta = beta;
@@ -272,10 +277,11 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
   // offsets and V-wide aligned B units, and stores V-wide C units.  When
   // the requested tile's V does not fit B and C (N, ldb, ldc or a pointer
   // not a multiple of V), the one-column tile (128 x 1) runs instead, which
-  // needs no alignment beyond the element size.  Beyond 32-bit offsets the
-  // call is refused.
+  // needs no alignment beyond the element size.  A flat B guarantees its row
+  // starts are multiples of 4 elements, so ldb does not enter.  Beyond
+  // 32-bit offsets the call is refused.
   auto vec_ok = [&](int v) {
-    return (ldb % v == 0) && (ldc % v == 0) && (N % v == 0) &&
+    return (flat || ldb % v == 0) && (ldc % v == 0) && (N % v == 0) &&
            ((uintptr_t)B % (eb * v) == 0) && ((uintptr_t)C % (4 * v) == 0);
   };
   int V = plan.cols_per_lane, MRt = tile_height(A->mr);
@@ -290,9 +296,9 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
   // a wavefront's records lie inside one panel: at most K kept columns of
   // ceil(mr / 12) records each (plus the loop's read-ahead)
   const uint64_t panel_rec = (uint64_t)A->K * (uint64_t)ceil_div(A->mr, kRecVals) + 64;
-  if ((uint64_t)A->K * (uint64_t)ldb * eb >= (1ull << 32) || panel_rec * 64u >= (1ull << 32)) {
+  if ((uint64_t)b_rows * (uint64_t)ldb * eb >= (1ull << 32) || panel_rec * 64u >= (1ull << 32)) {
     set_error("B (%lld x %lld elements) or a panel's records exceed 4 GiB of buffer offsets",
-              (long long)A->K, (long long)ldb);
+              (long long)b_rows, (long long)ldb);
     return ROSKO_EUNSUPPORTED;
   }
   g.n_chunks = ceil_div(N, 64 * V);
@@ -321,6 +327,21 @@ int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype
                        rs, A->row_perm, C, ldc, beta);
   ROSKO_LAUNCH_CHECK("k_reduce_splits");
   return ROSKO_OK;
+}
+
+int32_t launch_spmm_sparse(const rosko_packed* A, const void* B, int32_t b_dtype, int64_t N,
+                           int64_t ldb, float* C, int64_t ldc, int32_t beta,
+                           const rosko_plan& plan, float* ws, size_t ws_bytes, hipStream_t s) {
+  return spmm_sparse_core(A, A->rec, B, b_dtype, N, ldb, A->K, false, C, ldc, beta, plan, ws,
+                          ws_bytes, s);
+}
+
+int32_t launch_spmm_sparse_flat(const rosko_packed* A, const uint32_t* rec, const float* B,
+                                int64_t b_rows, int64_t N, float* C, int64_t ldc, int32_t beta,
+                                const rosko_plan& plan, float* ws, size_t ws_bytes,
+                                hipStream_t s) {
+  return spmm_sparse_core(A, rec ? rec : A->rec, B, ROSKO_F32, N, 1, b_rows, true, C, ldc,
+                          beta, plan, ws, ws_bytes, s);
 }
 
 }  // namespace rosko

@@ -147,17 +147,17 @@ k_spmm_rows(SpmmArgs g) {
       // 32-bit offsets from this run's first record and from B.  Each buffer
       // is sized exactly (the records from this run's first to the array's
       // end, capped below 4 GiB -- a run is far shorter; K rows of ldb
-      // elements), so the hardware returns zero for any load outside it
-      // instead of touching other memory
+      // elements; b_rows of them for a flat B), so the hardware returns zero
+      // for any load outside it instead of touching other memory
       constexpr uint32_t esz = TB == ROSKO_F32 ? 4 : 2;
       const int64_t rbytes = min((g.rec_bound - a) * 64, (int64_t)0xFFFFFFC0);
       const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
           (void*)(g.rec + a * 16), 0, (int)(uint32_t)rbytes, 0x00020000);
       const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)g.B, 0, (int)(uint32_t)(g.K * g.ldb * esz), 0x00020000);
+          (void*)g.B, 0, (int)(uint32_t)(g.b_rows * g.ldb * esz), 0x00020000);
       const int64_t cl = n0 < g.N - V ? n0 : g.N - V;
       RkLoop<MR, V, TB, DV>::run(acc, (uint32_t)n, rr, rb, (uint32_t)(g.ldb * esz),
-                             (uint32_t)(g.K - 1), (uint32_t)(lane & 15) * 4u,
+                             (uint32_t)(g.b_rows - 1), (uint32_t)(lane & 15) * 4u,
                              (uint32_t)(cl * esz));
     }
   }

@@ -7,6 +7,7 @@ torch, every step of the computation runs in librosko.so.
   spmm_backward(P, Pt, B, dC)   dB = A^T dC and dA (packed order)
   pack_csr(row_ptr, col, val)   Alg. 1 from CSR input (graphs), optional row order
   row_order(row_ptr, mr, mode)  the inspector's row order for pack_csr
+  ConvLayer(P, C_in, H, W)      sparse direct 3x3 convolution (no im2col)
 """
 from __future__ import annotations
 
@@ -379,3 +380,66 @@ def row_order(row_ptr: torch.Tensor, mr: int, mode: str = "balanced") -> torch.T
     L.check(L.lib().rosko_row_order(_ptr(row_ptr), M, mr, ORDERS[mode], _ptr(ws), ws.numel(),
                                     _ptr(perm), _stream_ptr()))
     return perm[:M]
+
+
+# ------------------------------------------------- direct convolution
+
+def conv_geometry(C_in: int, H: int, W: int) -> tuple[int, int]:
+    """(Wq, T): the padded row pitch and the length of each input copy."""
+    wq, t = C.c_int64(0), C.c_int64(0)
+    L.check(L.lib().rosko_conv_geometry(C_in, H, W, C.byref(wq), C.byref(t)))
+    return int(wq.value), int(t.value)
+
+
+class ConvLayer:
+    """A pruned 3x3 convolution (stride 1, padding 1) run as the sparse
+    direct convolution: P is the packed weight matrix (C_out x 9 C_in, the
+    im2col column order), whose records are remapped once for the input size
+    (C_in, H, W); run(X) returns the output on the padded-pitch grid
+    (C_out x H*Wq), unpad() the C_out x H x W output."""
+
+    def __init__(self, P: PackedMatrix, C_in: int, H: int, W: int, plan=None):
+        self.P, self.C_in, self.H, self.W, self.plan = P, C_in, H, W, plan
+        self.Wq, self.T = conv_geometry(C_in, H, W)
+        dev = P.rec.device
+        self.rec = torch.empty((max(P.nrec, 1), 16), dtype=torch.int32, device=dev)
+        self.Bc = torch.empty(4 * self.T, dtype=torch.float32, device=dev)
+        n = C.c_size_t(0)
+        st = P.struct()
+        L.check(L.lib().rosko_conv_workspace_size(C.byref(st), H, W,
+                                                  C.byref(plan) if plan is not None else None,
+                                                  C.byref(n)))
+        self.ws = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=dev)
+        self.ws_bytes = int(n.value)
+        self.remap()
+
+    def remap(self):
+        """Rewrites the records for the input geometry (after a repack of P)."""
+        st = self.P.struct()
+        L.check(L.lib().rosko_conv_records(C.byref(st), self.C_in, self.H, self.W,
+                                           _ptr(self.rec), self.rec.shape[0], _stream_ptr()))
+
+    def run(self, X: torch.Tensor, out: torch.Tensor | None = None, beta: int = 0):
+        if not (X.is_cuda and X.dtype == torch.float32 and X.is_contiguous()
+                and tuple(X.shape) == (self.C_in, self.H, self.W)):
+            raise ValueError("X must be a contiguous float32 CUDA tensor of (C_in, H, W)")
+        L.check(L.lib().rosko_conv_input(_ptr(X), self.C_in, self.H, self.W, _ptr(self.Bc),
+                                         _stream_ptr()))
+        N = self.H * self.Wq
+        if out is None:
+            if beta:
+                raise ValueError("beta = 1 needs out")
+            out = torch.empty((self.P.M, N), dtype=torch.float32, device=X.device)
+        st = self.P.struct()
+        pl = C.byref(self.plan) if self.plan is not None else None
+        L.check(L.lib().rosko_conv(C.byref(st), _ptr(self.rec), _ptr(self.Bc), self.C_in,
+                                   self.H, self.W, _ptr(out), max(out.stride(0), 1), beta, pl,
+                                   _ptr(self.ws) if self.ws_bytes else None, self.ws_bytes,
+                                   _stream_ptr()))
+        return out
+
+    def unpad(self, Yq: torch.Tensor) -> torch.Tensor:
+        Y = torch.empty((self.P.M, self.H, self.W), dtype=torch.float32, device=Yq.device)
+        L.check(L.lib().rosko_conv_unpad(_ptr(Yq), max(Yq.stride(0), 1), self.P.M, self.H,
+                                         self.W, _ptr(Y), _stream_ptr()))
+        return Y

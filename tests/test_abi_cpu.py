@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.rosko_abi_version() == 8
+    assert lib.rosko_abi_version() == 9
     assert lib.rosko_status_str(L.ROSKO_EINVAL) == b"ROSKO_EINVAL"
     assert lib.rosko_status_str(123) == b"ROSKO_UNKNOWN"
 
@@ -395,3 +395,38 @@ def test_csr_and_row_order_argument_checks():
     assert lib.rosko_row_order(None, 0, 4, 0, None, 0, None, None) == L.ROSKO_OK
     assert lib.rosko_row_order_workspace_size(0, C.byref(n)) == 0 and n.value == 0
     assert lib.rosko_row_order_workspace_size(-2, C.byref(n)) == L.ROSKO_EINVAL
+
+
+def test_conv_geometry_and_argument_checks():
+    """The padded grid's pitch and copy length, and the direct convolution's
+    host-side refusals."""
+    lib = L.lib()
+    wq, t = C.c_int64(0), C.c_int64(0)
+    for (ci, h, w, want_wq) in ((256, 56, 56, 58), (5, 7, 9, 12), (3, 1, 1, 4), (16, 14, 14, 16),
+                                (2, 3, 5, 8)):
+        assert lib.rosko_conv_geometry(ci, h, w, C.byref(wq), C.byref(t)) == 0
+        assert wq.value == want_wq and (h * wq.value) % 4 == 0 and wq.value >= w + 2
+        plane = (h + 2) * wq.value
+        assert t.value % 4 == 0 and ci * plane + 5 <= t.value <= ci * plane + 11
+    assert lib.rosko_conv_geometry(0, 4, 4, C.byref(wq), C.byref(t)) == L.ROSKO_EINVAL
+    # 4 T beyond the records' 24-bit column field
+    assert lib.rosko_conv_geometry(4096, 64, 64, C.byref(wq), C.byref(t)) == \
+        L.ROSKO_EUNSUPPORTED
+    fake = C.c_void_p(0x1000)
+    s = _packed(8, 45, 4)                   # 9 * 5 columns
+    s.nrec = 3
+    assert lib.rosko_conv_records(C.byref(s), 4, 7, 9, fake, 10, None) == L.ROSKO_EINVAL
+    assert lib.rosko_conv_records(C.byref(s), 5, 7, 9, fake, 2, None) == L.ROSKO_ESMALLBUF
+    s.nrec = -1
+    assert lib.rosko_conv_records(C.byref(s), 5, 7, 9, fake, 10, None) == L.ROSKO_EINVAL
+    plan = L.RoskoPlan()
+    plan.path = L.ROSKO_PATH_DENSE
+    n = C.c_size_t(0)
+    assert lib.rosko_conv_workspace_size(C.byref(s), 7, 9, C.byref(plan), C.byref(n)) == \
+        L.ROSKO_EUNSUPPORTED
+    assert lib.rosko_conv(C.byref(s), fake, fake, 5, 7, 9, fake, 84, 0, C.byref(plan), None, 0,
+                          None) == L.ROSKO_EUNSUPPORTED
+    assert lib.rosko_conv(C.byref(s), fake, fake, 5, 7, 9, fake, 83, 0, None, None, 0,
+                          None) == L.ROSKO_EINVAL         # ldy < H * Wq = 84
+    assert lib.rosko_conv(C.byref(s), fake, fake, 5, 7, 9, fake, 84, 2, None, None, 0,
+                          None) == L.ROSKO_EINVAL         # beta
