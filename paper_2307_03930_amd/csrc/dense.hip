@@ -6,10 +6,12 @@
 // above about 75% sparsity, Sec. 5.3, and training hands lower sparsities to
 // a dense library, Sec. 5.4).  This path multiplies every panel densely,
 // starting from the packed form (A itself is not an argument of rosko_spmm):
-//   1. k_densify:     one workgroup per panel zero-fills the panel's rows of
-//                     the dense copy Ad (Mp x Kp) and scatters the column
-//                     records' values into them -- exact, since the records
-//                     hold the values packing stored;
+//   1. k_densify_lds: (panels of up to 64 rows) one workgroup per (panel,
+//                     256-column block) builds its block of the dense copy
+//                     Ad (Mp x Kp) in LDS from the column records -- exact,
+//                     since the records hold the values packing stored --
+//                     and writes it out as whole rows; k_densify (taller
+//                     panels) zero-fills the block in Ad and scatters into it;
 //   2. k_transpose_b: Bt (Np x Kp) = B^T, so both MFMA operands run along k;
 //   3. k_dense_gemm:  C = s_m * Ad Bt^T (+ C) on 128 x 128 tiles, four
 //                     wavefronts of 2 x 2 blocks of 32 x 32, K steps staged
@@ -92,6 +94,65 @@ k_densify(const uint32_t* __restrict__ rec, const int64_t* __restrict__ kblk, in
       T* dst = Ad + (r0 + row) * Kp + k;
       if constexpr (BF) *dst = (uint16_t)(bits >> 16);   // values exactly BF16 here
       else *dst = __uint_as_float(bits);
+    }
+  }
+}
+
+// Panels of at most MAXR rows: workgroup (p, q) builds the block of rows
+// [p*mr, p*mr + rows_p) and columns [q*kDenseLdsK, ...) of Ad in LDS -- zero
+// it, scatter the panel's records with k in the block into it -- and writes
+// it out as whole rows with 16-byte stores, so Ad's lines are written once
+// and completely; the last panel's workgroups also zero the padding rows up
+// to Mp.  Same record range and skips as k_densify.
+constexpr int kDenseLdsK = 256;  // a multiple of ROSKO_KSTEP and of kKAlign
+constexpr int kDenseLdsRows = 64;
+template <bool BF>
+__global__ void __launch_bounds__(256)
+k_densify_lds(const uint32_t* __restrict__ rec, const int64_t* __restrict__ kblk, int64_t nkb,
+              int64_t rec_bound, int32_t mr, int32_t n_panels, int64_t M, int64_t K,
+              int64_t Mp, int64_t Kp, typename Op<BF>::T* __restrict__ Ad) {
+  using T = typename Op<BF>::T;
+  constexpr int EPC = 16 / sizeof(T);             // elements per 16 bytes
+  constexpr int RQ = kDenseLdsK / EPC;            // 16-byte pieces per LDS row
+  __shared__ uint4 tile4[kDenseLdsRows * RQ];
+  T* tile = reinterpret_cast<T*>(tile4);
+  const int64_t p = blockIdx.x;
+  const int64_t k_lo = (int64_t)blockIdx.y * kDenseLdsK;
+  const int64_t k_hi = min(k_lo + kDenseLdsK, Kp);
+  const int64_t r0 = p * mr;
+  const int rows = (int)min((int64_t)min(mr, kDenseLdsRows), M - r0);
+  for (int i = threadIdx.x; i < rows * RQ; i += 256) tile4[i] = make_uint4(0u, 0u, 0u, 0u);
+  __syncthreads();
+  const int64_t jb = k_lo / ROSKO_KSTEP, je = min(ceil_div_dev(k_hi, ROSKO_KSTEP), nkb);
+  const int64_t a = min(max(kblk[p * (nkb + 1) + min(jb, nkb)], (int64_t)0), rec_bound);
+  const int64_t e = min(max(kblk[p * (nkb + 1) + je], a), rec_bound);
+  for (int64_t r = a + threadIdx.x; r < e; r += 256) {
+    const uint32_t* R = rec + r * 16;
+    const uint32_t hdr = R[0];
+    const int64_t k = hdr >> 8;
+    const int cnt = (int)(hdr & 0xFFu);
+    if (k < k_lo || k >= k_hi || k >= K || cnt > 12) continue;
+    const int kk = (int)(k - k_lo);
+    for (int t = 0; t < cnt; ++t) {
+      const int row = (int)((R[1 + t / 4] >> (8 * (t % 4))) & 0xFFu);
+      if (row >= rows) continue;
+      const uint32_t bits = R[4 + t];
+      if constexpr (BF) tile[row * kDenseLdsK + kk] = (uint16_t)(bits >> 16);   // exact BF16
+      else tile[row * kDenseLdsK + kk] = __uint_as_float(bits);
+    }
+  }
+  __syncthreads();
+  const int per_row = (int)((k_hi - k_lo) / EPC);
+  for (int i = threadIdx.x; i < rows * per_row; i += 256) {
+    const int r = i / per_row, c = i - r * per_row;
+    *reinterpret_cast<uint4*>(Ad + (r0 + r) * Kp + k_lo + c * EPC) = tile4[r * RQ + c];
+  }
+  if (p == n_panels - 1) {
+    const int pad = (int)(Mp - (r0 + rows));
+    for (int i = threadIdx.x; i < pad * per_row; i += 256) {
+      const int r = i / per_row, c = i - r * per_row;
+      *reinterpret_cast<uint4*>(Ad + (r0 + rows + r) * Kp + k_lo + c * EPC) =
+          make_uint4(0u, 0u, 0u, 0u);
     }
   }
 }
@@ -296,10 +357,15 @@ int32_t run_dense(const rosko_packed* A, const void* B, int32_t b_dtype, int64_t
   T* Bt = reinterpret_cast<T*>(static_cast<char*>(ws) + L.bt);
   const int64_t nkb = (A->K + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
   const int64_t rec_bound = A->nrec >= 0 ? std::min(A->nrec, A->nrec_cap) : A->nrec_cap;
-  const dim3 dg((unsigned)A->n_panels, (unsigned)ceil_div(L.Kp, kDensifyK));
-  hipLaunchKernelGGL(k_densify<BF>, dg, dim3(256), 0, s, A->rec,
-                     A->kblk_ptr, nkb, rec_bound, A->mr, A->n_panels, A->M, A->K, L.Mp, L.Kp,
-                     Ad);
+  if (A->mr <= kDenseLdsRows) {
+    const dim3 dg((unsigned)A->n_panels, (unsigned)ceil_div(L.Kp, kDenseLdsK));
+    hipLaunchKernelGGL(k_densify_lds<BF>, dg, dim3(256), 0, s, A->rec, A->kblk_ptr, nkb,
+                       rec_bound, A->mr, A->n_panels, A->M, A->K, L.Mp, L.Kp, Ad);
+  } else {
+    const dim3 dg((unsigned)A->n_panels, (unsigned)ceil_div(L.Kp, kDensifyK));
+    hipLaunchKernelGGL(k_densify<BF>, dg, dim3(256), 0, s, A->rec, A->kblk_ptr, nkb, rec_bound,
+                       A->mr, A->n_panels, A->M, A->K, L.Mp, L.Kp, Ad);
+  }
   ROSKO_LAUNCH_CHECK("k_densify");
   const dim3 tg((unsigned)(L.Np / 32), (unsigned)(L.Kp / 32));
   if (b_dtype == ROSKO_F32)
