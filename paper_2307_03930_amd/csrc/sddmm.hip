@@ -102,6 +102,10 @@ __device__ __forceinline__ float wave_sum_f32(float x) {
 constexpr int kSdLdsG = 4;       // workgroups per panel
 constexpr int kSdDepth = 4;      // B rows in flight per wavefront
 constexpr int kSdChunk = 1024;   // widest column chunk (VQ = 4)
+// Column chunk of the LDS kernel by panel height: 1024 columns for panels
+// of up to 8 rows (32 KB of dC rows), 512 for up to 16 rows (also 32 KB, so
+// as many workgroups share a CU).
+inline int64_t sddmm_chunk(int32_t mr) { return mr <= 8 ? kSdChunk : kSdChunk / 2; }
 
 template <int ROWS, int VQ>
 __global__ void __launch_bounds__(64 * kSdW)
@@ -228,8 +232,8 @@ k_sddmm_sum(const float* __restrict__ part, int32_t n_chunks, int64_t stride, in
 }  // namespace
 
 size_t sddmm_ws_bytes(const rosko_packed* A, int64_t N) {
-  if (A == nullptr || A->mr > 16 || N <= kSdChunk) return 0;
-  return sizeof(float) * (size_t)ceil_div(N, kSdChunk) * (size_t)A->nnz_cap;
+  if (A == nullptr || A->mr > 16 || N <= sddmm_chunk(A->mr)) return 0;
+  return sizeof(float) * (size_t)ceil_div(N, sddmm_chunk(A->mr)) * (size_t)A->nnz_cap;
 }
 
 int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const float* B,
@@ -240,7 +244,8 @@ int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const
   const int64_t nz_lim = std::min(A->nnz_cap, dA_cap);
   if (A->mr <= 16) {
     // LDS path: panels of up to 16 rows, N in chunks of up to 1024 columns
-    const int64_t n_chunks = ceil_div(std::max<int64_t>(N, 1), kSdChunk);
+    const int64_t chunk = sddmm_chunk(A->mr);
+    const int64_t n_chunks = ceil_div(std::max<int64_t>(N, 1), chunk);
     float* out = dA_val;
     if (n_chunks > 1) {
       const size_t need = sizeof(float) * (size_t)n_chunks * (size_t)A->nnz_cap;
@@ -264,15 +269,14 @@ int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const
                      A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M, A->K, A->mr,          \
                      A->n_panels, A->row_perm, dC, lddc, B, ldb, N, vec, ncols_lim, nz_out,  \
                      out)
-    const int64_t nc = n_chunks > 1 ? kSdChunk : N;   // columns of a chunk
+    const int64_t nc = n_chunks > 1 ? chunk : N;   // columns of a chunk
     if (A->mr <= 8) {
       if (nc <= 256) RK_SDL(8, 1);
       else if (nc <= 512) RK_SDL(8, 2);
       else RK_SDL(8, 4);
     } else {
       if (nc <= 256) RK_SDL(16, 1);
-      else if (nc <= 512) RK_SDL(16, 2);
-      else RK_SDL(16, 4);
+      else RK_SDL(16, 2);
     }
 #undef RK_SDL
     ROSKO_LAUNCH_CHECK("k_sddmm_lds");
@@ -305,8 +309,8 @@ int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const
 // (row() the optional row order), in
 // packed order: the inverse of packing for a dense M x K gradient (the
 // weight gradient of the training decomposition is dA on the mask, zero
-// elsewhere; the caller zero-fills out).  One workgroup per panel, threads
-// over the panel's kept columns; indices clamped as in the SDDMM.
+// elsewhere; the caller zero-fills out).  A panel's kept columns are dealt
+// to the threads of several workgroups; indices clamped as in the SDDMM.
 namespace rosko {
 namespace {
 __global__ void __launch_bounds__(256)
@@ -319,7 +323,8 @@ k_scatter_dense(const int64_t* __restrict__ panel_col_ptr, const int32_t* __rest
   const int rows = (int)min((int64_t)mr, M - p * mr);
   const int64_t c_hi = min(panel_col_ptr[p + 1], ncols_lim);
   const int64_t c_lo = min(max(panel_col_ptr[p], (int64_t)0), c_hi);
-  for (int64_t c = c_lo + threadIdx.x; c < c_hi; c += 256) {
+  for (int64_t c = c_lo + (int64_t)blockIdx.y * 256 + threadIdx.x; c < c_hi;
+       c += (int64_t)gridDim.y * 256) {
     const int64_t k = col_ind[c];
     if (k < 0 || k >= K) continue;
     const int64_t z0 = max(col_ptr[c], (int64_t)0);
@@ -335,7 +340,9 @@ k_scatter_dense(const int64_t* __restrict__ panel_col_ptr, const int32_t* __rest
 int32_t launch_scatter_dense(const rosko_packed* A, const float* vals, int64_t n_vals,
                              float* out, int64_t ldo, hipStream_t s) {
   if (A->n_panels == 0 || A->K == 0) return ROSKO_OK;
-  hipLaunchKernelGGL(k_scatter_dense, dim3((unsigned)A->n_panels), dim3(256), 0, s,
+  // the panel's kept columns are split over kScatterG workgroups
+  constexpr unsigned kScatterG = 16;
+  hipLaunchKernelGGL(k_scatter_dense, dim3((unsigned)A->n_panels, kScatterG), dim3(256), 0, s,
                      A->panel_col_ptr, A->col_ind, A->col_nnz, A->col_ptr, A->loc, A->M, A->K,
                      A->mr, A->row_perm, A->ncols_cap, std::min(A->nnz_cap, n_vals), vals, out,
                      ldo);
