@@ -118,12 +118,12 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
             float* __restrict__ out) {
   constexpr int RW = 256 * VQ;                    // LDS row width (floats)
   constexpr int RWD = ROWS / 4;                   // dwords of row bytes per column
+  static_assert(ROWS == 8 || ROWS == 16, "panels of 8 or 16 rows");
   __shared__ float4 sdc4[ROWS * RW / 4];
   float* sdc = reinterpret_cast<float*>(sdc4);
-  const int64_t chunk = blockIdx.x / ((int64_t)n_panels * kSdLdsG);
-  const int64_t pg = blockIdx.x % ((int64_t)n_panels * kSdLdsG);
-  const int64_t p = pg / kSdLdsG;
-  const int g = (int)(pg % kSdLdsG);
+  const int64_t chunk = blockIdx.y;
+  const int64_t p = blockIdx.x / kSdLdsG;
+  const int g = (int)(blockIdx.x % kSdLdsG);
   const int64_t n0 = chunk * RW;
   float* dst = out + chunk * nz_lim;
   const int lane = threadIdx.x & 63;
@@ -190,10 +190,9 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
 #pragma unroll
           for (int q = 0; q < RWD; ++q) rj[q] = __builtin_amdgcn_readlane(rw[q], j);
           for (int t = 0; t < n; ++t) {
-            uint32_t word = rj[0];
-#pragma unroll
-            for (int q = 1; q < RWD; ++q)
-              if (t / 4 == q) word = rj[q];
+            uint32_t word;
+            if constexpr (RWD == 2) word = t < 4 ? rj[0] : rj[1];
+            else word = t < 4 ? rj[0] : (t < 8 ? rj[1] : (t < 12 ? rj[2] : rj[3]));
             const int r = (int)((word >> (8 * (t & 3))) & (uint32_t)(ROWS - 1));
             const float4* row = sdc4 + (r * RW) / 4 + lane;
             float acc = 0.0f;
@@ -256,12 +255,12 @@ int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const
       }
       out = ws;
     }
-    const int64_t nb = (int64_t)A->n_panels * kSdLdsG * n_chunks;
-    if (nb > INT32_MAX) {
+    const int64_t nb = (int64_t)A->n_panels * kSdLdsG;
+    if (nb > INT32_MAX || n_chunks > 65535) {
       set_error("SDDMM grid too large");
       return ROSKO_EUNSUPPORTED;
     }
-    const dim3 grid((unsigned)nb);
+    const dim3 grid((unsigned)nb, (unsigned)n_chunks);
     const bool vec = (N % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)B % 16 == 0);
     const int64_t nz_out = n_chunks > 1 ? A->nnz_cap : nz_lim;
 #define RK_SDL(R_, VQ_)                                                                      \
