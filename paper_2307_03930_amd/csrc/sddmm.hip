@@ -143,17 +143,22 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
   const int64_t a = c_lo + (c_hi - c_lo) * part / parts;
   const int64_t e = c_lo + (c_hi - c_lo) * (part + 1) / parts;
   // B row k at this lane's columns of the chunk; vec: aligned float4 loads,
-  // else element loads (columns past N read as 0 and meet zero LDS entries)
+  // else element loads (columns past N read as 0 and meet zero LDS entries).
+  // The chunk's start is folded into the base pointer once, so the loads'
+  // addresses carry no per-load offset arithmetic.
+  const float* Bn = B + n0;
+  const int64_t n_rem = N - n0;
   auto load_b = [&](int64_t k, float4* b) {
-    const float* row = B + k * ldb;
+    const float* row = Bn + k * ldb;
 #pragma unroll
     for (int v = 0; v < VQ; ++v) {
-      const int64_t col = n0 + 4 * lane + 256 * v;
-      if (vec && col < N) {
+      const int col = 4 * lane + 256 * v;
+      if (vec && col < n_rem) {
         b[v] = *reinterpret_cast<const float4*>(row + col);
       } else {
-        b[v] = make_float4(col < N ? row[col] : 0.0f, col + 1 < N ? row[col + 1] : 0.0f,
-                           col + 2 < N ? row[col + 2] : 0.0f, col + 3 < N ? row[col + 3] : 0.0f);
+        b[v] = make_float4(col < n_rem ? row[col] : 0.0f, col + 1 < n_rem ? row[col + 1] : 0.0f,
+                           col + 2 < n_rem ? row[col + 2] : 0.0f,
+                           col + 3 < n_rem ? row[col + 3] : 0.0f);
       }
     }
   };
