@@ -315,15 +315,16 @@ def run_training(args):
                 W -= 1e-3 * W.grad
                 W.grad = None
 
+    mr = args.mr if args.mr is not None else 8
     Wd1, Wd2 = W1_0.clone().requires_grad_(True), W2_0.clone().requires_grad_(True)
-    dense_ms = _time_us(lambda: dense_step(Wd1, Wd2), 20) / 1e3
+    dense_ms = _time_us(lambda: dense_step(Wd1, Wd2), 20, warm=20) / 1e3
     rows = []
     for s in (0.75, 0.80, 0.90, 0.95):
         W1, W2 = W1_0.clone(), W2_0.clone()
         training.magnitude_prune(W1, s)
         training.magnitude_prune(W2, s)
-        chain = training.PrunedChain(W1, W2, 16)
-        step_ms = _time_us(lambda: chain.step(X, T, 1e-3), 20) / 1e3
+        chain = training.PrunedChain(W1, W2, mr)
+        step_ms = _time_us(lambda: chain.step(X, T, 1e-3), 20, warm=20) / 1e3
         pack_ms = _time_us(lambda: (chain.pw1.repack(chain.W1.detach()),
                                     chain.pw2.repack(chain.W2.detach())), 20) / 1e3
         chain.pw1.check()
@@ -332,7 +333,7 @@ def run_training(args):
                      "speedup_vs_dense": round(dense_ms / step_ms, 2)})
     print(json.dumps({"workload": "pruned training step with repacking: W1 256x2304 (3x3 conv "
                                   "256->256) on im2col 2304x3136, ReLU, W2 256x256 (1x1 conv), "
-                                  "MSE loss, SGD; mr 16; FP32",
+                                  f"MSE loss, SGD; mr {mr}; FP32",
                       "unit": "ms", "dense_fp32_step_ms": round(dense_ms, 4),
                       "data": "synthetic", "per_sparsity": rows}), flush=True)
 

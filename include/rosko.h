@@ -373,10 +373,10 @@ int32_t rosko_spmm_noalloc(const rosko_packed *A, const void *B, int32_t b_dtype
  * At may be NULL when dB is.  ws: device workspace (256-byte aligned) of
  * at least the size rosko_spmm_backward_workspace_size reports for the same
  * A (NULL when dA is not wanted), At (NULL when dB is not wanted) and N: the
- * K-split partials of dB's SpMM, and for panels of up to 16 rows the SDDMM's
+ * K-split partials of dB's SpMM, and for panels of up to 32 rows the SDDMM's
  * partial dot products over column chunks of N (1024 columns for panels of
- * up to 8 rows, 512 for up to 16; 4 * ceil(N / chunk) * A->nnz_cap bytes
- * when N exceeds one chunk), added in chunk order into dA.
+ * up to 8 rows, 512 for up to 16, 256 for up to 32; 4 * ceil(N / chunk) *
+ * A->nnz_cap bytes when N exceeds one chunk), added in chunk order into dA.
  * A smaller ws returns ROSKO_ESMALLBUF.  Asynchronous. */
 int32_t rosko_spmm_backward_workspace_size(const rosko_packed *A, const rosko_packed *At,
                                            int64_t N, size_t *bytes);

@@ -3,7 +3,7 @@
 // mask), and the result is written in A's packed order so it lines up with
 // the packed values.
 //
-// Panels of up to 16 rows (the heights the training layers use) take the
+// Panels of up to 32 rows (the heights the training layers use) take the
 // LDS kernel below, over column chunks of N.  The general kernel (any mr, N)
 // gives a workgroup one panel; its wavefronts stride over the panel's kept
 // columns.  For a column the wave keeps the selected B row in registers
@@ -87,7 +87,7 @@ __device__ __forceinline__ float wave_sum_f32(float x) {
 }
 #undef RK_DPPF
 
-// Panels of at most ROWS (8 or 16) rows, one chunk of RW = 256 * VQ <= 1024
+// Panels of at most ROWS (8, 16 or 32) rows, one chunk of RW = 256 * VQ <= 1024
 // columns of dC and B per workgroup.  The workgroup puts its panel's dC rows
 // (that column chunk) in LDS once; each of its wavefronts takes a contiguous
 // range of the panel's kept columns (the panel's columns are also split over
@@ -103,9 +103,12 @@ constexpr int kSdLdsG = 4;       // workgroups per panel
 constexpr int kSdDepth = 4;      // B rows in flight per wavefront
 constexpr int kSdChunk = 1024;   // widest column chunk (VQ = 4)
 // Column chunk of the LDS kernel by panel height: 1024 columns for panels
-// of up to 8 rows (32 KB of dC rows), 512 for up to 16 rows (also 32 KB, so
-// as many workgroups share a CU).
-inline int64_t sddmm_chunk(int32_t mr) { return mr <= 8 ? kSdChunk : kSdChunk / 2; }
+// of up to 8 rows (32 KB of dC rows), 512 for up to 16 rows and 256 for up
+// to 32 rows (also 32 KB, so as many workgroups share a CU).
+inline int64_t sddmm_chunk(int32_t mr) {
+  return mr <= 8 ? kSdChunk : (mr <= 16 ? kSdChunk / 2 : kSdChunk / 4);
+}
+constexpr int32_t kSdLdsMaxRows = 32;
 
 template <int ROWS, int VQ>
 __global__ void __launch_bounds__(64 * kSdW)
@@ -118,7 +121,7 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
             float* __restrict__ out) {
   constexpr int RW = 256 * VQ;                    // LDS row width (floats)
   constexpr int RWD = ROWS / 4;                   // dwords of row bytes per column
-  static_assert(ROWS == 8 || ROWS == 16, "panels of 8 or 16 rows");
+  static_assert(ROWS == 8 || ROWS == 16 || ROWS == 32, "panels of 8, 16 or 32 rows");
   __shared__ float4 sdc4[ROWS * RW / 4];
   float* sdc = reinterpret_cast<float*>(sdc4);
   const int64_t chunk = blockIdx.y;
@@ -196,8 +199,16 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
           for (int q = 0; q < RWD; ++q) rj[q] = __builtin_amdgcn_readlane(rw[q], j);
           for (int t = 0; t < n; ++t) {
             uint32_t word;
-            if constexpr (RWD == 2) word = t < 4 ? rj[0] : rj[1];
-            else word = t < 4 ? rj[0] : (t < 8 ? rj[1] : (t < 12 ? rj[2] : rj[3]));
+            if constexpr (RWD == 2) {
+              word = t < 4 ? rj[0] : rj[1];
+            } else if constexpr (RWD == 4) {
+              word = t < 4 ? rj[0] : (t < 8 ? rj[1] : (t < 12 ? rj[2] : rj[3]));
+            } else {
+              word = rj[0];
+#pragma unroll
+              for (int q = 1; q < RWD; ++q)
+                if ((t >> 2) == q) word = rj[q];
+            }
             const int r = (int)((word >> (8 * (t & 3))) & (uint32_t)(ROWS - 1));
             const float4* row = sdc4 + (r * RW) / 4 + lane;
             float acc = 0.0f;
@@ -236,7 +247,7 @@ k_sddmm_sum(const float* __restrict__ part, int32_t n_chunks, int64_t stride, in
 }  // namespace
 
 size_t sddmm_ws_bytes(const rosko_packed* A, int64_t N) {
-  if (A == nullptr || A->mr > 16 || N <= sddmm_chunk(A->mr)) return 0;
+  if (A == nullptr || A->mr > kSdLdsMaxRows || N <= sddmm_chunk(A->mr)) return 0;
   return sizeof(float) * (size_t)ceil_div(N, sddmm_chunk(A->mr)) * (size_t)A->nnz_cap;
 }
 
@@ -246,8 +257,8 @@ int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const
   if (A->n_panels == 0 || A->K == 0) return ROSKO_OK;
   const int64_t ncols_lim = A->ncols_cap;
   const int64_t nz_lim = std::min(A->nnz_cap, dA_cap);
-  if (A->mr <= 16) {
-    // LDS path: panels of up to 16 rows, N in chunks of up to 1024 columns
+  if (A->mr <= kSdLdsMaxRows) {
+    // LDS path: panels of up to 32 rows, N in chunks of 256 to 1024 columns
     const int64_t chunk = sddmm_chunk(A->mr);
     const int64_t n_chunks = ceil_div(std::max<int64_t>(N, 1), chunk);
     float* out = dA_val;
@@ -278,9 +289,11 @@ int32_t launch_sddmm(const rosko_packed* A, const float* dC, int64_t lddc, const
       if (nc <= 256) RK_SDL(8, 1);
       else if (nc <= 512) RK_SDL(8, 2);
       else RK_SDL(8, 4);
-    } else {
+    } else if (A->mr <= 16) {
       if (nc <= 256) RK_SDL(16, 1);
       else RK_SDL(16, 2);
+    } else {
+      RK_SDL(32, 1);
     }
 #undef RK_SDL
     ROSKO_LAUNCH_CHECK("k_sddmm_lds");

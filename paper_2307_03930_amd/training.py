@@ -41,7 +41,7 @@ def magnitude_prune(W: torch.Tensor, sparsity: float) -> None:
 class PrunedChain:
     """Weights, their packed buffers and one SGD step of the chain."""
 
-    def __init__(self, W1: torch.Tensor, W2: torch.Tensor, mr: int = 16):
+    def __init__(self, W1: torch.Tensor, W2: torch.Tensor, mr: int = 8):
         self.W1 = W1.detach().clone().requires_grad_(True)
         self.W2 = W2.detach().clone().requires_grad_(True)
         self.pw1 = PackedWeight(self.W1.detach(), mr)

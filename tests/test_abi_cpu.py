@@ -192,13 +192,14 @@ def test_backward_argument_checks():
 def test_backward_workspace_size():
     """The SDDMM's column-chunk partials: 4 * ceil(N / chunk) * nnz_cap bytes
     when N exceeds one chunk (1024 columns for panels of up to 8 rows, 512 for
-    up to 16), none otherwise or for taller panels; with At the larger of
-    that and dB's SpMM workspace."""
+    up to 16, 256 for up to 32), none otherwise or for taller panels; with At
+    the larger of that and dB's SpMM workspace."""
     lib = L.lib()
     n = C.c_size_t(0)
     for mr, N, want in [(8, 1024, 0), (8, 1025, 4 * 2 * 10), (16, 3136, 4 * 7 * 10),
                         (16, 512, 0), (12, 513, 4 * 2 * 10), (4, 5000, 4 * 5 * 10),
-                        (32, 3136, 0), (8, 0, 0)]:
+                        (32, 3136, 4 * 13 * 10), (32, 256, 0), (20, 257, 4 * 2 * 10),
+                        (64, 3136, 0), (8, 0, 0)]:
         s = _packed(64, 128, mr)
         assert lib.rosko_spmm_backward_workspace_size(C.byref(s), None, N, C.byref(n)) == 0
         assert n.value == want, (mr, N)

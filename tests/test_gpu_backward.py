@@ -31,7 +31,9 @@ def _dA_scale(pk, dC, B):
                                       # panels of 9..16 rows, and N in 1024-column chunks
                                       # (ragged last chunk; N % 4 != 0 takes element loads)
                                       (50, 200, 700, 16), (40, 300, 2500, 16),
-                                      (33, 100, 1027, 8), (20, 64, 3136, 12), (64, 96, 2049, 4)])
+                                      (33, 100, 1027, 8), (20, 64, 3136, 12), (64, 96, 2049, 4),
+                                      # panels of 17..32 rows: 256-column chunks
+                                      (70, 300, 256, 32), (45, 130, 777, 20), (96, 64, 3136, 32)])
 def test_backward_small(M, K, N, mr):
     say(f"backward {M}x{K}x{N} mr={mr}")
     A = synth.sparse_matrix(M, K, 0.1, 700 + M)
