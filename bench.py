@@ -490,6 +490,9 @@ def main():
                     help="panel height for every matrix (default: the library's analytic "
                          "plan rule picks it per matrix)")
     ap.add_argument("--graphs", default=None, help="gcn workload: comma-separated graph names")
+    ap.add_argument("--pack-mode", choices=("auto", "two_pass"), default="auto",
+                    help="packing launches: one where the grid allows (auto) or the count "
+                         "pass then the write (two_pass); the packed arrays are the same")
     ap.add_argument("--workload", choices=("cnn", "precision", "backward", "training", "gcn",
                                            "conv"),
                     default="cnn",
@@ -502,6 +505,10 @@ def main():
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
+
+    if args.pack_mode != "auto":
+        from paper_2307_03930_amd import ops
+        ops.set_pack_mode(args.pack_mode)
 
     if args.workload == "precision":
         return run_precision(args)
@@ -528,7 +535,7 @@ def main():
     B = torch.from_numpy(B_np).to(dev)
     As = [torch.from_numpy(a).to(dev) for a in As_np]
     # per matrix, set up once outside the timed region: panel height and
-    # panel height and register tile from the plan scheduler on the matrix's
+    # register tile from the plan scheduler on the matrix's
     # statistics (unless given), the parallel shape from the library; buffers sized once
     # (the sizing query synchronises; the step does not)
     packs, wss, Cs, sws, plans, mrs = [], [], [], [], [], []
@@ -683,6 +690,7 @@ def main():
                    "M": M, "K": K, "N": N,
                    "mr": args.mr if args.mr is not None else
                    f"per matrix, {sched.chooser_name()} scheduler",
+                   "pack_mode": args.pack_mode,
                    "parallelism": "single-gpu"},
         # the SpMM call (k_spmm_rows, then k_reduce_splits when K is split),
         # one launch per sparsity, timed back to back with events on the

@@ -210,6 +210,30 @@ int32_t rosko_pack_transpose_query(const float *A, int64_t M, int64_t K, int64_t
  * ROSKO_ESMALLBUF if they exceeded the capacities. */
 int32_t rosko_pack_result(const void *ws, size_t ws_bytes, rosko_packed *packed, void *stream);
 
+/* How rosko_pack and rosko_pack_transpose enqueue Alg. 1's running offsets
+ * (Sec. 4.1); a setting for the whole process, ROSKO_PACK_AUTO at load.
+ * Every mode gives the same packed arrays, bit for bit; they differ in
+ * launches and time.
+ *   ROSKO_PACK_AUTO:     one launch for grids of up to 1280 tiles of 64
+ *                        (panel, column) pairs and panels of up to 32 rows,
+ *                        when the stream is not capturing a graph: each tile
+ *                        counts its own columns, publishes its totals in the
+ *                        workspace, and adds up those of the tiles before it;
+ *                        a tile whose totals have not appeared after a few
+ *                        re-reads is counted again from A, so no wait
+ *                        depends on another workgroup having run.  Other
+ *                        grids: two launches, a count pass then the write.
+ *   ROSKO_PACK_TWO_PASS: the count pass, then the write, for every grid.
+ *   ROSKO_PACK_RECOUNT:  as AUTO, but no tile publishes, so each one counts
+ *                        every tile before it itself (time quadratic in the
+ *                        tiles: for testing that path).
+ * A pack in flight keeps the mode it was enqueued with.  EINVAL for any
+ * other value. */
+#define ROSKO_PACK_AUTO 0
+#define ROSKO_PACK_TWO_PASS 1
+#define ROSKO_PACK_RECOUNT 2
+int32_t rosko_pack_set_mode(int32_t mode);
+
 /* ---- packing from compressed sparse rows (graph matrices, Sec. 5.5) ----
  * The input is an M x K matrix in CSR form on the device: row_ptr [M+1]
  * int64 (row m's entries are [row_ptr[m], row_ptr[m+1]), within
@@ -495,7 +519,7 @@ int32_t rosko_plan_select(const float *features_host, const float *params, const
 /* ---- errors ----------------------------------------------------------- */
 const char *rosko_status_str(int32_t status);
 const char *rosko_last_error(void);   /* per host thread; "" if none */
-int32_t rosko_abi_version(void);      /* 9 */
+int32_t rosko_abi_version(void);      /* 10 */
 
 #ifdef __cplusplus
 }

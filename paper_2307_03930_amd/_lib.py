@@ -27,6 +27,9 @@ ROSKO_PATH_SPARSE = 0
 ROSKO_PATH_DENSE = 1
 ROSKO_ORDER_DEGREE = 0
 ROSKO_ORDER_BALANCED = 1
+ROSKO_PACK_AUTO = 0
+ROSKO_PACK_TWO_PASS = 1
+ROSKO_PACK_RECOUNT = 2
 ROSKO_NFEAT = 16
 ROSKO_SCHED_CANDIDATES = 7
 ROSKO_KSTEP = 128
@@ -81,6 +84,7 @@ SIGNATURES = {
     "rosko_pack_transpose": (_I32, [_P, _I64, _I64, _I64, _I32, _I32, _P, _SZ,
                                     C.POINTER(RoskoPacked), _P]),
     "rosko_pack_result": (_I32, [_P, _SZ, C.POINTER(RoskoPacked), _P]),
+    "rosko_pack_set_mode": (_I32, [_I32]),
     "rosko_pack_csr_workspace_size": (_I32, [_I64, _I64, _I64, _I32, C.POINTER(_SZ)]),
     "rosko_pack_csr_query": (_I32, [_P, _P, _P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P,
                                     C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),

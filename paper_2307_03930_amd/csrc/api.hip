@@ -99,7 +99,7 @@ static int32_t check_packed_for_read(const rosko_packed* A) {
 
 extern "C" {
 
-int32_t rosko_abi_version(void) { return 9; }
+int32_t rosko_abi_version(void) { return 10; }
 
 const char* rosko_last_error(void) { return g_err; }
 
@@ -259,6 +259,11 @@ int32_t rosko_pack_result(const void* ws, size_t ws_bytes, rosko_packed* packed,
              (long long)packed->nnz_cap, (long long)packed->ncols_cap,
              (long long)packed->nrec_cap);
   return ROSKO_OK;
+}
+
+int32_t rosko_pack_set_mode(int32_t mode) {
+  clear_error();
+  return set_pack_mode(mode);
 }
 
 // ------------------------------------------------------- CSR packing

@@ -71,7 +71,16 @@ inline int pack_rows_per_lane(int32_t mr, int cpl) {
 // Up to this many tiles the write pass adds up the tile sums before its own
 // tile itself (no separate scan launch); beyond, a one-workgroup scan runs.
 constexpr int64_t kLocalPrefixTiles = 4096;
+// Up to this many tiles (panels of up to 32 rows) the write pass counts its
+// own columns and takes its offset from the aggregates the tiles before it
+// publish: one launch, no count pass (see the single-pass notes in
+// pack.hip).  kFusedSpin: re-reads of a missing aggregate before the tile
+// counts that tile again itself.
+constexpr int64_t kFusedMaxTiles = 1280;
+constexpr int32_t kFusedSpin = 32;
 PackWs pack_ws_layout(int64_t R, int64_t S, int32_t mr, bool transpose);
+// rosko_pack_set_mode
+int32_t set_pack_mode(int32_t mode);
 
 // Enqueue count + tile scan (everything rosko_pack_query needs).
 int32_t launch_pack_count_scan(const float* A, int64_t R, int64_t S, int64_t lda, int32_t mr,

@@ -13,6 +13,9 @@
 // (and the prefix of "count > 0" the column slot) that Alg. 1's running
 // indices reach there.  All arithmetic on offsets is integer, hence the
 // packed arrays are bit-identical to a sequential run of Alg. 1.
+#include <atomic>
+#include <chrono>
+
 #include "encode.h"
 #include "internal.h"
 
@@ -436,6 +439,162 @@ k_pack_write(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
 constexpr int kLdsMaxRows = 64;
 constexpr int64_t kImageMaxTiles = 1024;   // about 4 tiles per CU
 
+// Where a write tile's running offsets start: the scan pass (kPfxScan), the
+// sums of the tiles before it from the count pass, added up by the tile
+// itself (kPfxLocal), or, with no count pass at all, the aggregates that the
+// tiles before it publish as they go (kPfxFused, below).
+constexpr int kPfxScan = 0, kPfxLocal = 1, kPfxFused = 2;
+
+// ------------------------------------------------- single-pass prefix
+// A tile counts its own columns from the rows it loads for staging, so the
+// count pass is not needed; what it still needs is the sum over the tiles
+// before it.  Each tile publishes its aggregate (values, kept columns,
+// records) as one 64-bit word: the launch's tag in the high half, a marker
+// bit and the three counts in the low half (at most 2048 / 256 / 256 in a
+// tile of 64 columns per lane-pair, so 13 + 9 + 9 bits).  A word counts only
+// if it carries this launch's tag and the marker, so words left by earlier
+// launches are never taken.  Then each tile reads the words of all tiles
+// before it; one that is not there yet is re-read a few times and, if still
+// missing, counted again from A by the whole wavefront, exactly as its own
+// tile would.  So the result never depends on another workgroup having run
+// (no wait can hang), and every offset is the same exact integer sum as in
+// the two-pass forms.
+constexpr int kLbPerLane = 16;   // words in flight per lane: 1024 tiles a round
+
+__device__ __forceinline__ uint64_t agg_word(uint32_t tag, Tri32 s) {
+  return ((uint64_t)tag << 32) | (uint64_t(1) << 31) | (uint64_t)(uint32_t)s.a |
+         ((uint64_t)(uint32_t)s.b << 13) | ((uint64_t)(uint32_t)s.c << 22);
+}
+__device__ __forceinline__ bool agg_ready(uint64_t w, uint32_t tag) {
+  return (uint32_t)(w >> 32) == tag && ((w >> 31) & 1u);
+}
+
+// (values, kept columns, records) of tile `tile`, counted from A the way the
+// tile itself counts them; the same in every lane.  Called by the whole
+// wavefront.
+template <int CPL, int RT>
+__device__ __forceinline__ Tri32 tile_aggregate(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
+                                int32_t mr, int64_t total, int64_t tile) {
+  constexpr int RMAX = RT < 32 ? RT : 32;   // RT <= 32: one load round holds the panel
+  const int lane = threadIdx.x & 63;
+  Tri32 sum{0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const int64_t f = tile * (64 * CPL) + 64 * j + lane;
+    int c = 0;
+    if (f < total) {
+      const int64_t p = f / S, k = f - p * S, r0 = p * mr;
+      const int rows = (int)((R - r0) < mr ? (R - r0) : mr);
+      const float* col = A + r0 * lda + k;
+      float x[RMAX];
+#pragma unroll
+      for (int i = 0; i < RMAX; ++i) x[i] = col[(int64_t)(i < rows ? i : rows - 1) * lda];
+#pragma unroll
+      for (int i = 0; i < RMAX; ++i) c += (i < rows) & kept(x[i]);
+    }
+    Tri32 t;
+    (void)wave_excl_scan3(c, &t);
+    sum.a += t.a;
+    sum.b += t.b;
+    sum.c += t.c;
+  }
+  return sum;
+}
+
+// lb_issue: the words of tiles base + 64 u + lane, u < kLbPerLane, loaded
+// from addresses clamped to the tiles before t (t > 0; words past t are
+// ignored by the caller).
+__device__ __forceinline__ void lb_issue(const uint64_t* flags, int64_t t, int64_t base,
+                                         uint64_t* w) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int u = 0; u < kLbPerLane; ++u) {
+    const int64_t i = base + 64 * u + lane;
+    w[u] = __hip_atomic_load(flags + (i < t ? i : t - 1), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// lookback_sum: the sum of the aggregates of tiles [0, t), read in rounds
+// of kLbPerLane words per lane.  Lane l takes tiles l, l + 64, ...;
+// the words still missing are re-read together (one round trip per
+// re-read, a short sleep between) up to `spin` times.  A round with every
+// word present is added up as it is; otherwise the round is done again on
+// the slow path (kept out of the unrolled code, so the kernel stays small):
+// its words loaded once more and each one still missing counted from A, one
+// tile at a time by the whole wavefront.  A word and a count of the same
+// tile are the same integers, so either gives the exact sum.
+template <int CPL, int RT>
+__device__ __forceinline__ Tri lookback_sum(const uint64_t* flags, int64_t t, uint32_t tag,
+                                            int32_t spin, const float* __restrict__ A,
+                                            int64_t R, int64_t S, int64_t lda, int32_t mr,
+                                            int64_t total) {
+  const int lane = threadIdx.x & 63;
+  Tri acc{0, 0, 0};
+  for (int64_t base = 0; base < t; base += 64 * kLbPerLane) {
+    uint64_t w[kLbPerLane];
+    lb_issue(flags, t, base, w);
+    bool miss[kLbPerLane];
+#pragma unroll
+    for (int u = 0; u < kLbPerLane; ++u)
+      miss[u] = base + 64 * u + lane < t && !agg_ready(w[u], tag);
+    bool any = false;
+    for (int r = 0; r < spin; ++r) {
+      any = false;
+#pragma unroll
+      for (int u = 0; u < kLbPerLane; ++u) any |= miss[u];
+      if (!__any(any)) break;
+      __builtin_amdgcn_s_sleep(2);
+      uint64_t nw[kLbPerLane];
+      lb_issue(flags, t, base, nw);
+#pragma unroll
+      for (int u = 0; u < kLbPerLane; ++u) {
+        if (miss[u]) w[u] = nw[u];
+        miss[u] = miss[u] && !agg_ready(nw[u], tag);
+      }
+    }
+    any = false;
+#pragma unroll
+    for (int u = 0; u < kLbPerLane; ++u) any |= miss[u];
+    if (!__any(any)) {
+#pragma unroll
+      for (int u = 0; u < kLbPerLane; ++u) {
+        if (base + 64 * u + lane < t) {
+          acc.a += (int64_t)(w[u] & 0x1FFFu);
+          acc.b += (int64_t)((w[u] >> 13) & 0x1FFu);
+          acc.c += (int64_t)((w[u] >> 22) & 0x1FFu);
+        }
+      }
+    } else {
+#pragma unroll 1
+      for (int u = 0; u < kLbPerLane; ++u) {
+        const int64_t i = base + 64 * u + lane;
+        uint64_t x = __hip_atomic_load(flags + (i < t ? i : t - 1), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t m = __ballot(i < t && !agg_ready(x, tag));
+        while (m) {                      // wave-uniform
+          const int l = __builtin_ctzll(m);
+          m &= m - 1;
+          const Tri32 sg = tile_aggregate<CPL, RT>(A, R, S, lda, mr, total, base + 64 * u + l);
+          if (lane == l) x = agg_word(tag, sg);
+        }
+        if (i < t) {
+          acc.a += (int64_t)(x & 0x1FFFu);
+          acc.b += (int64_t)((x >> 13) & 0x1FFu);
+          acc.c += (int64_t)((x >> 22) & 0x1FFu);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    acc.a += __shfl_xor(acc.a, d, 64);
+    acc.b += __shfl_xor(acc.b, d, 64);
+    acc.c += __shfl_xor(acc.c, d, 64);
+  }
+  return acc;
+}
+
 template <int DT>
 __device__ __forceinline__ uint32_t value_code(float x, const float* __restrict__ row_scale,
                                                int64_t row) {
@@ -450,11 +609,12 @@ __device__ __forceinline__ uint32_t code_bits(uint32_t code) {
   return dec_fp8((uint8_t)code);
 }
 
-template <int DT, bool LOCAL, int CPL, int RT, bool TABLE>
+template <int DT, int PFX, int CPL, int RT, bool TABLE>
 __global__ void __launch_bounds__(kPackThreads)
 k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr,
                  int64_t P, const int32_t* __restrict__ counts,
                  const int64_t* __restrict__ tile_offs, const int64_t* __restrict__ tile_sums,
+                 uint64_t* flags, uint32_t tag, int32_t spin, int32_t publish,
                  int64_t* __restrict__ totals, int64_t nnz_cap, int64_t ncols_cap,
                  int64_t* __restrict__ panel_nz_ptr, int64_t* __restrict__ panel_col_ptr,
                  int32_t* __restrict__ col_ind, int32_t* __restrict__ col_nnz,
@@ -465,6 +625,7 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   static_assert((CPL == 4 && RT == 8) || (CPL == 2 && RT == 16) ||
                     (CPL == 1 && (RT == 8 || RT == 16 || RT == 32 || RT == kLdsMaxRows)),
                 "panel height bound of the instantiation");
+  static_assert(PFX != kPfxFused || RT <= 32, "single pass: the whole column in one load round");
   // rows held per column: RT in one load round (RT <= 16, or RT = 32 / CPL),
   // else 32 in batches (one pair per lane, mr up to RT); records per column
   // at most ceil(RT / 12)
@@ -507,7 +668,7 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   for (int j = 0; j < CPL; ++j) {
     const int64_t f = fb + 64 * j;
     valid[j] = f < total;
-    c[j] = valid[j] ? counts[f] : 0;
+    if constexpr (PFX != kPfxFused) c[j] = valid[j] ? counts[f] : 0;
     p[j] = valid[j] ? f / S : 0;
     k[j] = valid[j] ? f - p[j] * S : 0;
     r0[j] = p[j] * mr;
@@ -525,8 +686,38 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
       for (int i = 0; i < RMAX; ++i) xs[j * RMAX + i] = col[(int64_t)(i < last ? i : last) * lda];
     }
   }
+  if constexpr (PFX == kPfxFused) {
+    // the tile's own counts, from the rows just loaded (all of the panel:
+    // RT <= 32 rows in one round)
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      int cnt = 0;
+#pragma unroll
+      for (int i = 0; i < RMAX; ++i) cnt += (i < rows[j]) & kept(xs[j * RMAX + i]);
+      c[j] = cnt;
+    }
+  }
+  // exclusive prefix in flattened order: the columns of j = 0 (lanes in
+  // order), then j = 1, ...
+  Tri32 e[CPL], run{0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    Tri32 t;
+    const Tri32 x = wave_excl_scan3(c[j], &t);
+    e[j] = Tri32{run.a + x.a, run.b + x.b, run.c + x.c};
+    run.a += t.a;
+    run.b += t.b;
+    run.c += t.c;
+  }
   Tri carry{0, 0, 0};
-  if constexpr (LOCAL) {
+  // single pass: publish this tile's aggregate now; those of the tiles
+  // before it are read after the staging below, which needs no offsets (by
+  // then most of them are there)
+  if constexpr (PFX == kPfxFused) {
+    if (publish && lane == 0)
+      __hip_atomic_store(flags + blockIdx.x, agg_word(tag, run), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  } else if constexpr (PFX == kPfxLocal) {
     const int64_t nb = blockIdx.x;
     for (int64_t i = lane; i < nb; i += 64 * 8) {
       int64_t va[8], vb[8], vc[8];
@@ -551,18 +742,6 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   } else {
     carry = Tri{tile_offs[3 * blockIdx.x], tile_offs[3 * blockIdx.x + 1],
                 tile_offs[3 * blockIdx.x + 2]};
-  }
-  // exclusive prefix in flattened order: the columns of j = 0 (lanes in
-  // order), then j = 1, ...
-  Tri32 e[CPL], run{0, 0, 0};
-#pragma unroll
-  for (int j = 0; j < CPL; ++j) {
-    Tri32 t;
-    const Tri32 x = wave_excl_scan3(c[j], &t);
-    e[j] = Tri32{run.a + x.a, run.b + x.b, run.c + x.c};
-    run.a += t.a;
-    run.b += t.b;
-    run.c += t.c;
   }
   const int nv = min(run.a, kLdsVals), nrec = min(run.c, kLdsRecs);
   // zero the tile's records (unused row bytes and value slots stay zero)
@@ -630,6 +809,8 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
       s_code[t] = value_code<DT>(__uint_as_float(s_code[t]), row_scale, s_grow[t]);
     __syncthreads();
   }
+  if constexpr (PFX == kPfxFused)
+    carry = lookback_sum<CPL, RT>(flags, blockIdx.x, tag, spin, A, R, S, lda, mr, total);
   // coalesced copies of the tile's values, rows and records
   const int64_t z0 = carry.a, q0 = carry.c;
 #pragma unroll 4
@@ -686,7 +867,7 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
       col_ptr[col_slot] = nz_off;
     }
   }
-  if constexpr (LOCAL) {
+  if constexpr (PFX != kPfxScan) {
     if (blockIdx.x == gridDim.x - 1 && lane == 0) {
       carry.a += run.a;
       carry.b += run.b;
@@ -828,6 +1009,31 @@ int32_t launch_pack_count_scan(const float* A, int64_t R, int64_t S, int64_t lda
   return ROSKO_OK;
 }
 
+// Tag of a single-pass launch: distinct for every launch of the process (the
+// first one drawn from the clock), so a word an earlier launch left in the
+// workspace never carries the tag of a later one.
+static std::atomic<uint32_t> g_pack_tag{0};
+static std::atomic<int32_t> g_pack_mode{ROSKO_PACK_AUTO};
+
+static uint32_t next_pack_tag() {
+  uint32_t t = g_pack_tag.load(std::memory_order_relaxed);
+  if (t == 0) {
+    const uint32_t seed =
+        (uint32_t)std::chrono::steady_clock::now().time_since_epoch().count() | 1u;
+    g_pack_tag.compare_exchange_strong(t, seed, std::memory_order_relaxed);
+  }
+  return g_pack_tag.fetch_add(1, std::memory_order_relaxed);
+}
+
+int32_t set_pack_mode(int32_t mode) {
+  if (mode != ROSKO_PACK_AUTO && mode != ROSKO_PACK_TWO_PASS && mode != ROSKO_PACK_RECOUNT) {
+    set_error("unknown packing mode %d", mode);
+    return ROSKO_EINVAL;
+  }
+  g_pack_mode.store(mode, std::memory_order_relaxed);
+  return ROSKO_OK;
+}
+
 int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t mr,
                     int32_t val_dtype, void* ws, const PackWs& L, const rosko_packed* out,
                     hipStream_t s) {
@@ -836,15 +1042,8 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
   int64_t* tsum = reinterpret_cast<int64_t*>(w + L.tile_sums);
   int64_t* toff = reinterpret_cast<int64_t*>(w + L.tile_offs);
   int64_t* totals = reinterpret_cast<int64_t*>(w + L.totals);
-  const bool local = L.NT > 0 && L.NT <= kLocalPrefixTiles;
-  int32_t st;
-  if (local) {
-    launch_count(A, R, S, lda, mr, L, counts, tsum, s);
-    ROSKO_LAUNCH_CHECK("k_pack_count");
-  } else if ((st = launch_pack_count_scan(A, R, S, lda, mr, ws, L, out, s))) {
-    return st;
-  }
-  if (L.NT == 0) return ROSKO_OK;
+  // the aggregate words of the single pass live where the tile sums would
+  uint64_t* flags = reinterpret_cast<uint64_t*>(w + L.tile_sums);
   const bool lds = mr <= kLdsMaxRows;
   // mr > kLdsMaxRows only with one pair per lane (pack_cols_per_lane)
   // the LDS instantiation whose panel-height bound RT covers mr: 8 with 4
@@ -858,40 +1057,98 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
     set_error("internal: panel height %d above the packing tile's %d rows", mr, rt);
     return ROSKO_EINTERNAL;
   }
+  // Single pass (no count launch) for grids of up to kFusedMaxTiles tiles of
+  // panels of up to 32 rows, unless the stream is being captured into a
+  // graph: a replay would reuse the launch's tag, so captured packs take the
+  // two-pass form.
+  const int32_t mode = g_pack_mode.load(std::memory_order_relaxed);
+  bool fused = false;
+  if (mode != ROSKO_PACK_TWO_PASS && L.NT > 0 && L.NT <= kFusedMaxTiles && lds && rt <= 32) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    ROSKO_HIP_CHECK(hipStreamIsCapturing(s, &cap));
+    fused = cap == hipStreamCaptureStatusNone;
+  }
+  const bool local = !fused && L.NT > 0 && L.NT <= kLocalPrefixTiles;
+  int32_t st;
+  if (fused) {
+    // nothing before the write pass
+  } else if (local) {
+    launch_count(A, R, S, lda, mr, L, counts, tsum, s);
+    ROSKO_LAUNCH_CHECK("k_pack_count");
+  } else if ((st = launch_pack_count_scan(A, R, S, lda, mr, ws, L, out, s))) {
+    return st;
+  }
+  if (L.NT == 0) return ROSKO_OK;
+  if (!lds) {
+#define ROSKO_WRITE_G(DT_, LOC)                                                                \
+  hipLaunchKernelGGL((k_pack_write<DT_, LOC>), dim3((unsigned)L.NT), dim3(kPackThreads), 0, s, \
+                     A, R, S, lda, mr, L.P, counts, toff, tsum, totals, out->nnz_cap,          \
+                     out->ncols_cap, out->panel_nz_ptr, out->panel_col_ptr, out->col_ind,      \
+                     out->col_nnz, out->col_ptr, out->loc, out->val, out->row_scale,           \
+                     out->kblk_ptr, out->nrec_cap, out->rec)
+    if (local) {
+      if (val_dtype == ROSKO_F32) ROSKO_WRITE_G(ROSKO_F32, true);
+      else if (val_dtype == ROSKO_BF16) ROSKO_WRITE_G(ROSKO_BF16, true);
+      else ROSKO_WRITE_G(ROSKO_FP8_E4M3, true);
+    } else {
+      if (val_dtype == ROSKO_F32) ROSKO_WRITE_G(ROSKO_F32, false);
+      else if (val_dtype == ROSKO_BF16) ROSKO_WRITE_G(ROSKO_BF16, false);
+      else ROSKO_WRITE_G(ROSKO_FP8_E4M3, false);
+    }
+#undef ROSKO_WRITE_G
+    ROSKO_LAUNCH_CHECK("k_pack_write");
+    return ROSKO_OK;
+  }
+  const uint32_t tag = fused ? next_pack_tag() : 0u;
+  // the test mode publishes nothing, so every tile recounts every tile
+  // before it; re-reads of a missing word before recounting it
+  const int32_t publish = mode == ROSKO_PACK_RECOUNT ? 0 : 1;
+  const int32_t spin = publish ? kFusedSpin : 1;
   // record images staged whole for grids of up to kImageMaxTiles tiles (a
   // few per CU: each tile's own chain is the time), as a table above (the
   // smaller LDS footprint lets more workgroups share a CU)
   const bool table = L.NT > kImageMaxTiles;
-#define ROSKO_KWRITE_T(DT, LOC, TB)                                                            \
-  (!lds ? (k_pack_write<DT, LOC>)                                                             \
-        : L.cpl == 4 ? (k_pack_write_lds<DT, LOC, 4, 8, TB>)                                  \
-        : L.cpl == 2 ? (k_pack_write_lds<DT, LOC, 2, 16, TB>)                                 \
-        : rt == 8 ? (k_pack_write_lds<DT, LOC, 1, 8, TB>)                                     \
-        : rt == 16 ? (k_pack_write_lds<DT, LOC, 1, 16, TB>)                                   \
-        : rt == 32 ? (k_pack_write_lds<DT, LOC, 1, 32, TB>)                                   \
-                   : (k_pack_write_lds<DT, LOC, 1, kLdsMaxRows, TB>))
-#define ROSKO_KWRITE(DT, LOC) (table ? ROSKO_KWRITE_T(DT, LOC, true) : ROSKO_KWRITE_T(DT, LOC, false))
-#define ROSKO_KWRITE_FP8(LOC) ROSKO_KWRITE_T(ROSKO_FP8_E4M3, LOC, true)
+#define ROSKO_KWRITE_T(DT, PF, TB)                                                             \
+  (L.cpl == 4    ? (k_pack_write_lds<DT, PF, 4, 8, TB>)                                       \
+   : L.cpl == 2  ? (k_pack_write_lds<DT, PF, 2, 16, TB>)                                      \
+   : rt == 8     ? (k_pack_write_lds<DT, PF, 1, 8, TB>)                                       \
+   : rt == 16    ? (k_pack_write_lds<DT, PF, 1, 16, TB>)                                      \
+                 : (k_pack_write_lds<DT, PF, 1, 32, TB>))
+#define ROSKO_KWRITE_T64(DT, PF, TB)                                                           \
+  (rt == kLdsMaxRows ? (k_pack_write_lds<DT, PF, 1, kLdsMaxRows, TB>) : ROSKO_KWRITE_T(DT, PF, TB))
+#define ROSKO_KWRITE(DT, PF)                                                                   \
+  (table ? ROSKO_KWRITE_T64(DT, PF, true) : ROSKO_KWRITE_T64(DT, PF, false))
+#define ROSKO_KWRITE_FP8(PF) ROSKO_KWRITE_T64(ROSKO_FP8_E4M3, PF, true)
 #define ROSKO_WRITE(KERNEL)                                                                    \
   hipLaunchKernelGGL(KERNEL,                                                                  \
                      dim3((unsigned)L.NT), dim3(kPackThreads), 0, s,                         \
-                     A, R, S, lda, mr, L.P, counts, toff, tsum, totals, out->nnz_cap,         \
+                     A, R, S, lda, mr, L.P, counts, toff, tsum, flags, tag, spin, publish,    \
+                     totals, out->nnz_cap,                                                     \
                      out->ncols_cap, out->panel_nz_ptr, out->panel_col_ptr, out->col_ind,     \
                      out->col_nnz, out->col_ptr, out->loc, out->val, out->row_scale,          \
                      out->kblk_ptr, out->nrec_cap, out->rec)
-  if (local) {
-    if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_F32, true));
-    else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_BF16, true));
-    else ROSKO_WRITE(ROSKO_KWRITE_FP8(true));
+  if (fused) {
+    // RT <= 32 here; the single-pass instantiations have no 64-row form
+#define ROSKO_KWRITE_F(DT)                                                                     \
+  (table ? ROSKO_KWRITE_T(DT, kPfxFused, true) : ROSKO_KWRITE_T(DT, kPfxFused, false))
+    if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_KWRITE_F(ROSKO_F32));
+    else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_KWRITE_F(ROSKO_BF16));
+    else ROSKO_WRITE(ROSKO_KWRITE_T(ROSKO_FP8_E4M3, kPfxFused, true));
+#undef ROSKO_KWRITE_F
+  } else if (local) {
+    if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_F32, kPfxLocal));
+    else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_BF16, kPfxLocal));
+    else ROSKO_WRITE(ROSKO_KWRITE_FP8(kPfxLocal));
   } else {
-    if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_F32, false));
-    else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_BF16, false));
-    else ROSKO_WRITE(ROSKO_KWRITE_FP8(false));
+    if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_F32, kPfxScan));
+    else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_BF16, kPfxScan));
+    else ROSKO_WRITE(ROSKO_KWRITE_FP8(kPfxScan));
   }
 #undef ROSKO_WRITE
 #undef ROSKO_KWRITE
 #undef ROSKO_KWRITE_FP8
 #undef ROSKO_KWRITE_T
+#undef ROSKO_KWRITE_T64
   ROSKO_LAUNCH_CHECK("k_pack_write");
   return ROSKO_OK;
 }

@@ -255,6 +255,18 @@ def spmm_backward(P: PackedMatrix, Pt: PackedMatrix | None, B: torch.Tensor, dC:
     return (dA[: P.nnz] if dA is not None else None), dB
 
 
+PACK_MODES = {"auto": L.ROSKO_PACK_AUTO, "two_pass": L.ROSKO_PACK_TWO_PASS,
+              "recount": L.ROSKO_PACK_RECOUNT}
+
+
+def set_pack_mode(mode: str) -> None:
+    """Process-wide: how packing enqueues its running offsets (rosko_pack_set_mode):
+    "auto" (one launch where the grid allows), "two_pass" (count, then write)
+    or "recount" (one launch, every tile counting the tiles before it; for
+    tests).  The packed arrays are the same in every mode."""
+    L.check(L.lib().rosko_pack_set_mode(PACK_MODES[mode]))
+
+
 def pack_into(A: torch.Tensor, P: PackedMatrix, ws: torch.Tensor) -> PackedMatrix:
     """Re-packs A into P's existing buffers (same shape, mr and dtype; the
     capacities must hold A's structure).  Asynchronous: no host sync."""

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.rosko_abi_version() == 9
+    assert lib.rosko_abi_version() == 10
     assert lib.rosko_status_str(L.ROSKO_EINVAL) == b"ROSKO_EINVAL"
     assert lib.rosko_status_str(123) == b"ROSKO_UNKNOWN"
 
@@ -70,6 +70,18 @@ def test_workspace_size_closed_form():
     assert n.value == r(4 * P16 * 4096) + 2 * r(24 * NT16) + r(32)
     assert lib.rosko_pack_workspace_size(256, 2304, 32, 1, C.byref(n)) == 0
     assert n.value == r(4 * P2 * 256) + 2 * r(24 * NT2) + r(32) + r(4 * 256 * 2304)
+
+
+def test_pack_mode_setting():
+    """rosko_pack_set_mode takes the three modes and refuses anything else
+    (host only: no GPU call)."""
+    lib = L.lib()
+    for mode in (L.ROSKO_PACK_TWO_PASS, L.ROSKO_PACK_RECOUNT, L.ROSKO_PACK_AUTO):
+        assert lib.rosko_pack_set_mode(mode) == L.ROSKO_OK
+    for bad in (-1, 3, 100):
+        assert lib.rosko_pack_set_mode(bad) == L.ROSKO_EINVAL
+        assert b"mode" in lib.rosko_last_error()
+    assert lib.rosko_pack_set_mode(L.ROSKO_PACK_AUTO) == L.ROSKO_OK
 
 
 @pytest.mark.parametrize("mr", [0, -1, 257])
