@@ -11,8 +11,8 @@
 //   count   -- kept entries per packed row (one wavefront per row), input
 //              checks (permutation, row pointers, column range),
 //   scan    -- row offsets of the kept entries (panels are contiguous runs),
-//   gather  -- per kept entry the key (its column) and the value (source
-//              entry index, packed row), compacted in packed order,
+//   gather  -- per kept entry the key (its column) and the value (its FP32
+//              bits and packed row), compacted in packed order,
 //   sort    -- segmented stable radix sort by column, one segment per panel
 //              (rocPRIM),
 //   heads   -- entries whose column differs from the previous one, or that
@@ -37,6 +37,7 @@ namespace {
 
 constexpr int kT = 256;           // threads per workgroup of the element-wise passes
 constexpr int kRowsPerWg = 4;     // one wavefront per row in the row passes
+constexpr int kRowChunks = 4;     // 64-entry chunks of a row loaded together
 
 // bits of the "bad input" word (totals[kTotBad])
 constexpr uint64_t kBadPerm = 1, kBadPermDup = 2, kBadRowPtr = 4, kBadCol = 8,
@@ -94,15 +95,25 @@ k_csr_count(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col
     if (b < 0 || e < b || e > nz_in) {
       bad |= kBadRowPtr;
     } else {
-      for (int64_t j0 = b; j0 < e; j0 += 64) {
-        const int64_t j = j0 + lane;
-        int keep = 0;
-        if (j < e) {
-          const int32_t c = col_idx[j];
-          if (c < 0 || c >= K) bad |= kBadCol;
-          else keep = kept(val[j]);
+      // kRowChunks chunks of 64 entries per pass, their loads issued
+      // together from addresses clamped into the row (a hub row of
+      // thousands of entries then takes a quarter of the round trips)
+      for (int64_t j0 = b; j0 < e; j0 += 64 * kRowChunks) {
+        int32_t cc[kRowChunks];
+        float xx[kRowChunks];
+#pragma unroll
+        for (int u = 0; u < kRowChunks; ++u) {
+          const int64_t j = std::min<int64_t>(j0 + 64 * u + lane, e - 1);
+          cc[u] = col_idx[j];
+          xx[u] = val[j];
         }
-        cnt += __popcll(__ballot(keep));
+#pragma unroll
+        for (int u = 0; u < kRowChunks; ++u) {
+          const bool in = j0 + 64 * u + lane < e;
+          const bool col_ok = cc[u] >= 0 && cc[u] < K;
+          if (in && !col_ok) bad |= kBadCol;
+          cnt += __popcll(__ballot(in && col_ok && kept(xx[u])));
+        }
       }
     }
   }
@@ -111,7 +122,9 @@ k_csr_count(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col
 }
 
 // One wavefront per packed row: its kept entries at rowoff[i] onwards, in
-// CSR order: key = column, value = (source entry << 32) | packed row.
+// CSR order: key = column, value = (the entry's FP32 bits << 32) | packed row
+// (the value travels with the sort, so no later pass gathers it from the
+// CSR arrays).
 __global__ void __launch_bounds__(kT)
 k_csr_gather(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
              const float* __restrict__ val, const int32_t* __restrict__ perm, int64_t M,
@@ -127,21 +140,26 @@ k_csr_gather(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ co
   if (b < 0 || e < b || e > nz_in) return;
   int64_t pos = rowoff[i];
   const int64_t end = rowoff[i + 1];
-  for (int64_t j0 = b; j0 < e; j0 += 64) {
-    const int64_t j = j0 + lane;
-    int keep = 0;
-    int32_t c = 0;
-    if (j < e) {
-      c = col_idx[j];
-      keep = (c >= 0 && c < K) ? kept(val[j]) : 0;
+  for (int64_t j0 = b; j0 < e; j0 += 64 * kRowChunks) {
+    int32_t cc[kRowChunks];
+    float xx[kRowChunks];
+#pragma unroll
+    for (int u = 0; u < kRowChunks; ++u) {
+      const int64_t j = std::min<int64_t>(j0 + 64 * u + lane, e - 1);
+      cc[u] = col_idx[j];
+      xx[u] = val[j];
     }
-    const uint64_t mask = __ballot(keep);
-    const int64_t at = pos + lanes_below(mask);
-    if (keep && at < end) {
-      keys[at] = (uint32_t)c;
-      vals[at] = ((uint64_t)j << 32) | (uint64_t)i;
+#pragma unroll
+    for (int u = 0; u < kRowChunks; ++u) {
+      const bool keep = j0 + 64 * u + lane < e && cc[u] >= 0 && cc[u] < K && kept(xx[u]);
+      const uint64_t mask = __ballot(keep);
+      const int64_t at = pos + lanes_below(mask);
+      if (keep && at < end) {
+        keys[at] = (uint32_t)cc[u];
+        vals[at] = ((uint64_t)__float_as_uint(xx[u]) << 32) | (uint64_t)i;
+      }
+      pos += __popcll(mask);
     }
-    pos += __popcll(mask);
   }
 }
 
@@ -181,7 +199,7 @@ __global__ void __launch_bounds__(kT)
 k_csr_entries(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ vals,
               const int32_t* __restrict__ hd, const int32_t* __restrict__ cid,
               const int64_t* __restrict__ rowoff, int64_t M, int64_t nz, int32_t mr,
-              const float* __restrict__ src_val, int32_t* __restrict__ colstart,
+              int32_t* __restrict__ colstart,
               int32_t* __restrict__ colk, int64_t* __restrict__ totals, int32_t* col_ind,
               int64_t* col_ptr, uint8_t* loc, void* val, const float* row_scale,
               int64_t nnz_cap, int64_t ncols_cap) {
@@ -206,8 +224,9 @@ k_csr_entries(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ va
     if (z == E - 1 && c + 1 <= ncols_cap) col_ptr[c + 1] = E;
     if (z < nnz_cap) {
       loc[z] = (uint8_t)(row % mr);
-      const float x = src_val[v >> 32];
-      if (DT == ROSKO_F32) reinterpret_cast<float*>(val)[z] = x;
+      const uint32_t xb = (uint32_t)(v >> 32);
+      const float x = __uint_as_float(xb);
+      if (DT == ROSKO_F32) reinterpret_cast<uint32_t*>(val)[z] = xb;
       else if (DT == ROSKO_BF16) reinterpret_cast<uint16_t*>(val)[z] = enc_bf16(x);
       else reinterpret_cast<uint8_t*>(val)[z] = enc_fp8(__fdiv_rn(x, row_scale[row]));
     }
@@ -235,24 +254,32 @@ k_csr_colcnt(const int32_t* __restrict__ colstart, const int32_t* __restrict__ c
 }
 
 // Per kept column: its records (header, row bytes, FP32 values of the stored
-// codes, unused slots zero) from rptr[c].
+// codes, unused slots zero) from rptr[c], one lane per column.  The values
+// come with the sorted entries, so each column's chain is its offsets, its
+// entries and the stores.  (Four lanes per column, each storing one 16-byte
+// part so that a wavefront's stores are contiguous, measured slower: a
+// wavefront then covers 16 columns instead of 64 and the grid runs four
+// times the dependent-load chains.)
 template <int DT>
 __global__ void __launch_bounds__(kT)
 k_csr_records(const int32_t* __restrict__ colstart, const int32_t* __restrict__ colk,
               const int32_t* __restrict__ cid, const int64_t* __restrict__ rptr,
               const uint64_t* __restrict__ vals, const int64_t* __restrict__ rowoff, int64_t M,
-              int64_t nz, int32_t mr, const float* __restrict__ src_val,
-              const float* __restrict__ row_scale, uint32_t* __restrict__ rec,
-              int64_t nrec_cap) {
+              int64_t nz, int32_t mr, const float* __restrict__ row_scale,
+              uint32_t* __restrict__ rec, int64_t nrec_cap) {
   const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (c >= nz) return;
+  // the column's own words are loaded together with the entry total (the
+  // arrays hold nz entries, so every index here is in range); only the
+  // entries wait for the column count
   const int64_t E = rowoff[M];
-  const int64_t ncols = csr_ncols(cid, E);
-  if (c >= ncols) return;
   const int64_t z0 = colstart[c];
-  const int64_t cnt = ((c + 1 < ncols) ? (int64_t)colstart[c + 1] : E) - z0;
+  const int64_t z1 = colstart[std::min<int64_t>(c + 1, nz - 1)];
   const uint32_t k = (uint32_t)colk[c];
   int64_t r = rptr[c];
+  const int64_t ncols = csr_ncols(cid, E);
+  if (c >= ncols) return;
+  const int64_t cnt = ((c + 1 < ncols) ? z1 : E) - z0;
   for (int64_t q = 0; q < cnt; q += kRecVals, ++r) {
     const int n = (int)std::min<int64_t>(kRecVals, cnt - q);
     uint32_t w[16];
@@ -263,12 +290,12 @@ k_csr_records(const int32_t* __restrict__ colstart, const int32_t* __restrict__ 
       uint32_t bits = 0u;
       if (u < n) {
         const uint64_t v = vals[z0 + q + u];
-        const int64_t row = (int64_t)(uint32_t)v;
-        w[1 + u / 4] |= (uint32_t)(row % mr) << (8 * (u % 4));
-        const float x = src_val[v >> 32];
-        if (DT == ROSKO_F32) bits = __float_as_uint(x);
-        else if (DT == ROSKO_BF16) bits = dec_bf16(enc_bf16(x));
-        else bits = dec_fp8(enc_fp8(__fdiv_rn(x, row_scale[row])));
+        const uint32_t row = (uint32_t)v;
+        w[1 + u / 4] |= (row % (uint32_t)mr) << (8 * (u % 4));
+        const uint32_t xb = (uint32_t)(v >> 32);
+        if (DT == ROSKO_F32) bits = xb;
+        else if (DT == ROSKO_BF16) bits = dec_bf16(enc_bf16(__uint_as_float(xb)));
+        else bits = dec_fp8(enc_fp8(__fdiv_rn(__uint_as_float(xb), row_scale[row])));
       }
       w[4 + u] = bits;
     }
@@ -555,7 +582,7 @@ int32_t launch_pack_csr(const int64_t* row_ptr, const int32_t* col_idx, const fl
     }
 #define RK_ENT(DT_, W_)                                                                      \
   hipLaunchKernelGGL((k_csr_entries<DT_, W_>), dim3(g_nz), dim3(kT), 0, s, kout, vout, hd,   \
-                     cid, rowoff, M, nz_in, mr, val, colstart, colk, totals,                 \
+                     cid, rowoff, M, nz_in, mr, colstart, colk, totals,                      \
                      write ? out->col_ind : nullptr, write ? out->col_ptr : nullptr,         \
                      write ? out->loc : nullptr, write ? out->val : nullptr,                 \
                      write ? out->row_scale : nullptr, write ? out->nnz_cap : 0,             \
@@ -582,10 +609,10 @@ int32_t launch_pack_csr(const int64_t* row_ptr, const int32_t* col_idx, const fl
   }
   if (write) {
     if (nz_in > 0) {
+      const unsigned g_rec = grid_of(nz_in, kT);
 #define RK_REC(DT_)                                                                          \
-  hipLaunchKernelGGL((k_csr_records<DT_>), dim3(grid_of(nz_in, kT)), dim3(kT), 0, s,         \
-                     colstart, colk, cid, rptr, vout, rowoff, M, nz_in, mr, val,             \
-                     out->row_scale, out->rec, out->nrec_cap)
+  hipLaunchKernelGGL((k_csr_records<DT_>), dim3(g_rec), dim3(kT), 0, s, colstart, colk, cid, \
+                     rptr, vout, rowoff, M, nz_in, mr, out->row_scale, out->rec, out->nrec_cap)
       if (val_dtype == ROSKO_F32) RK_REC(ROSKO_F32);
       else if (val_dtype == ROSKO_BF16) RK_REC(ROSKO_BF16);
       else RK_REC(ROSKO_FP8_E4M3);
