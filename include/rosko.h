@@ -492,12 +492,13 @@ int32_t rosko_sched_analytic(const float *features_host, int32_t *index);
 /* The value-type rule: the network and the analytic rule were fitted on
  * FP32 values times FP32 B.  When the values are BF16 or FP8 and B is BF16,
  * the dense path runs on the BF16 matrix cores (16x the FP32 vector rate),
- * so from density features_host[3] >= 0.025 it sets *index to the dense
+ * so from density features_host[3] >= 0.015 it sets *index to the dense
  * candidate (ROSKO_SCHED_CANDIDATES - 1); otherwise *index is left as it is.
  * The threshold is the crossover measured on a 4096 x 4096 matrix times a
- * 4096 x 2048 BF16 B (dense 131 us; sparse 324 us at density 0.10 and 116 us
- * at 0.02); both paths' times scale with N, and the dense one with M*K
- * against the sparse one's nnz, so the crossover is a density.  val_dtype
+ * 4096 x 2048 BF16 B (dense 98-106 us at every density; sparse 123 us at
+ * density 0.02, 98-100 us at 0.015, 72-74 us at 0.01); both paths' times
+ * scale with N, and the dense one with M*K against the sparse one's nnz, so
+ * the crossover is a density.  val_dtype
  * ROSKO_F32 / BF16 / FP8_E4M3, b_dtype ROSKO_F32 / BF16.  Host only. */
 int32_t rosko_sched_precision(const float *features_host, int32_t val_dtype, int32_t b_dtype,
                               int32_t *index);

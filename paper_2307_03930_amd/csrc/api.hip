@@ -782,7 +782,7 @@ int32_t rosko_sched_analytic(const float* f, int32_t* index) {
 
 // The value-type rule (see rosko.h): products the BF16 matrix cores can
 // take (BF16 or FP8 values times a BF16 B) go dense from this density up.
-constexpr float kBf16DenseDensity = 0.025f;
+constexpr float kBf16DenseDensity = 0.015f;
 constexpr int32_t kDenseCandidate = ROSKO_SCHED_CANDIDATES - 1;
 
 int32_t rosko_sched_precision(const float* f, int32_t val_dtype, int32_t b_dtype,

@@ -20,6 +20,7 @@
 // exactly BF16 (BF16 or FP8 values, BF16 B), else FP32 MFMA
 // (v_mfma_f32_32x32x2f32); FP32 accumulation either way.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -126,19 +127,24 @@ k_densify_lds(const uint32_t* __restrict__ rec, const int64_t* __restrict__ kblk
   const int64_t jb = k_lo / ROSKO_KSTEP, je = min(ceil_div_dev(k_hi, ROSKO_KSTEP), nkb);
   const int64_t a = min(max(kblk[p * (nkb + 1) + min(jb, nkb)], (int64_t)0), rec_bound);
   const int64_t e = min(max(kblk[p * (nkb + 1) + je], a), rec_bound);
+  // a record as four 16-byte loads: header and row words, then the values
+  const uint4* rec4 = reinterpret_cast<const uint4*>(rec);
   for (int64_t r = a + threadIdx.x; r < e; r += 256) {
-    const uint32_t* R = rec + r * 16;
-    const uint32_t hdr = R[0];
-    const int64_t k = hdr >> 8;
-    const int cnt = (int)(hdr & 0xFFu);
+    const uint4 h = rec4[r * 4];
+    const int64_t k = h.x >> 8;
+    const int cnt = (int)(h.x & 0xFFu);
     if (k < k_lo || k >= k_hi || k >= K || cnt > 12) continue;
+    const uint4 v0 = rec4[r * 4 + 1], v1 = rec4[r * 4 + 2], v2 = rec4[r * 4 + 3];
+    const uint32_t rw[3] = {h.y, h.z, h.w};
+    const uint32_t vb[12] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w,
+                             v2.x, v2.y, v2.z, v2.w};
     const int kk = (int)(k - k_lo);
-    for (int t = 0; t < cnt; ++t) {
-      const int row = (int)((R[1 + t / 4] >> (8 * (t % 4))) & 0xFFu);
-      if (row >= rows) continue;
-      const uint32_t bits = R[4 + t];
-      if constexpr (BF) tile[row * kDenseLdsK + kk] = (uint16_t)(bits >> 16);   // exact BF16
-      else tile[row * kDenseLdsK + kk] = __uint_as_float(bits);
+#pragma unroll
+    for (int t = 0; t < 12; ++t) {
+      const int row = (int)((rw[t / 4] >> (8 * (t % 4))) & 0xFFu);
+      if (t >= cnt || row >= rows) continue;
+      if constexpr (BF) tile[row * kDenseLdsK + kk] = (uint16_t)(vb[t] >> 16);   // exact BF16
+      else tile[row * kDenseLdsK + kk] = __uint_as_float(vb[t]);
     }
   }
   __syncthreads();
@@ -157,31 +163,63 @@ k_densify_lds(const uint32_t* __restrict__ rec, const int64_t* __restrict__ kblk
   }
 }
 
-// Bt[n][k] = B[k][n] for n < N, k < K, zero elsewhere in Np x Kp; 32 x 32
-// tiles through LDS (one extra column against bank conflicts).
-template <int TB, bool BF>
+// Bt[n][k] = B[k][n] for n < N, k < K, zero elsewhere in Np x Kp, through
+// 64 x 64 tiles in LDS (held as FP32, one extra column against bank
+// conflicts).  VEC (B 16-byte aligned, ldb a multiple of the elements per 16
+// bytes): a thread loads 16-byte pieces of B's rows (elements past N or K
+// read as zero), and every thread stores 16-byte pieces of Bt's rows (Bt is
+// 256-byte aligned and Kp a multiple of 64).  Otherwise the loads are per
+// element.
+constexpr int kTrT = 64;
+template <int TB, bool BF, bool VEC>
 __global__ void __launch_bounds__(256)
 k_transpose_b(const void* __restrict__ B, int64_t K, int64_t N, int64_t ldb,
               typename Op<BF>::T* __restrict__ Bt, int64_t Kp) {
   using T = typename Op<BF>::T;
-  __shared__ float tile[32][33];
-  const int64_t k0 = (int64_t)blockIdx.y * 32, n0 = (int64_t)blockIdx.x * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-  for (int i = ty; i < 32; i += 8) {
-    const int64_t k = k0 + i, n = n0 + tx;
-    float x = 0.0f;
-    if (k < K && n < N) {
-      if constexpr (TB == ROSKO_F32) x = reinterpret_cast<const float*>(B)[k * ldb + n];
-      else x = __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(B)[k * ldb + n] << 16);
+  using TI = typename std::conditional<TB == ROSKO_F32, float, uint16_t>::type;
+  constexpr int EI = 16 / sizeof(TI), EO = 16 / sizeof(T);   // elements per 16 bytes
+  __shared__ float tile[kTrT][kTrT + 1];
+  const int64_t k0 = (int64_t)blockIdx.y * kTrT, n0 = (int64_t)blockIdx.x * kTrT;
+  const TI* Bi = reinterpret_cast<const TI*>(B);
+  auto widen = [](TI x) -> float {
+    if constexpr (TB == ROSKO_F32) return x;
+    else return __uint_as_float((uint32_t)x << 16);
+  };
+  // loads: kTrT / EI pieces per row, 256 / (kTrT / EI) rows per pass
+  constexpr int PR = kTrT / EI, RP = 256 / PR;
+  const int lr = threadIdx.x / PR, lp = threadIdx.x % PR;
+#pragma unroll
+  for (int i = 0; i < kTrT / RP; ++i) {
+    const int kl = lr + i * RP;
+    const int64_t k = k0 + kl, n = n0 + lp * EI;
+    TI x[EI];
+    if (VEC && k < K && n + EI <= N) {
+      const uint4 u = *reinterpret_cast<const uint4*>(Bi + k * ldb + n);
+      __builtin_memcpy(x, &u, 16);
+    } else {
+#pragma unroll
+      for (int e = 0; e < EI; ++e) x[e] = (k < K && n + e < N) ? Bi[k * ldb + n + e] : (TI)0;
     }
-    tile[i][tx] = x;
+#pragma unroll
+    for (int e = 0; e < EI; ++e) tile[kl][lp * EI + e] = widen(x[e]);
   }
   __syncthreads();
-  for (int i = ty; i < 32; i += 8) {
-    const float x = tile[tx][i];
-    T* dst = Bt + (n0 + i) * Kp + (k0 + tx);
-    if constexpr (BF) *dst = (uint16_t)(__float_as_uint(x) >> 16);   // exact: B is BF16
-    else *dst = x;
+  // stores: kTrT / EO pieces per Bt row, 256 / (kTrT / EO) rows per pass
+  constexpr int PW = kTrT / EO, WP = 256 / PW;
+  const int wr = threadIdx.x / PW, wp = threadIdx.x % PW;
+#pragma unroll
+  for (int i = 0; i < kTrT / WP; ++i) {
+    const int nl = wr + i * WP;
+    T y[EO];
+#pragma unroll
+    for (int e = 0; e < EO; ++e) {
+      const float x = tile[wp * EO + e][nl];
+      if constexpr (BF) y[e] = (uint16_t)(__float_as_uint(x) >> 16);   // exact: B is BF16
+      else y[e] = x;
+    }
+    uint4 u;
+    __builtin_memcpy(&u, y, 16);
+    *reinterpret_cast<uint4*>(Bt + (n0 + nl) * Kp + k0 + wp * EO) = u;
   }
 }
 
@@ -367,13 +405,19 @@ int32_t run_dense(const rosko_packed* A, const void* B, int32_t b_dtype, int64_t
                        A->mr, A->n_panels, A->M, A->K, L.Mp, L.Kp, Ad);
   }
   ROSKO_LAUNCH_CHECK("k_densify");
-  const dim3 tg((unsigned)(L.Np / 32), (unsigned)(L.Kp / 32));
-  if (b_dtype == ROSKO_F32)
-    hipLaunchKernelGGL((k_transpose_b<ROSKO_F32, BF>), tg, dim3(256), 0, s, B, A->K, N, ldb, Bt,
-                       L.Kp);
-  else
-    hipLaunchKernelGGL((k_transpose_b<ROSKO_BF16, BF>), tg, dim3(256), 0, s, B, A->K, N, ldb,
-                       Bt, L.Kp);
+  const dim3 tg((unsigned)(L.Np / kTrT), (unsigned)(L.Kp / kTrT));
+  const int64_t bes = b_dtype == ROSKO_F32 ? 4 : 2;
+  const bool vec = (reinterpret_cast<uintptr_t>(B) % 16 == 0) && ((ldb * bes) % 16 == 0);
+#define RK_TR(TB_, V_)                                                                         \
+  hipLaunchKernelGGL((k_transpose_b<TB_, BF, V_>), tg, dim3(256), 0, s, B, A->K, N, ldb, Bt, L.Kp)
+  if (b_dtype == ROSKO_F32) {
+    if (vec) RK_TR(ROSKO_F32, true);
+    else RK_TR(ROSKO_F32, false);
+  } else {
+    if (vec) RK_TR(ROSKO_BF16, true);
+    else RK_TR(ROSKO_BF16, false);
+  }
+#undef RK_TR
   ROSKO_LAUNCH_CHECK("k_transpose_b");
   const int64_t tm = L.Mp / kTile, tn = L.Np / kTile;
   const float* rs = A->val_dtype == ROSKO_FP8_E4M3 ? A->row_scale : nullptr;

@@ -331,14 +331,14 @@ def test_sched_candidates_and_analytic_rule():
                                      C.byref(i2), C.byref(m2), C.byref(p2)) == 0
         assert i2.value == want and (m2.value, p2.path, p2.cols_per_lane) == seen[want]
         # the value-type rule: BF16/FP8 values times a BF16 B go dense from
-        # density 0.025 up; FP32 operands, or an FP32 B, keep the choice
+        # density 0.015 up; FP32 operands, or an FP32 B, keep the choice
         for vd, bd in ((L.ROSKO_BF16, L.ROSKO_BF16), (L.ROSKO_FP8_E4M3, L.ROSKO_BF16),
                        (L.ROSKO_F32, L.ROSKO_BF16), (L.ROSKO_BF16, L.ROSKO_F32)):
             assert lib.rosko_plan_select(f, None, None, None, vd, bd, C.byref(i2),
                                          C.byref(m2), C.byref(p2)) == 0
             mfma = vd != L.ROSKO_F32 and bd == L.ROSKO_BF16
-            assert i2.value == (6 if mfma and d >= 0.025 else want), (d, lN, vd, bd)
-    for d, want in ((0.0249, 1), (0.025, 6), (0.9, 6)):
+            assert i2.value == (6 if mfma and d >= 0.015 else want), (d, lN, vd, bd)
+    for d, want in ((0.0149, 1), (0.015, 6), (0.9, 6)):
         f[3], f[2], idx.value = d, 10.0, 1
         assert lib.rosko_sched_precision(f, L.ROSKO_BF16, L.ROSKO_BF16, C.byref(idx)) == 0
         assert idx.value == want
