@@ -214,7 +214,7 @@ int32_t rosko_pack_result(const void *ws, size_t ws_bytes, rosko_packed *packed,
  * (Sec. 4.1); a setting for the whole process, ROSKO_PACK_AUTO at load.
  * Every mode gives the same packed arrays, bit for bit; they differ in
  * launches and time.
- *   ROSKO_PACK_AUTO:     one launch for grids of up to 1280 tiles of 64
+ *   ROSKO_PACK_AUTO:     one launch for grids of up to 2048 tiles of 64
  *                        (panel, column) pairs and panels of up to 32 rows,
  *                        when the stream is not capturing a graph: each tile
  *                        counts its own columns, publishes its totals in the

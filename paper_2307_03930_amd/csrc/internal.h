@@ -76,7 +76,7 @@ constexpr int64_t kLocalPrefixTiles = 4096;
 // publish: one launch, no count pass (see the single-pass notes in
 // pack.hip).  kFusedSpin: re-reads of a missing aggregate before the tile
 // counts that tile again itself.
-constexpr int64_t kFusedMaxTiles = 1280;
+constexpr int64_t kFusedMaxTiles = 2048;
 constexpr int32_t kFusedSpin = 32;
 PackWs pack_ws_layout(int64_t R, int64_t S, int32_t mr, bool transpose);
 // rosko_pack_set_mode

@@ -59,6 +59,7 @@ CASES = [
     (256, 2304, 32, 0.05, "row_clustered"),  # 288 tiles of 32 rows
     (512, 2304, 8, 0.2, "row_clustered"),   # four pairs per lane
     (1024, 2304, 16, 0.05, "column_banded"),  # two pairs per lane, 1152 tiles
+    (1024, 4096, 8, 0.05, "iid"),           # four pairs per lane, 2048 tiles (the limit)
     (77, 131, 3, 0.3, "iid"),               # ragged panels of 3 rows
     (100, 70, 24, 0.5, "iid"),              # 24-row panels, ragged last panel
     (37, 1000, 12, 0.1, "iid"),             # 12-row panels
@@ -70,7 +71,7 @@ CASES = [
 def test_pack_modes_bit_exact(case):
     M, K, mr, d, kind = case
     tiles, cpl = _tiles(M, K, mr)
-    assert tiles <= 1280            # every case takes the single pass in auto
+    assert tiles <= 2048            # every case takes the single pass in auto
     A = synth.sparse_matrix(M, K, d, 1300 + M + K + mr, kind)
     Ad = dev(A)
     try:
