@@ -343,7 +343,7 @@ def run_gcn(args):
     adjacency A of a synthetic power-law graph (by default 60000 nodes, mean
     degree 120, 99.8% sparse), feature lengths 32..512, FP32.  A is packed
     from CSR on the GPU (mr 16) in the natural row order and in the
-    inspector's balanced order; each SpMM is timed, and 150 sampled rows of
+    inspector's balanced and degree orders; each SpMM is timed, and 150 sampled rows of
     each result are checked against an FP64 host reference.  The CPU
     baseline is the oracle's CSR product on a sample of rows."""
     import numpy as np
@@ -363,15 +363,15 @@ def run_gcn(args):
         rows = np.unique(synth.rng(77).integers(0, gr.n, 600))[::4]
         g = synth.rng(78)
         packs = {}
-        for order in ("natural", "balanced"):
+        for order in ("natural", "balanced", "degree"):
             t1 = time.perf_counter()
-            perm = None if order == "natural" else ops.row_order(rp, mr, "balanced")
+            perm = None if order == "natural" else ops.row_order(rp, mr, order)
             P = ops.pack_csr(rp, ci, va, gr.n, mr, "f32", perm)
             pack_ms = _time_us(lambda: ops.pack_csr_into(rp, ci, va, P, P._ws), 3,
                                warm=1) / 1e3
             order_ms = None
             if perm is not None:
-                order_ms = _time_us(lambda: ops.row_order(rp, mr, "balanced"), 3, warm=1) / 1e3
+                order_ms = _time_us(lambda: ops.row_order(rp, mr, order), 3, warm=1) / 1e3
             pan = np.add.reduceat(np.diff(gr.row_ptr)[perm.cpu().numpy()] if perm is not None
                                   else np.diff(gr.row_ptr), np.arange(0, gr.n, mr))
             packs[order] = (P, pack_ms, order_ms, float(pan.max() / pan.mean()))
