@@ -634,6 +634,11 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   constexpr int kLdsVals = kPackTile * CPL * RT;     // values per tile, at most
   constexpr int kLdsRecs = kPackTile * CPL * RPC;    // records per tile, at most
   static_assert(CPL * RPC * kPackTile <= kLdsRecs && CPL * RMAX * kPackTile <= kLdsVals, "");
+  // a tile's values, kept columns and records fit the 13, 9 and 9 bits of its
+  // single-pass aggregate word (agg_word)
+  static_assert(PFX != kPfxFused ||
+                    (kLdsVals <= 0x1FFF && kPackTile * CPL <= 0x1FF && kLdsRecs <= 0x1FF),
+                "single-pass aggregate fields");
   // the tile's values / rows as they go out, plus one discard slot per lane
   // for the entries that are not kept
   __shared__ uint32_t s_code[kLdsVals + 64];
