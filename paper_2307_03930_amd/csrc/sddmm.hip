@@ -133,10 +133,37 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t r0 = p * mr;
   const int rows = (int)min((int64_t)mr, M - r0);
-  for (int idx = threadIdx.x; idx < ROWS * RW; idx += 64 * kSdW) {
-    const int r = idx / RW, n = idx - r * RW;
-    sdc[idx] = (r < rows && n0 + n < N)
-                   ? dC[perm_row(row_perm, r0 + r, M) * lddc + n0 + n] : 0.0f;
+  // the panel's dC rows (this chunk) into LDS: a thread's loads are all
+  // issued before any of its LDS stores, so the fill costs one round trip
+  constexpr int PER = ROWS * RW / (64 * kSdW);    // floats per thread
+  static_assert(PER * 64 * kSdW == ROWS * RW, "the workgroup covers the LDS rows exactly");
+  {
+    float v[PER];
+    if (rows > 0 && n0 < N) {
+      // every load unconditional, from an address inside dC (out-of-range
+      // elements re-read the chunk's first element of the panel's first row
+      // and keep zero), so the compiler issues them back to back
+      int64_t prow[PER];
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int r = (threadIdx.x + i * 64 * kSdW) / RW;
+        prow[i] = perm_row(row_perm, r0 + (r < rows ? r : rows - 1), M);
+      }
+      const int64_t base = perm_row(row_perm, r0, M) * lddc + n0;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int idx = threadIdx.x + i * 64 * kSdW;
+        const int r = idx / RW, n = idx - r * RW;
+        const bool ok = r < rows && n0 + n < N;
+        const float x = dC[ok ? prow[i] * lddc + n0 + n : base];
+        v[i] = ok ? x : 0.0f;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) v[i] = 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) sdc[threadIdx.x + i * 64 * kSdW] = v[i];
   }
   __syncthreads();
   // clamped as in k_sddmm
@@ -168,19 +195,34 @@ k_sddmm_lds(const int64_t* __restrict__ panel_col_ptr, const int32_t* __restrict
   for (int64_t cb = a; cb < e; cb += 64) {
     const int64_t c = cb + lane;
     const bool valid = c < e;
-    const int kk = valid ? (int)min(max((int64_t)col_ind[c], (int64_t)0), K - 1) : 0;
-    const int64_t zz = valid ? max(col_ptr[c], (int64_t)0) : 0;
-    const int nn = valid ? (int)max((int64_t)0, min((int64_t)min(col_nnz[c], ROWS),
-                                                    nz_lim - zz))
-                         : 0;
-    uint32_t rw[RWD];                           // in-panel rows of the column, bytes
+    // the three column words, loaded together from an index inside [cb, e)
+    // (lanes past the range re-read column e - 1 and keep nothing of it)
+    const int64_t cc = valid ? c : e - 1;
+    const int32_t ci = col_ind[cc], cn = col_nnz[cc];
+    const int64_t cp = col_ptr[cc];
+    const int kk = valid ? (int)min(max((int64_t)ci, (int64_t)0), K - 1) : 0;
+    const int64_t zz = valid ? max(cp, (int64_t)0) : 0;
+    const int nn = valid ? (int)max((int64_t)0, min((int64_t)min(cn, ROWS), nz_lim - zz)) : 0;
+    // in-panel rows of the column as bytes: the loads (only the column's own
+    // entries) all issued before they are combined
+    uint32_t lb[ROWS];
+    if (nz_lim > 0) {
+      // unconditional byte loads inside [0, nz_lim): the column's own
+      // entries, lanes without one re-read entry 0 and keep nothing
+#pragma unroll
+      for (int t = 0; t < ROWS; ++t) {
+        const uint32_t b = loc[nn > 0 ? zz + (t < nn ? t : nn - 1) : 0];
+        lb[t] = t < nn ? b : 0u;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < ROWS; ++t) lb[t] = 0u;
+    }
+    uint32_t rw[RWD];
 #pragma unroll
     for (int q = 0; q < RWD; ++q) rw[q] = 0u;
 #pragma unroll
-    for (int t = 0; t < ROWS; ++t) {
-      const uint32_t r = t < nn ? loc[zz + t] : 0u;
-      rw[t / 4] |= r << (8 * (t % 4));
-    }
+    for (int t = 0; t < ROWS; ++t) rw[t / 4] |= lb[t] << (8 * (t % 4));
     const int cnt = (int)min<int64_t>(64, e - cb);
     float4 bq[kSdDepth][VQ];
 #pragma unroll
