@@ -227,8 +227,14 @@ int32_t rosko_pack_result(const void *ws, size_t ws_bytes, rosko_packed *packed,
  *   ROSKO_PACK_RECOUNT:  as AUTO, but no tile publishes, so each one counts
  *                        every tile before it itself (time quadratic in the
  *                        tiles: for testing that path).
- * A pack in flight keeps the mode it was enqueued with.  EINVAL for any
- * other value. */
+ * A pack in flight keeps the mode it was enqueued with.  The single pass
+ * takes a published word only if it carries the launch's tag (unique within
+ * the process) and a marker bit, so words that earlier packs left in the
+ * workspace are never taken; a workspace that last held unrelated data could
+ * hold a matching word by chance (about 2^-33 per word for arbitrary bits),
+ * which would misplace that pack's offsets (writes still stay within the
+ * capacities).  rosko_pack_query on the same workspace first overwrites those
+ * words, as does ROSKO_PACK_TWO_PASS.  EINVAL for any other value. */
 #define ROSKO_PACK_AUTO 0
 #define ROSKO_PACK_TWO_PASS 1
 #define ROSKO_PACK_RECOUNT 2
