@@ -27,16 +27,33 @@ namespace {
 // pairs; the scans below carry all three.
 struct Tri { int64_t a, b, c; };
 
-// Rows i0 .. i0+31 of a column into registers: 32 independent loads in
-// flight at once (addresses clamped to the panel's last row; the caller
-// masks entries at or past `rows`).
+// Rows i0 .. i0+N-1 of a column into registers, all N loads issued before
+// any of them is used.  `last` is the column's entry in a row at or below
+// the panel's last row that is still in the matrix (the hot callers pass its
+// entry in the matrix's last row, R - 1): an address past it is clamped to
+// it (lda > 0), and the caller masks the entries at or past the panel's
+// rows.  Every address is an add of the lane-independent offset j * lda and
+// a minimum.  A lane-dependent 64-bit row index times lda would take two
+// multiplies per row, the second of which reads the high half of a register
+// pair that the compiler may have handed to a load still in flight, and the
+// wait it then inserts splits the loads into several round trips; the
+// scheduling barrier keeps the first use of a row from being placed before
+// the last load.
+template <int N>
+__device__ __forceinline__ void load_col(const float* __restrict__ col, int64_t lda, int i0,
+                                         const float* last, float* x) {
+  const float* b = col + (int64_t)i0 * lda;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const float* a = b + (int64_t)j * lda;
+    x[j] = *(a < last ? a : last);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+// The same, clamped to the panel's last row (rows >= 1).
 __device__ __forceinline__ void load_rows32(const float* __restrict__ col, int64_t lda, int i0,
                                             int rows, float* x) {
-#pragma unroll
-  for (int j = 0; j < 32; ++j) {
-    const int i = (i0 + j < rows) ? i0 + j : rows - 1;
-    x[j] = col[(int64_t)i * lda];
-  }
+  load_col<32>(col, lda, i0, col + (int64_t)(rows - 1) * lda, x);
 }
 
 // Records a kept column of `cnt` values occupies.
@@ -130,17 +147,17 @@ k_pack_count(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int
       const int64_t r0 = p * mr;
       const int rows = (int)((R - r0) < mr ? (R - r0) : mr);
       const float* col = A + r0 * lda + k;
+      const float* last = A + (R - 1) * lda + k;
       if constexpr (RR == 32) {
         for (int i0 = 0; i0 < rows; i0 += 32) {
           float x[32];
-          load_rows32(col, lda, i0, rows, x);
+          load_col<32>(col, lda, i0, last, x);
 #pragma unroll
           for (int i = 0; i < 32; ++i) c += (i0 + i < rows) & kept(x[i]);
         }
       } else {
         float x[RMAX];
-#pragma unroll
-        for (int i = 0; i < RMAX; ++i) x[i] = col[(int64_t)(i < rows ? i : rows - 1) * lda];
+        load_col<RMAX>(col, lda, 0, last, x);
 #pragma unroll
         for (int i = 0; i < RMAX; ++i) c += (i < rows) & kept(x[i]);
       }
@@ -487,8 +504,7 @@ __device__ __forceinline__ Tri32 tile_aggregate(const float* __restrict__ A, int
       const int rows = (int)((R - r0) < mr ? (R - r0) : mr);
       const float* col = A + r0 * lda + k;
       float x[RMAX];
-#pragma unroll
-      for (int i = 0; i < RMAX; ++i) x[i] = col[(int64_t)(i < rows ? i : rows - 1) * lda];
+      load_col<RMAX>(col, lda, 0, A + (R - 1) * lda + k, x);
 #pragma unroll
       for (int i = 0; i < RMAX; ++i) c += (i < rows) & kept(x[i]);
     }
@@ -513,6 +529,10 @@ __device__ __forceinline__ void lb_issue(const uint64_t* flags, int64_t t, int64
     w[u] = __hip_atomic_load(flags + (i < t ? i : t - 1), __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
   }
+  // all the loads before any use of their words: the compiler keeps atomic
+  // loads in program order and would otherwise test the first word (and so
+  // wait for it) before issuing the second
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // lookback_sum: the sum of the aggregates of tiles [0, t), read in rounds
@@ -665,6 +685,7 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   const int64_t total = P * S;
   const int64_t nkb = (S + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
   const int64_t fb = (int64_t)blockIdx.x * (64 * CPL) + lane;
+  const float* A_last = A + (R - 1) * lda;   // the matrix's last row (R >= 1)
   bool valid[CPL];
   int c[CPL], rows[CPL];
   int64_t p[CPL], k[CPL], r0[CPL];
@@ -681,15 +702,11 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   }
   // rows, with the counts: one round trip (clamped reads of valid memory)
   if constexpr (RT >= 32) {
-    if (rows[0] > 0) load_rows32(A + r0[0] * lda + k[0], lda, 0, rows[0], xs);
+    if (rows[0] > 0) load_col<32>(A + r0[0] * lda + k[0], lda, 0, A_last + k[0], xs);
   } else {
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-      const float* col = A + r0[j] * lda + k[j];
-      const int last = rows[j] > 0 ? rows[j] - 1 : 0;
-#pragma unroll
-      for (int i = 0; i < RMAX; ++i) xs[j * RMAX + i] = col[(int64_t)(i < last ? i : last) * lda];
-    }
+    for (int j = 0; j < CPL; ++j)
+      load_col<RMAX>(A + r0[j] * lda + k[j], lda, 0, A_last + k[j], xs + j * RMAX);
   }
   if constexpr (PFX == kPfxFused) {
     // the tile's own counts, from the rows just loaded (all of the panel:
@@ -765,7 +782,7 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
     int rank = 0;
     for (int i0 = 0; i0 < (RT >= 32 ? min(mr, RT) : RMAX); i0 += 32) {
       if (RT >= 32 && i0 > 0 && c[0] > 0 && i0 < rows[0])
-        load_rows32(A + r0[0] * lda + k[0], lda, i0, rows[0], xs);
+        load_col<32>(A + r0[0] * lda + k[0], lda, i0, A_last + k[0], xs);
 #pragma unroll
       for (int jj = 0; jj < RMAX; ++jj) {
         const int i = i0 + jj;
