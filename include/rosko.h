@@ -199,6 +199,33 @@ int32_t rosko_pack_transpose(const float *A, int64_t M, int64_t K, int64_t lda, 
                              int32_t val_dtype, void *ws, size_t ws_bytes, rosko_packed *out,
                              void *stream);
 
+/* One matrix of rosko_pack_batch: the arguments of rosko_pack (stream aside). */
+typedef struct rosko_pack_job {
+  const float *A;
+  int64_t M, K, lda;
+  int32_t mr, val_dtype;
+  void *ws;
+  size_t ws_bytes;
+  rosko_packed *out;
+} rosko_pack_job;
+
+/* Packs jobs[0..n) as n calls of rosko_pack would (Alg. 1, Sec. 4.1), with
+ * the same packed arrays bit for bit, in fewer launches: where the packing
+ * mode gives a matrix the single pass, the matrices whose single pass has
+ * the same value type and tile form (panel-height bound, pairs per lane,
+ * record staging) share one grid, up to 8 to a launch, so their dispatch and
+ * memory latencies overlap instead of adding up.  Each tile adds up only the
+ * published totals of its own matrix, in that matrix's workspace.  The other
+ * matrices are packed one by one, as rosko_pack would.  Every job is checked
+ * as rosko_pack checks its arguments before anything is enqueued: the first
+ * failing job's status is returned and nothing is enqueued.  The jobs'
+ * workspaces must be pairwise disjoint and their `out` structs distinct
+ * (EINVAL otherwise); their packed buffers must not overlap either (not
+ * checked).  n: 0 .. ROSKO_PACK_BATCH_MAX (EINVAL otherwise).
+ * Asynchronous; rosko_pack_result on a job's workspace gives its totals. */
+#define ROSKO_PACK_BATCH_MAX 64
+int32_t rosko_pack_batch(int32_t n, const rosko_pack_job *jobs, void *stream);
+
 /* As rosko_pack_query, for packing A^T (K x M) from A (M x K, lda); ws sized
  * with transpose != 0.  SYNCHRONISES `stream`. */
 int32_t rosko_pack_transpose_query(const float *A, int64_t M, int64_t K, int64_t lda,
@@ -526,7 +553,7 @@ int32_t rosko_plan_select(const float *features_host, const float *params, const
 /* ---- errors ----------------------------------------------------------- */
 const char *rosko_status_str(int32_t status);
 const char *rosko_last_error(void);   /* per host thread; "" if none */
-int32_t rosko_abi_version(void);      /* 10 */
+int32_t rosko_abi_version(void);      /* 11 */
 
 #ifdef __cplusplus
 }

@@ -30,6 +30,7 @@ ROSKO_ORDER_BALANCED = 1
 ROSKO_PACK_AUTO = 0
 ROSKO_PACK_TWO_PASS = 1
 ROSKO_PACK_RECOUNT = 2
+ROSKO_PACK_BATCH_MAX = 64
 ROSKO_NFEAT = 16
 ROSKO_SCHED_CANDIDATES = 7
 ROSKO_KSTEP = 128
@@ -47,6 +48,12 @@ class RoskoPacked(C.Structure):
         ("loc", C.c_void_p), ("val", C.c_void_p), ("row_scale", C.c_void_p),
         ("kblk_ptr", C.c_void_p), ("rec", C.c_void_p), ("row_perm", C.c_void_p),
     ]
+
+
+class RoskoPackJob(C.Structure):
+    _fields_ = [("A", C.c_void_p), ("M", C.c_int64), ("K", C.c_int64), ("lda", C.c_int64),
+                ("mr", C.c_int32), ("val_dtype", C.c_int32), ("ws", C.c_void_p),
+                ("ws_bytes", C.c_size_t), ("out", C.POINTER(RoskoPacked))]
 
 
 class RoskoPlan(C.Structure):
@@ -85,6 +92,7 @@ SIGNATURES = {
                                     C.POINTER(RoskoPacked), _P]),
     "rosko_pack_result": (_I32, [_P, _SZ, C.POINTER(RoskoPacked), _P]),
     "rosko_pack_set_mode": (_I32, [_I32]),
+    "rosko_pack_batch": (_I32, [_I32, C.POINTER(RoskoPackJob), _P]),
     "rosko_pack_csr_workspace_size": (_I32, [_I64, _I64, _I64, _I32, C.POINTER(_SZ)]),
     "rosko_pack_csr_query": (_I32, [_P, _P, _P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P,
                                     C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),

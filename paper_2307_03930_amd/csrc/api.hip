@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "pack_batch.h"
 
 namespace rosko {
 
@@ -99,7 +100,7 @@ static int32_t check_packed_for_read(const rosko_packed* A) {
 
 extern "C" {
 
-int32_t rosko_abi_version(void) { return 10; }
+int32_t rosko_abi_version(void) { return 11; }
 
 const char* rosko_last_error(void) { return g_err; }
 
@@ -213,6 +214,53 @@ int32_t rosko_pack(const float* A, int64_t M, int64_t K, int64_t lda, int32_t mr
   RK_REQUIRE(ws != nullptr && ws_bytes >= L.bytes, ROSKO_ESMALLBUF,
              "workspace %zu bytes < %zu", ws_bytes, L.bytes);
   return pack_common(A, M, K, lda, mr, val_dtype, ws, L, out, static_cast<hipStream_t>(stream));
+}
+
+int32_t rosko_pack_batch(int32_t n, const rosko_pack_job* jobs, void* stream) {
+  clear_error();
+  RK_REQUIRE(n >= 0 && n <= ROSKO_PACK_BATCH_MAX, ROSKO_EINVAL, "batch of %d jobs (0..%d)", n,
+             ROSKO_PACK_BATCH_MAX);
+  RK_REQUIRE(n == 0 || jobs != nullptr, ROSKO_EINVAL, "jobs is null");
+  PackTask t[ROSKO_PACK_BATCH_MAX];
+  for (int32_t i = 0; i < n; ++i) {
+    const rosko_pack_job& J = jobs[i];
+    int32_t st = check_dense(J.A, J.M, J.K, J.lda, "A");
+    if (st) return st;
+    if ((st = check_mr(J.mr))) return st;
+    if ((st = check_packed_for_write(J.out, J.M, J.K, J.mr, J.val_dtype))) return st;
+    RK_REQUIRE(J.out->row_perm == nullptr, ROSKO_EUNSUPPORTED,
+               "job %d: the dense packer keeps the row order: row_perm must be NULL", i);
+    const PackWs L = pack_ws_layout(J.M, J.K, J.mr, false);
+    RK_REQUIRE(L.P <= INT32_MAX, ROSKO_EUNSUPPORTED, "job %d: too many panels", i);
+    RK_REQUIRE(J.ws != nullptr && J.ws_bytes >= L.bytes, ROSKO_ESMALLBUF,
+               "job %d: workspace %zu bytes < %zu", i, J.ws_bytes, L.bytes);
+    t[i] = PackTask{J.A, J.M, J.K, J.lda, J.mr, J.val_dtype, J.ws, L, J.out};
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(t[i].ws), a1 = a0 + t[i].L.bytes;
+    for (int32_t j = i + 1; j < n; ++j) {
+      const uintptr_t b0 = reinterpret_cast<uintptr_t>(t[j].ws), b1 = b0 + t[j].L.bytes;
+      RK_REQUIRE(t[i].out != t[j].out, ROSKO_EINVAL, "jobs %d and %d share their packed output",
+                 i, j);
+      RK_REQUIRE(a1 <= b0 || b1 <= a0, ROSKO_EINVAL, "jobs %d and %d share workspace bytes", i,
+                 j);
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  for (int32_t i = 0; i < n; ++i) {
+    rosko_packed* out = t[i].out;
+    out->n_panels = (int32_t)t[i].L.P;
+    out->val_dtype = t[i].val_dtype;
+    out->nnz = -1;
+    out->ncols = -1;
+    out->nrec = -1;
+    if (t[i].val_dtype == ROSKO_FP8_E4M3) {
+      int32_t st = launch_row_scale(t[i].A, t[i].R, t[i].S, t[i].lda, out->row_scale, s);
+      if (st) return st;
+    }
+  }
+  return launch_pack_batch(t, n, s);
 }
 
 int32_t rosko_pack_transpose(const float* A, int64_t M, int64_t K, int64_t lda, int32_t mr,

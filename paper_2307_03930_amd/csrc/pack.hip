@@ -18,6 +18,7 @@
 
 #include "encode.h"
 #include "internal.h"
+#include "pack_batch.h"
 
 namespace rosko {
 
@@ -629,18 +630,19 @@ __device__ __forceinline__ uint32_t code_bits(uint32_t code) {
   return dec_fp8((uint8_t)code);
 }
 
+// One tile (64*CPL (panel, column) pairs, one wavefront) of the write pass:
+// tile `tile` of a grid of `ntiles` tiles over the matrix.
 template <int DT, int PFX, int CPL, int RT, bool TABLE>
-__global__ void __launch_bounds__(kPackThreads)
-k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr,
-                 int64_t P, const int32_t* __restrict__ counts,
-                 const int64_t* __restrict__ tile_offs, const int64_t* __restrict__ tile_sums,
-                 uint64_t* flags, uint32_t tag, int32_t spin, int32_t publish,
-                 int64_t* __restrict__ totals, int64_t nnz_cap, int64_t ncols_cap,
-                 int64_t* __restrict__ panel_nz_ptr, int64_t* __restrict__ panel_col_ptr,
-                 int32_t* __restrict__ col_ind, int32_t* __restrict__ col_nnz,
-                 int64_t* __restrict__ col_ptr, uint8_t* __restrict__ loc,
-                 void* __restrict__ val, const float* __restrict__ row_scale,
-                 int64_t* __restrict__ kblk_ptr, int64_t nrec_cap, uint32_t* __restrict__ rec) {
+__device__ __forceinline__ void pack_write_tile(
+    const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr, int64_t P,
+    const int32_t* __restrict__ counts, const int64_t* __restrict__ tile_offs,
+    const int64_t* __restrict__ tile_sums, uint64_t* flags, uint32_t tag, int32_t spin,
+    int32_t publish, int64_t* __restrict__ totals, int64_t nnz_cap, int64_t ncols_cap,
+    int64_t* __restrict__ panel_nz_ptr, int64_t* __restrict__ panel_col_ptr,
+    int32_t* __restrict__ col_ind, int32_t* __restrict__ col_nnz, int64_t* __restrict__ col_ptr,
+    uint8_t* __restrict__ loc, void* __restrict__ val, const float* __restrict__ row_scale,
+    int64_t* __restrict__ kblk_ptr, int64_t nrec_cap, uint32_t* __restrict__ rec, int64_t tile,
+    int64_t ntiles) {
   static_assert(kPackTile == 64 && kPackThreads == 64, "one wavefront per tile");
   static_assert((CPL == 4 && RT == 8) || (CPL == 2 && RT == 16) ||
                     (CPL == 1 && (RT == 8 || RT == 16 || RT == 32 || RT == kLdsMaxRows)),
@@ -684,7 +686,7 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   const int lane = threadIdx.x;
   const int64_t total = P * S;
   const int64_t nkb = (S + ROSKO_KSTEP - 1) / ROSKO_KSTEP;
-  const int64_t fb = (int64_t)blockIdx.x * (64 * CPL) + lane;
+  const int64_t fb = tile * (64 * CPL) + lane;
   const float* A_last = A + (R - 1) * lda;   // the matrix's last row (R >= 1)
   bool valid[CPL];
   int c[CPL], rows[CPL];
@@ -737,10 +739,10 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
   // then most of them are there)
   if constexpr (PFX == kPfxFused) {
     if (publish && lane == 0)
-      __hip_atomic_store(flags + blockIdx.x, agg_word(tag, run), __ATOMIC_RELAXED,
+      __hip_atomic_store(flags + tile, agg_word(tag, run), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
   } else if constexpr (PFX == kPfxLocal) {
-    const int64_t nb = blockIdx.x;
+    const int64_t nb = tile;
     for (int64_t i = lane; i < nb; i += 64 * 8) {
       int64_t va[8], vb[8], vc[8];
 #pragma unroll
@@ -762,8 +764,7 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
       carry.c += __shfl_xor(carry.c, d, 64);
     }
   } else {
-    carry = Tri{tile_offs[3 * blockIdx.x], tile_offs[3 * blockIdx.x + 1],
-                tile_offs[3 * blockIdx.x + 2]};
+    carry = Tri{tile_offs[3 * tile], tile_offs[3 * tile + 1], tile_offs[3 * tile + 2]};
   }
   const int nv = min(run.a, kLdsVals), nrec = min(run.c, kLdsRecs);
   // zero the tile's records (unused row bytes and value slots stay zero)
@@ -832,7 +833,7 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
     __syncthreads();
   }
   if constexpr (PFX == kPfxFused)
-    carry = lookback_sum<CPL, RT>(flags, blockIdx.x, tag, spin, A, R, S, lda, mr, total);
+    carry = lookback_sum<CPL, RT>(flags, tile, tag, spin, A, R, S, lda, mr, total);
   // coalesced copies of the tile's values, rows and records
   const int64_t z0 = carry.a, q0 = carry.c;
 #pragma unroll 4
@@ -890,7 +891,7 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
     }
   }
   if constexpr (PFX != kPfxScan) {
-    if (blockIdx.x == gridDim.x - 1 && lane == 0) {
+    if (tile == ntiles - 1 && lane == 0) {
       carry.a += run.a;
       carry.b += run.b;
       carry.c += run.c;
@@ -898,6 +899,72 @@ k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda,
                     panel_col_ptr, col_ptr, kblk_ptr);
     }
   }
+}
+
+// The write pass of one matrix after its count pass.
+template <int DT, int PFX, int CPL, int RT, bool TABLE>
+__global__ void __launch_bounds__(kPackThreads)
+k_pack_write_lds(const float* __restrict__ A, int64_t R, int64_t S, int64_t lda, int32_t mr,
+                 int64_t P, const int32_t* __restrict__ counts,
+                 const int64_t* __restrict__ tile_offs, const int64_t* __restrict__ tile_sums,
+                 int64_t* __restrict__ totals, int64_t nnz_cap, int64_t ncols_cap,
+                 int64_t* __restrict__ panel_nz_ptr, int64_t* __restrict__ panel_col_ptr,
+                 int32_t* __restrict__ col_ind, int32_t* __restrict__ col_nnz,
+                 int64_t* __restrict__ col_ptr, uint8_t* __restrict__ loc,
+                 void* __restrict__ val, const float* __restrict__ row_scale,
+                 int64_t* __restrict__ kblk_ptr, int64_t nrec_cap, uint32_t* __restrict__ rec) {
+  static_assert(PFX != kPfxFused, "the single pass runs as k_pack_single");
+  pack_write_tile<DT, PFX, CPL, RT, TABLE>(
+      A, R, S, lda, mr, P, counts, tile_offs, tile_sums, nullptr, 0u, 0, 0, totals, nnz_cap,
+      ncols_cap, panel_nz_ptr, panel_col_ptr, col_ind, col_nnz, col_ptr, loc, val, row_scale,
+      kblk_ptr, nrec_cap, rec, (int64_t)blockIdx.x, (int64_t)gridDim.x);
+}
+
+// The single pass over up to kPackJobs matrices in one grid: job j owns
+// tiles [tile0, tile0 + ntiles) of the grid (the jobs in order, job 0 from
+// tile 0), and every tile adds up only the words of its own matrix's tiles,
+// in that matrix's workspace.  One job is the single pass of one matrix.
+struct PackJob {
+  const float* A;
+  int64_t R, S, lda, P;
+  int32_t mr;
+  int32_t reserved;
+  uint64_t* flags;
+  int64_t* totals;
+  int64_t nnz_cap, ncols_cap, nrec_cap;
+  int64_t* panel_nz_ptr;
+  int64_t* panel_col_ptr;
+  int32_t* col_ind;
+  int32_t* col_nnz;
+  int64_t* col_ptr;
+  uint8_t* loc;
+  void* val;
+  const float* row_scale;
+  int64_t* kblk_ptr;
+  uint32_t* rec;
+  int64_t tile0, ntiles;
+};
+constexpr int kPackJobs = 8;
+struct PackJobs {
+  PackJob job[kPackJobs];
+  int32_t n;
+};
+
+template <int DT, int CPL, int RT, bool TABLE>
+__global__ void __launch_bounds__(kPackThreads)
+k_pack_single(const PackJobs jobs, uint32_t tag, int32_t spin, int32_t publish) {
+  const int64_t b = blockIdx.x;
+  int j = 0;
+#pragma unroll
+  for (int i = 1; i < kPackJobs; ++i)
+    if (i < jobs.n && b >= jobs.job[i].tile0) j = i;
+  const PackJob& J = jobs.job[j];
+  const int64_t tile = b - J.tile0;
+  if (tile < 0 || tile >= J.ntiles) return;      // a grid larger than its jobs' tiles
+  pack_write_tile<DT, kPfxFused, CPL, RT, TABLE>(
+      J.A, J.R, J.S, J.lda, J.mr, J.P, nullptr, nullptr, nullptr, J.flags, tag, spin, publish,
+      J.totals, J.nnz_cap, J.ncols_cap, J.panel_nz_ptr, J.panel_col_ptr, J.col_ind, J.col_nnz,
+      J.col_ptr, J.loc, J.val, J.row_scale, J.kblk_ptr, J.nrec_cap, J.rec, tile, J.ntiles);
 }
 
 // -------------------------------------------------------------- row scale
@@ -1056,6 +1123,99 @@ int32_t set_pack_mode(int32_t mode) {
   return ROSKO_OK;
 }
 
+// The LDS instantiation whose panel-height bound RT covers mr: 8 with 4
+// pairs per lane, 16 with 2, and with one pair per lane the rows per lane
+// load (8 or 16 for small panels) or 32 / 64 (see pack_cols_per_lane); mr
+// above kLdsMaxRows only with one pair per lane.
+static int pack_rt(const PackWs& L, int32_t mr) {
+  return L.cpl == 4   ? 8
+         : L.cpl == 2 ? 16
+         : L.rr < 32  ? L.rr
+                      : (mr <= 32 ? 32 : kLdsMaxRows);
+}
+
+// Single pass (no count launch) for grids of up to kFusedMaxTiles tiles of
+// panels of up to 32 rows, unless the stream is being captured into a
+// graph: a replay would reuse the launch's tag, so captured packs take the
+// two-pass form.
+static int32_t single_pass_ok(const PackWs& L, int32_t mr, int rt, int32_t mode, hipStream_t s,
+                              bool* ok) {
+  *ok = false;
+  if (mode != ROSKO_PACK_TWO_PASS && L.NT > 0 && L.NT <= kFusedMaxTiles && mr <= kLdsMaxRows &&
+      rt <= 32) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    ROSKO_HIP_CHECK(hipStreamIsCapturing(s, &cap));
+    *ok = cap == hipStreamCaptureStatusNone;
+  }
+  return ROSKO_OK;
+}
+
+// One matrix's entry in a single-pass grid, from tile tile0 on; its
+// aggregate words live in its workspace where the tile sums would.
+static PackJob make_job(const float* A, int64_t R, int64_t S, int64_t lda, int32_t mr, void* ws,
+                        const PackWs& L, const rosko_packed* out, int64_t tile0) {
+  char* w = static_cast<char*>(ws);
+  PackJob j{};
+  j.A = A;
+  j.R = R;
+  j.S = S;
+  j.lda = lda;
+  j.P = L.P;
+  j.mr = mr;
+  j.flags = reinterpret_cast<uint64_t*>(w + L.tile_sums);
+  j.totals = reinterpret_cast<int64_t*>(w + L.totals);
+  j.nnz_cap = out->nnz_cap;
+  j.ncols_cap = out->ncols_cap;
+  j.nrec_cap = out->nrec_cap;
+  j.panel_nz_ptr = out->panel_nz_ptr;
+  j.panel_col_ptr = out->panel_col_ptr;
+  j.col_ind = out->col_ind;
+  j.col_nnz = out->col_nnz;
+  j.col_ptr = out->col_ptr;
+  j.loc = out->loc;
+  j.val = out->val;
+  j.row_scale = out->row_scale;
+  j.kblk_ptr = out->kblk_ptr;
+  j.rec = out->rec;
+  j.tile0 = tile0;
+  j.ntiles = L.NT;
+  return j;
+}
+
+// One single-pass launch over the jobs' tiles (`grid` of them in all), all of
+// one value type and tile form (cpl, rt, record table), with a fresh tag.
+static int32_t launch_single(const PackJobs& jobs, int64_t grid, int32_t val_dtype, int cpl,
+                             int rt, bool table, int32_t mode, hipStream_t s) {
+  if (grid <= 0) return ROSKO_OK;
+  if (grid > INT32_MAX) {
+    set_error("matrix too large for the packing grid");
+    return ROSKO_EUNSUPPORTED;
+  }
+  const uint32_t tag = next_pack_tag();
+  // the test mode publishes nothing, so every tile recounts every tile
+  // before it; re-reads of a missing word before recounting it
+  const int32_t publish = mode == ROSKO_PACK_RECOUNT ? 0 : 1;
+  const int32_t spin = publish ? kFusedSpin : 1;
+#define ROSKO_SINGLE_T(DT, TB)                                                                 \
+  (cpl == 4    ? (k_pack_single<DT, 4, 8, TB>)                                                \
+   : cpl == 2  ? (k_pack_single<DT, 2, 16, TB>)                                               \
+   : rt == 8   ? (k_pack_single<DT, 1, 8, TB>)                                                \
+   : rt == 16  ? (k_pack_single<DT, 1, 16, TB>)                                               \
+               : (k_pack_single<DT, 1, 32, TB>))
+  void (*k)(const PackJobs, uint32_t, int32_t, int32_t);
+  if (val_dtype == ROSKO_F32)
+    k = table ? ROSKO_SINGLE_T(ROSKO_F32, true) : ROSKO_SINGLE_T(ROSKO_F32, false);
+  else if (val_dtype == ROSKO_BF16)
+    k = table ? ROSKO_SINGLE_T(ROSKO_BF16, true) : ROSKO_SINGLE_T(ROSKO_BF16, false);
+  else
+    k = ROSKO_SINGLE_T(ROSKO_FP8_E4M3, true);   // FP8 packs through the record table
+#undef ROSKO_SINGLE_T
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kPackThreads), 0, s, jobs, tag, spin,
+                     publish);
+  ROSKO_LAUNCH_CHECK("k_pack_single");
+  return ROSKO_OK;
+}
+
 int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t mr,
                     int32_t val_dtype, void* ws, const PackWs& L, const rosko_packed* out,
                     hipStream_t s) {
@@ -1064,34 +1224,17 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
   int64_t* tsum = reinterpret_cast<int64_t*>(w + L.tile_sums);
   int64_t* toff = reinterpret_cast<int64_t*>(w + L.tile_offs);
   int64_t* totals = reinterpret_cast<int64_t*>(w + L.totals);
-  // the aggregate words of the single pass live where the tile sums would
-  uint64_t* flags = reinterpret_cast<uint64_t*>(w + L.tile_sums);
   const bool lds = mr <= kLdsMaxRows;
-  // mr > kLdsMaxRows only with one pair per lane (pack_cols_per_lane)
-  // the LDS instantiation whose panel-height bound RT covers mr: 8 with 4
-  // pairs per lane, 16 with 2, and with one pair per lane the rows per lane
-  // load (8 or 16 for small panels) or 32 / 64 (see pack_cols_per_lane)
-  const int rt = L.cpl == 4   ? 8
-                 : L.cpl == 2 ? 16
-                 : L.rr < 32  ? L.rr
-                              : (mr <= 32 ? 32 : kLdsMaxRows);
+  const int rt = pack_rt(L, mr);
   if (lds && mr > rt) {
     set_error("internal: panel height %d above the packing tile's %d rows", mr, rt);
     return ROSKO_EINTERNAL;
   }
-  // Single pass (no count launch) for grids of up to kFusedMaxTiles tiles of
-  // panels of up to 32 rows, unless the stream is being captured into a
-  // graph: a replay would reuse the launch's tag, so captured packs take the
-  // two-pass form.
   const int32_t mode = g_pack_mode.load(std::memory_order_relaxed);
   bool fused = false;
-  if (mode != ROSKO_PACK_TWO_PASS && L.NT > 0 && L.NT <= kFusedMaxTiles && lds && rt <= 32) {
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    ROSKO_HIP_CHECK(hipStreamIsCapturing(s, &cap));
-    fused = cap == hipStreamCaptureStatusNone;
-  }
+  int32_t st = single_pass_ok(L, mr, rt, mode, s, &fused);
+  if (st) return st;
   const bool local = !fused && L.NT > 0 && L.NT <= kLocalPrefixTiles;
-  int32_t st;
   if (fused) {
     // nothing before the write pass
   } else if (local) {
@@ -1121,11 +1264,12 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
     ROSKO_LAUNCH_CHECK("k_pack_write");
     return ROSKO_OK;
   }
-  const uint32_t tag = fused ? next_pack_tag() : 0u;
-  // the test mode publishes nothing, so every tile recounts every tile
-  // before it; re-reads of a missing word before recounting it
-  const int32_t publish = mode == ROSKO_PACK_RECOUNT ? 0 : 1;
-  const int32_t spin = publish ? kFusedSpin : 1;
+  if (fused) {
+    PackJobs jobs{};
+    jobs.n = 1;
+    jobs.job[0] = make_job(A, R, S, lda, mr, ws, L, out, 0);
+    return launch_single(jobs, L.NT, val_dtype, L.cpl, rt, L.NT > kImageMaxTiles, mode, s);
+  }
   // record images staged whole for grids of up to kImageMaxTiles tiles (a
   // few per CU: each tile's own chain is the time), as a table above (the
   // smaller LDS footprint lets more workgroups share a CU)
@@ -1144,20 +1288,11 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
 #define ROSKO_WRITE(KERNEL)                                                                    \
   hipLaunchKernelGGL(KERNEL,                                                                  \
                      dim3((unsigned)L.NT), dim3(kPackThreads), 0, s,                         \
-                     A, R, S, lda, mr, L.P, counts, toff, tsum, flags, tag, spin, publish,    \
-                     totals, out->nnz_cap,                                                     \
+                     A, R, S, lda, mr, L.P, counts, toff, tsum, totals, out->nnz_cap,         \
                      out->ncols_cap, out->panel_nz_ptr, out->panel_col_ptr, out->col_ind,     \
                      out->col_nnz, out->col_ptr, out->loc, out->val, out->row_scale,          \
                      out->kblk_ptr, out->nrec_cap, out->rec)
-  if (fused) {
-    // RT <= 32 here; the single-pass instantiations have no 64-row form
-#define ROSKO_KWRITE_F(DT)                                                                     \
-  (table ? ROSKO_KWRITE_T(DT, kPfxFused, true) : ROSKO_KWRITE_T(DT, kPfxFused, false))
-    if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_KWRITE_F(ROSKO_F32));
-    else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_KWRITE_F(ROSKO_BF16));
-    else ROSKO_WRITE(ROSKO_KWRITE_T(ROSKO_FP8_E4M3, kPfxFused, true));
-#undef ROSKO_KWRITE_F
-  } else if (local) {
+  if (local) {
     if (val_dtype == ROSKO_F32) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_F32, kPfxLocal));
     else if (val_dtype == ROSKO_BF16) ROSKO_WRITE(ROSKO_KWRITE(ROSKO_BF16, kPfxLocal));
     else ROSKO_WRITE(ROSKO_KWRITE_FP8(kPfxLocal));
@@ -1172,6 +1307,62 @@ int32_t launch_pack(const float* A, int64_t R, int64_t S, int64_t lda, int32_t m
 #undef ROSKO_KWRITE_T
 #undef ROSKO_KWRITE_T64
   ROSKO_LAUNCH_CHECK("k_pack_write");
+  return ROSKO_OK;
+}
+
+int32_t launch_pack_batch(const PackTask* tasks, int32_t n, hipStream_t s) {
+  if (n <= 0) return ROSKO_OK;
+  if (n > kPackBatchMax) {
+    set_error("internal: batch of %d packs above %d", n, kPackBatchMax);
+    return ROSKO_EINTERNAL;
+  }
+  const int32_t mode = g_pack_mode.load(std::memory_order_relaxed);
+  // the single-pass form of each task (-1: the task packs on its own)
+  int32_t key[kPackBatchMax];
+  for (int32_t i = 0; i < n; ++i) {
+    const PackTask& t = tasks[i];
+    const int rt = pack_rt(t.L, t.mr);
+    bool fused = false;
+    int32_t st = single_pass_ok(t.L, t.mr, rt, mode, s, &fused);
+    if (st) return st;
+    if (fused && t.mr > rt) {
+      set_error("internal: panel height %d above the packing tile's %d rows", t.mr, rt);
+      return ROSKO_EINTERNAL;
+    }
+    const bool table = t.L.NT > kImageMaxTiles || t.val_dtype == ROSKO_FP8_E4M3;
+    key[i] = fused ? ((t.val_dtype * 8 + t.L.cpl) * 64 + rt) * 2 + (table ? 1 : 0) : -1;
+    if (!fused) {
+      if ((st = launch_pack(t.A, t.R, t.S, t.lda, t.mr, t.val_dtype, t.ws, t.L, t.out, s)))
+        return st;
+    }
+  }
+  // the single passes: each form's tasks in order, kPackJobs to a launch
+  bool done[kPackBatchMax] = {};
+  for (int32_t i = 0; i < n; ++i) {
+    if (key[i] < 0 || done[i]) continue;
+    PackJobs jobs{};
+    int64_t grid = 0;
+    for (int32_t j = i; j < n; ++j) {
+      if (done[j] || key[j] != key[i]) continue;
+      const PackTask& t = tasks[j];
+      jobs.job[jobs.n++] = make_job(t.A, t.R, t.S, t.lda, t.mr, t.ws, t.L, t.out, grid);
+      grid += t.L.NT;
+      done[j] = true;
+      if (jobs.n == kPackJobs) {
+        int32_t st = launch_single(jobs, grid, tasks[i].val_dtype, tasks[i].L.cpl,
+                                   pack_rt(tasks[i].L, tasks[i].mr),
+                                   (key[i] & 1) != 0, mode, s);
+        if (st) return st;
+        jobs = PackJobs{};
+        grid = 0;
+      }
+    }
+    if (jobs.n > 0) {
+      int32_t st = launch_single(jobs, grid, tasks[i].val_dtype, tasks[i].L.cpl,
+                                 pack_rt(tasks[i].L, tasks[i].mr), (key[i] & 1) != 0, mode, s);
+      if (st) return st;
+    }
+  }
   return ROSKO_OK;
 }
 

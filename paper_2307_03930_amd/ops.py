@@ -280,6 +280,29 @@ def pack_into(A: torch.Tensor, P: PackedMatrix, ws: torch.Tensor) -> PackedMatri
     return P
 
 
+def pack_batch_into(items) -> None:
+    """Re-packs several matrices at once (rosko_pack_batch): items is a
+    sequence of (A, P, ws), each as for pack_into, with distinct workspaces
+    and buffers.  The packed arrays are those pack_into gives, bit for bit;
+    the single passes of matrices of one kernel form share launches.
+    Asynchronous: no host sync."""
+    items = list(items)
+    if len(items) > L.ROSKO_PACK_BATCH_MAX:
+        raise ValueError(f"at most {L.ROSKO_PACK_BATCH_MAX} matrices per batch")
+    jobs = (L.RoskoPackJob * max(len(items), 1))()
+    structs = []
+    for i, (A, P, ws) in enumerate(items):
+        _check_dense(A, "A")
+        M, K = A.shape
+        if (M, K) != (P.M, P.K):
+            raise ValueError("shape differs from the packed buffers")
+        st = P.struct()
+        structs.append(st)
+        jobs[i] = L.RoskoPackJob(_ptr(A), M, K, max(A.stride(0), 1), P.mr, P.val_dtype, _ptr(ws),
+                                 ws.numel(), C.pointer(st))
+    L.check(L.lib().rosko_pack_batch(len(items), jobs, _stream_ptr()))
+
+
 def pack_transpose_into(A: torch.Tensor, Pt: PackedMatrix, ws: torch.Tensor) -> PackedMatrix:
     """Re-packs A^T (A: M x K) into Pt's existing buffers (Pt is K x M, FP32
     values; its capacities must hold A's structure).  Asynchronous."""

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.rosko_abi_version() == 10
+    assert lib.rosko_abi_version() == 11
     assert lib.rosko_status_str(L.ROSKO_EINVAL) == b"ROSKO_EINVAL"
     assert lib.rosko_status_str(123) == b"ROSKO_UNKNOWN"
 
@@ -157,6 +157,41 @@ def test_pack_argument_checks():
     s4 = _packed(8, 6, 4)
     assert lib.rosko_pack_transpose(fake, 8, 6, 6, 4, L.ROSKO_F32, fake, 1 << 20, C.byref(s4),
                                     None) == L.ROSKO_EINVAL
+
+
+def test_pack_batch_argument_checks():
+    """rosko_pack_batch checks every job before it enqueues anything: a bad
+    job, a shared workspace or a shared output is refused on the host."""
+    lib = L.lib()
+    need = C.c_size_t()
+    assert lib.rosko_pack_workspace_size(8, 8, 4, 0, C.byref(need)) == L.ROSKO_OK
+    outs = [_packed(8, 8, 4) for _ in range(3)]
+
+    def job(i, ws, ws_bytes=None, out=None, K=8):
+        return L.RoskoPackJob(0x1000, 8, K, 8, 4, L.ROSKO_F32, ws,
+                              need.value if ws_bytes is None else ws_bytes,
+                              C.pointer(out if out is not None else outs[i]))
+
+    def run(js):
+        arr = (L.RoskoPackJob * max(len(js), 1))(*js)
+        return lib.rosko_pack_batch(len(js), arr, None)
+
+    # batch size and a null job array
+    assert lib.rosko_pack_batch(-1, None, None) == L.ROSKO_EINVAL
+    assert lib.rosko_pack_batch(L.ROSKO_PACK_BATCH_MAX + 1, None, None) == L.ROSKO_EINVAL
+    assert lib.rosko_pack_batch(1, None, None) == L.ROSKO_EINVAL
+    # the second job's workspace is too small: its index in the message
+    assert run([job(0, 0x100000), job(1, 0x200000, ws_bytes=need.value - 1)]) \
+        == L.ROSKO_ESMALLBUF
+    assert b"job 1" in lib.rosko_last_error()
+    # a job whose shape differs from its output struct
+    assert run([job(0, 0x100000), job(1, 0x200000, K=9)]) == L.ROSKO_EINVAL
+    # overlapping workspaces (the second starts inside the first)
+    assert run([job(0, 0x100000), job(1, 0x100000 + need.value - 256)]) == L.ROSKO_EINVAL
+    assert b"workspace" in lib.rosko_last_error()
+    # one output struct for two jobs
+    assert run([job(0, 0x100000), job(1, 0x200000, out=outs[0])]) == L.ROSKO_EINVAL
+    assert b"packed output" in lib.rosko_last_error()
 
 
 def test_spmm_argument_checks():
