@@ -199,17 +199,21 @@ int32_t rosko_pack_transpose(const float *A, int64_t M, int64_t K, int64_t lda, 
                              int32_t val_dtype, void *ws, size_t ws_bytes, rosko_packed *out,
                              void *stream);
 
-/* One matrix of rosko_pack_batch: the arguments of rosko_pack (stream aside). */
+/* One matrix of rosko_pack_batch: the arguments of rosko_pack (stream aside),
+ * or with transpose != 0 those of rosko_pack_transpose (A is M x K and A^T
+ * is packed: out->M = K, out->K = M, ws sized with transpose != 0). */
 typedef struct rosko_pack_job {
   const float *A;
   int64_t M, K, lda;
   int32_t mr, val_dtype;
+  int32_t transpose, reserved;
   void *ws;
   size_t ws_bytes;
   rosko_packed *out;
 } rosko_pack_job;
 
-/* Packs jobs[0..n) as n calls of rosko_pack would (Alg. 1, Sec. 4.1), with
+/* Packs jobs[0..n) as n calls of rosko_pack (or rosko_pack_transpose) would
+ * (Alg. 1, Sec. 4.1), with
  * the same packed arrays bit for bit, in fewer launches: where the packing
  * mode gives a matrix the single pass, the matrices whose single pass has
  * the same value type and tile form (panel-height bound, pairs per lane,
@@ -217,7 +221,8 @@ typedef struct rosko_pack_job {
  * memory latencies overlap instead of adding up.  Each tile adds up only the
  * published totals of its own matrix, in that matrix's workspace.  The other
  * matrices are packed one by one, as rosko_pack would.  Every job is checked
- * as rosko_pack checks its arguments before anything is enqueued: the first
+ * as rosko_pack (rosko_pack_transpose) checks its arguments before anything
+ * is enqueued (the transposes of the transpose jobs come first): the first
  * failing job's status is returned and nothing is enqueued.  The jobs'
  * workspaces must be pairwise disjoint and their `out` structs distinct
  * (EINVAL otherwise); their packed buffers must not overlap either (not

@@ -52,7 +52,8 @@ class RoskoPacked(C.Structure):
 
 class RoskoPackJob(C.Structure):
     _fields_ = [("A", C.c_void_p), ("M", C.c_int64), ("K", C.c_int64), ("lda", C.c_int64),
-                ("mr", C.c_int32), ("val_dtype", C.c_int32), ("ws", C.c_void_p),
+                ("mr", C.c_int32), ("val_dtype", C.c_int32), ("transpose", C.c_int32),
+                ("reserved", C.c_int32), ("ws", C.c_void_p),
                 ("ws_bytes", C.c_size_t), ("out", C.POINTER(RoskoPacked))]
 
 

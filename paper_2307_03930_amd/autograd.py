@@ -51,6 +51,18 @@ class PackedWeight:
         ops.pack_result(self.Pt, self.ws_t, transpose=True)
 
 
+def repack_weights(pairs) -> None:
+    """Re-packs several weights, each W and W^T into its PackedWeight's
+    buffers, in one batched call (rosko_pack_batch: the single passes of one
+    kernel form share a launch); asynchronous.  pairs: (W, PackedWeight)."""
+    items = []
+    for W, pw in pairs:
+        Wd = W.detach()
+        items.append((Wd, pw.P, pw.ws))
+        items.append((Wd, pw.Pt, pw.ws_t, True))
+    ops.pack_batch_into(items)
+
+
 class RoskoSparseMatmul(torch.autograd.Function):
     @staticmethod
     def forward(ctx, W: torch.Tensor, B: torch.Tensor, pw: PackedWeight, repack: bool):

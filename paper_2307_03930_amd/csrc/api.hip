@@ -224,17 +224,24 @@ int32_t rosko_pack_batch(int32_t n, const rosko_pack_job* jobs, void* stream) {
   PackTask t[ROSKO_PACK_BATCH_MAX];
   for (int32_t i = 0; i < n; ++i) {
     const rosko_pack_job& J = jobs[i];
+    const bool tr = J.transpose != 0;
+    // the packed matrix: A, or A^T (K x M) for a transpose job
+    const int64_t R = tr ? J.K : J.M, S = tr ? J.M : J.K;
     int32_t st = check_dense(J.A, J.M, J.K, J.lda, "A");
     if (st) return st;
     if ((st = check_mr(J.mr))) return st;
-    if ((st = check_packed_for_write(J.out, J.M, J.K, J.mr, J.val_dtype))) return st;
+    if ((st = check_packed_for_write(J.out, R, S, J.mr, J.val_dtype))) return st;
     RK_REQUIRE(J.out->row_perm == nullptr, ROSKO_EUNSUPPORTED,
                "job %d: the dense packer keeps the row order: row_perm must be NULL", i);
-    const PackWs L = pack_ws_layout(J.M, J.K, J.mr, false);
+    const PackWs L = pack_ws_layout(R, S, J.mr, tr);
     RK_REQUIRE(L.P <= INT32_MAX, ROSKO_EUNSUPPORTED, "job %d: too many panels", i);
     RK_REQUIRE(J.ws != nullptr && J.ws_bytes >= L.bytes, ROSKO_ESMALLBUF,
                "job %d: workspace %zu bytes < %zu", i, J.ws_bytes, L.bytes);
-    t[i] = PackTask{J.A, J.M, J.K, J.lda, J.mr, J.val_dtype, J.ws, L, J.out};
+    // a transpose job packs the dense transpose it writes into its workspace
+    const float* src =
+        tr ? reinterpret_cast<const float*>(static_cast<const char*>(J.ws) + L.transposed) : J.A;
+    t[i] = PackTask{src, R, S, tr ? (J.M > 0 ? J.M : 1) : J.lda, J.mr, J.val_dtype, J.ws, L,
+                    J.out};
   }
   for (int32_t i = 0; i < n; ++i) {
     const uintptr_t a0 = reinterpret_cast<uintptr_t>(t[i].ws), a1 = a0 + t[i].L.bytes;
@@ -248,6 +255,13 @@ int32_t rosko_pack_batch(int32_t n, const rosko_pack_job* jobs, void* stream) {
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();
+  for (int32_t i = 0; i < n; ++i) {
+    if (jobs[i].transpose) {
+      float* At = reinterpret_cast<float*>(static_cast<char*>(jobs[i].ws) + t[i].L.transposed);
+      int32_t st = launch_transpose(jobs[i].A, jobs[i].M, jobs[i].K, jobs[i].lda, At, s);
+      if (st) return st;
+    }
+  }
   for (int32_t i = 0; i < n; ++i) {
     rosko_packed* out = t[i].out;
     out->n_panels = (int32_t)t[i].L.P;

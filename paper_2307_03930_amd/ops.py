@@ -282,24 +282,29 @@ def pack_into(A: torch.Tensor, P: PackedMatrix, ws: torch.Tensor) -> PackedMatri
 
 def pack_batch_into(items) -> None:
     """Re-packs several matrices at once (rosko_pack_batch): items is a
-    sequence of (A, P, ws), each as for pack_into, with distinct workspaces
-    and buffers.  The packed arrays are those pack_into gives, bit for bit;
-    the single passes of matrices of one kernel form share launches.
+    sequence of (A, P, ws) as for pack_into, or (A, Pt, ws, True) as for
+    pack_transpose_into (FP32 values), with distinct workspaces and buffers.
+    The packed arrays are those the one-matrix calls give, bit for bit; the
+    single passes of matrices of one kernel form share launches.
     Asynchronous: no host sync."""
     items = list(items)
     if len(items) > L.ROSKO_PACK_BATCH_MAX:
         raise ValueError(f"at most {L.ROSKO_PACK_BATCH_MAX} matrices per batch")
     jobs = (L.RoskoPackJob * max(len(items), 1))()
     structs = []
-    for i, (A, P, ws) in enumerate(items):
+    for i, item in enumerate(items):
+        A, P, ws = item[:3]
+        tr = bool(item[3]) if len(item) > 3 else False
         _check_dense(A, "A")
         M, K = A.shape
-        if (M, K) != (P.M, P.K):
+        if ((K, M) if tr else (M, K)) != (P.M, P.K):
             raise ValueError("shape differs from the packed buffers")
+        if tr and P.val_dtype != L.ROSKO_F32:
+            raise ValueError("transposed packs hold FP32 values")
         st = P.struct()
         structs.append(st)
-        jobs[i] = L.RoskoPackJob(_ptr(A), M, K, max(A.stride(0), 1), P.mr, P.val_dtype, _ptr(ws),
-                                 ws.numel(), C.pointer(st))
+        jobs[i] = L.RoskoPackJob(_ptr(A), M, K, max(A.stride(0), 1), P.mr, P.val_dtype,
+                                 1 if tr else 0, 0, _ptr(ws), ws.numel(), C.pointer(st))
     L.check(L.lib().rosko_pack_batch(len(items), jobs, _stream_ptr()))
 
 

@@ -10,8 +10,9 @@ fraction of the original weights every `prune_every` steps until the target
 sparsity is reached (the training schedule of Sec. 5.4, read as a fraction
 of the original weights per round).
 
-Every step packs both weights afresh (Alg. 1, on the GPU, into buffers sized
-at the first pack) and runs every product of the step through the library:
+Every step packs both weights and their transposes afresh (Alg. 1, on the
+GPU, into buffers sized at the first pack; the four packs in one batched
+call) and runs every product of the step through the library:
   forward   C1 = W1 X,  H = relu(C1),  C2 = W2 H           (Rosko SpMM, Alg. 2)
   backward  dW2 = (dC2 H^T) on W2's mask                   (SDDMM, scattered)
             dH  = W2^T dC2                                 (SpMM on the packed W2^T)
@@ -23,7 +24,7 @@ from __future__ import annotations
 
 import torch
 
-from .autograd import PackedWeight, rosko_matmul
+from .autograd import PackedWeight, repack_weights, rosko_matmul
 
 
 def magnitude_prune(W: torch.Tensor, sparsity: float) -> None:
@@ -48,9 +49,11 @@ class PrunedChain:
         self.pw2 = PackedWeight(self.W2.detach(), mr)
 
     def forward(self, X: torch.Tensor):
-        C1 = rosko_matmul(self.W1, X, self.pw1)
+        # both weights and their transposes re-packed in one batched call
+        repack_weights([(self.W1, self.pw1), (self.W2, self.pw2)])
+        C1 = rosko_matmul(self.W1, X, self.pw1, repack=False)
         H = torch.relu(C1)
-        C2 = rosko_matmul(self.W2, H, self.pw2)
+        C2 = rosko_matmul(self.W2, H, self.pw2, repack=False)
         return C1, H, C2
 
     def step(self, X: torch.Tensor, T: torch.Tensor, lr: float) -> torch.Tensor:

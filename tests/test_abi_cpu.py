@@ -168,7 +168,7 @@ def test_pack_batch_argument_checks():
     outs = [_packed(8, 8, 4) for _ in range(3)]
 
     def job(i, ws, ws_bytes=None, out=None, K=8):
-        return L.RoskoPackJob(0x1000, 8, K, 8, 4, L.ROSKO_F32, ws,
+        return L.RoskoPackJob(0x1000, 8, K, 8, 4, L.ROSKO_F32, 0, 0, ws,
                               need.value if ws_bytes is None else ws_bytes,
                               C.pointer(out if out is not None else outs[i]))
 
@@ -192,6 +192,15 @@ def test_pack_batch_argument_checks():
     # one output struct for two jobs
     assert run([job(0, 0x100000), job(1, 0x200000, out=outs[0])]) == L.ROSKO_EINVAL
     assert b"packed output" in lib.rosko_last_error()
+    # a transpose job wants the K x M output and a workspace with the
+    # transposed copy: an 8 x 6 A against an 8 x 6 output is refused, and
+    # the workspace of a plain 8 x 8 pack is too small for the 8 x 8 transpose
+    tj = job(0, 0x100000, out=_packed(8, 6, 4), K=6)
+    tj.transpose = 1
+    assert run([tj]) == L.ROSKO_EINVAL
+    tj = job(0, 0x100000)
+    tj.transpose = 1
+    assert run([tj]) == L.ROSKO_ESMALLBUF
 
 
 def test_spmm_argument_checks():

@@ -159,3 +159,28 @@ def test_batch_captured_in_graph_replays():
         torch.cuda.synchronize()
         for (M, K, mr, d, kind, dtype, seed), A, P, ws in zip(specs, news[rep], Ps, wss):
             assert_pack_equal(_result(P, ws), O.pack(A, mr, DT[dtype]))
+
+
+def test_batch_with_transposed_packs():
+    """A training step's packs in one call: two weights (256 x 2304 and
+    256 x 256 at 90%, mr 8) and their transposes; each against the oracle's
+    pack of W and of W^T."""
+    mr = 8
+    Ws = [synth.sparse_matrix(256, 2304, 0.1, 2400, "iid"),
+          synth.sparse_matrix(256, 256, 0.1, 2401, "iid")]
+    items, checks = [], []
+    for W in Ws:
+        M, K = W.shape
+        Wd = dev(W)
+        P = _alloc_for([W], M, K, mr, "f32")
+        Pt = _alloc_for([W.T.copy()], K, M, mr, "f32")
+        ws = _ws(M, K, mr)
+        ws_t = torch.empty(max(ops.workspace_size(M, K, mr, transpose=True), 1),
+                           dtype=torch.uint8, device="cuda")
+        items += [(Wd, P, ws), (Wd, Pt, ws_t, True)]
+        checks += [(P, ws, O.pack(W, mr, O.F32)), (Pt, ws_t, O.pack(W.T.copy(), mr, O.F32))]
+    for rnd in range(2):
+        say(f"pack batch with transposes, round {rnd}")
+        ops.pack_batch_into(items)
+        for P, ws, ref in checks:
+            assert_pack_equal(_result(P, ws), ref)
