@@ -184,3 +184,30 @@ def test_batch_with_transposed_packs():
         ops.pack_batch_into(items)
         for P, ws, ref in checks:
             assert_pack_equal(_result(P, ws), ref)
+
+
+def test_batch_with_empty_matrices():
+    """Empty and all-zero matrices in a batch beside a normal one: each gets
+    the oracle's empty pointer arrays, the normal one its exact pack."""
+    from tests.gpu_helpers import packed_to_np
+    mr = 8
+    items, empties = [], []
+    for shape in [(0, 10), (10, 0), (0, 0), (33, 17)]:
+        A = np.zeros(shape, np.float32)
+        Ad = dev(A) if A.size else torch.zeros(shape, dtype=torch.float32, device="cuda")
+        P = ops.pack(Ad, mr)
+        ws = _ws(shape[0], shape[1], mr)
+        items.append((Ad, P, ws))
+        empties.append((A, P, ws))
+    B = synth.sparse_matrix(256, 2304, 0.2, 2500, "iid")
+    PB = _alloc_for([B], 256, 2304, mr, "f32")
+    wsB = _ws(256, 2304, mr)
+    items.insert(2, (dev(B), PB, wsB))
+    say("pack batch with empty matrices")
+    ops.pack_batch_into(items)
+    assert_pack_equal(_result(PB, wsB), O.pack(B, mr, O.F32))
+    for A, P, ws in empties:
+        R = _result(P, ws)
+        ref = O.pack(A, mr)
+        assert R.nnz == 0 and R.ncols == 0 and R.nrec == 0
+        assert np.array_equal(packed_to_np(R)["panel_nz_ptr"], ref.panel_nz_ptr)
