@@ -203,6 +203,14 @@ def test_pack_batch_argument_checks():
     assert run([tj]) == L.ROSKO_ESMALLBUF
 
 
+def test_pack_batch_binding_limits():
+    """ops.pack_batch_into refuses more matrices than one call takes before it
+    touches any tensor."""
+    from paper_2307_03930_amd import ops
+    with pytest.raises(ValueError):
+        ops.pack_batch_into([None] * (L.ROSKO_PACK_BATCH_MAX + 1))
+
+
 def test_spmm_argument_checks():
     lib = L.lib()
     fake = C.c_void_p(0x1000)
